@@ -1,0 +1,430 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than its own formulas:
+closed forms (the two-center theorem of Sec. 4), invariants (partition of
+unity and bounds of Sec. 3.2), brute-force enumeration of the elastic-net
+KKT system on tiny inputs, textbook reductions (ridge, OLS, all-zero), the
+printed center counts of Table 2, and hand-computed geometry.
+"""
+import itertools
+import math
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_16564_amd import synth
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+
+
+def _read_table(name):
+    rows = []
+    for line in (GOLDEN / name).read_text().splitlines():
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+def _single_model(lo, hi, c, sigma, beta):
+    """One-subdomain dictionary over [lo, hi]^d for the oracle evaluator."""
+    c = np.atleast_2d(np.asarray(c, float))
+    M, d = c.shape
+    D = O.Dictionary(1, M, d)
+    D.m[:] = M
+    D.c[:] = c.ravel()
+    D.sigma[:] = sigma
+    axis = [np.array([lo, hi], float) for _ in range(d)]
+    return D, axis, np.asarray(beta, float)
+
+
+# ---------------------------------------------------------------- Sec. 3.2
+def test_partition_of_unity_rows():
+    """Def. 1: rows of the Shepard-normalized matrix sum to one."""
+    rows = _read_table("shepard_three_gaussians.txt")
+    c = np.array([[float(r[0]), float(r[1])] for r in rows])
+    s = np.array([float(r[2]) for r in rows])
+    x = synth.random_points(2, 500, seed=11)
+    W = O.design(x, c, s)
+    assert np.all(W >= 0) and np.all(W <= 1)
+    assert np.max(np.abs(W.sum(1) - 1.0)) <= 3 * 2.0 ** -53 * 4
+    # larger lattice dictionary
+    c2, s2, _ = O.lattice([0.0, 0.0], [1.0, 1.0], [8, 8], 1.0)
+    W2 = O.design(x, c2, s2)
+    assert np.max(np.abs(W2.sum(1) - 1.0)) <= 64 * 2.0 ** -53 * 4
+
+
+def test_constant_field_reproduced_exactly_by_surrogate():
+    """PU: beta = const * 1 gives K*(x) = const everywhere."""
+    rows = _read_table("shepard_three_gaussians.txt")
+    c = np.array([[float(r[0]), float(r[1])] for r in rows])
+    s = np.array([float(r[2]) for r in rows])
+    D, axis, _ = _single_model(0.0, 1.0, c, s, np.zeros(3))
+    x = synth.random_points(2, 1000, seed=3)
+    for const in (-2.5, 0.0, 1.75, 3.0):
+        v, nout = O.evaluate(axis, D, np.full(3, const), x)
+        assert nout == 0
+        assert np.max(np.abs(v - const)) <= 4 * 2.0 ** -53 * abs(const) + 1e-300
+
+
+def test_bounds_min_max_beta():
+    """Sec. 3.2: the normalized field stays within [min beta, max beta]."""
+    rows = _read_table("shepard_three_gaussians.txt")
+    c = np.array([[float(r[0]), float(r[1])] for r in rows])
+    s = np.array([float(r[2]) for r in rows])
+    rng = np.random.default_rng(5)
+    x = synth.random_points(2, 2000, seed=4)
+    for _ in range(5):
+        beta = rng.normal(size=3) * 3
+        D, axis, _ = _single_model(0.0, 1.0, c, s, beta)
+        v, _ = O.evaluate(axis, D, beta, x)
+        tol = 1e-15 * np.abs(beta).max()
+        assert v.min() >= beta.min() - tol and v.max() <= beta.max() + tol
+        # the unnormalized sum is not bounded (overshoot in overlaps)
+    phi = np.exp(-((x[:, None, :] - c[None]) ** 2).sum(-1) / (2 * s ** 2))
+    assert (phi.sum(1) > 1.0).any() or (phi.sum(1) < 1.0).any()
+
+
+# ---------------------------------------------------------------- Sec. 4 theorem
+THEOREM_CASES = [(0.5, 0.1, 0.0), (0.3, 0.05, 0.0), (1.0, 0.2, 0.0), (0.4, 0.08, 0.15),
+                 (0.25, 0.03, -0.1)]
+
+
+@pytest.mark.parametrize("c,sigma,b", THEOREM_CASES)
+def test_two_center_logistic_pointwise(c, sigma, b):
+    """Theorem (Sec. 4.1): centers c v and gamma c v with gamma = -1 - 2b/c,
+    equal widths, beta = (1, 0) give exactly the logistic of slope
+    2(b+c)/sigma^2 in the normal coordinate y = x + b (d = 1, v = 1)."""
+    gamma = -1.0 - 2.0 * b / c
+    cen = np.array([[c], [gamma * c]])
+    D, axis, beta = _single_model(-5.0, 5.0, cen, np.array([sigma, sigma]), [1.0, 0.0])
+    k = 2.0 * (b + c) / sigma ** 2
+    ys = np.linspace(-30.0 / k, 30.0 / k, 2001)
+    xs = (ys - b)[:, None]
+    v, _ = O.evaluate(axis, D, beta, xs)
+    ref = 1.0 / (1.0 + np.exp(-k * ys))
+    assert np.max(np.abs(v - ref) / np.maximum(ref, 1e-300)) < 1e-12
+    # half-maximum convention at the interface
+    v0, _ = O.evaluate(axis, D, beta, np.array([[-b]]))
+    assert abs(v0[0] - 0.5) < 1e-15
+
+
+@pytest.mark.parametrize("c,sigma,b", THEOREM_CASES)
+def test_two_center_l1_error_closed_form(c, sigma, b):
+    """Eq. (analytic_formula) / (1d_error): int |H - K*| dy = ln2 sigma^2 / (c+b).
+    The integral of the oracle's surrogate is taken by composite 20-point
+    Gauss-Legendre on [-Y, Y] plus the exact logistic tail beyond Y."""
+    gamma = -1.0 - 2.0 * b / c
+    cen = np.array([[c], [gamma * c]])
+    D, axis, beta = _single_model(-50.0, 50.0, cen, np.array([sigma, sigma]), [1.0, 0.0])
+    k = 2.0 * (b + c) / sigma ** 2
+    Y = 32.0 / k
+    gx, gw = np.polynomial.legendre.leggauss(20)
+    edges = np.linspace(0.0, Y, 257)
+    total = 0.0
+    for side in (-1.0, 1.0):
+        a, bb = edges[:-1], edges[1:]
+        ys = (0.5 * (a + bb))[:, None] + 0.5 * (bb - a)[:, None] * gx[None, :]
+        ws = 0.5 * (bb - a)[:, None] * gw[None, :]
+        ys = side * ys
+        v, _ = O.evaluate(axis, D, beta, (ys - b).reshape(-1, 1))
+        H = (ys.reshape(-1) > 0).astype(float)
+        total += float((ws.reshape(-1) * np.abs(H - v)).sum())
+    total += 2.0 * math.log1p(math.exp(-k * Y)) / k
+    exact = math.log(2.0) * sigma ** 2 / (c + b)
+    assert abs(total - exact) / exact < 1e-9
+
+
+def test_step_fit_l1_scales_like_sigma2_over_c():
+    """a3-a6 on a 1-D jump: two fitted centers at +-c; the L1 error of the
+    fitted field follows the theorem's sigma^2/c law (log-log slope 1)."""
+    n = 4000
+    xs = -1.0 + (np.arange(n) + 0.5) * (2.0 / n)
+    y = (xs > 0).astype(float)
+    c = 0.3
+    sig = np.array([0.04, 0.06, 0.09])
+    l1 = []
+    for s in sig:
+        cen = np.array([[-c], [c]])
+        beta, st, stats = O.fit_one(xs[:, None], y, cen, np.array([s, s]), 0.0, 0.0, cd_sweeps=4)
+        assert st == 0
+        D, axis, _ = _single_model(-1.0, 1.0, cen, np.array([s, s]), beta)
+        gx, gw = np.polynomial.legendre.leggauss(16)
+        edges = np.linspace(-1.0, 1.0, 801)
+        a, bb = edges[:-1], edges[1:]
+        q = (0.5 * (a + bb))[:, None] + 0.5 * (bb - a)[:, None] * gx[None, :]
+        w = 0.5 * (bb - a)[:, None] * gw[None, :]
+        v, _ = O.evaluate(axis, D, beta, q.reshape(-1, 1))
+        l1.append(float((w.reshape(-1) * np.abs((q.reshape(-1) > 0) - v)).sum()))
+    slope = np.polyfit(np.log(sig ** 2 / c), np.log(l1), 1)[0]
+    assert abs(slope - 1.0) < 0.05
+    # same order as the theorem's construction ln2 sigma^2 / c
+    ratio = np.array(l1) / (math.log(2) * sig ** 2 / c)
+    assert np.all((ratio > 0.5) & (ratio < 2.0))
+
+
+# ---------------------------------------------------------------- elastic net
+def _brute_force_enet(G, b, l1, l2):
+    """Enumerate all 3^M sign patterns; return the KKT-feasible solutions."""
+    M = len(b)
+    A = G + l2 * np.eye(M)
+    sols = []
+    for th in itertools.product((-1.0, 0.0, 1.0), repeat=M):
+        th = np.array(th)
+        S = np.nonzero(th)[0]
+        beta = np.zeros(M)
+        if len(S):
+            beta[S] = np.linalg.solve(A[np.ix_(S, S)], b[S] - l1 * th[S])
+            if np.any(np.sign(beta[S]) != th[S]):
+                continue
+        g = b - A @ beta
+        Z = np.nonzero(th == 0)[0]
+        if len(Z) and np.max(np.abs(g[Z])) > l1 * (1 + 1e-10):
+            continue
+        sols.append(beta)
+    return sols
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_enet_matches_brute_force(seed):
+    """Strict convexity (lambda2 > 0) gives one KKT point among 3^M patterns."""
+    rng = np.random.default_rng(100 + seed)
+    N, M = 16, int(rng.integers(3, 9))
+    X = rng.normal(size=(N, M))
+    X[:, 1] += 0.9 * X[:, 0]  # correlated columns
+    y = rng.normal(size=N)
+    G, b = X.T @ X, X.T @ y
+    l1 = float(rng.uniform(0.05, 0.6) * np.abs(b).max())
+    l2 = float(rng.uniform(1e-3, 1.0))
+    sols = _brute_force_enet(G, b, l1, l2)
+    assert len(sols) == 1
+    for warm in (None, rng.normal(size=M)):
+        beta, it = O.fss(G, b, l1, l2, beta=warm)
+        assert it > 0
+        assert np.max(np.abs(beta - sols[0])) <= 1e-10 * max(1.0, np.abs(sols[0]).max())
+        assert np.array_equal(beta != 0, sols[0] != 0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_enet_on_shepard_design_matches_brute_force(seed):
+    """Same pin on the method's own normalized design (tiny N, M)."""
+    rng = np.random.default_rng(200 + seed)
+    x = synth.random_points(2, 16, seed=300 + seed)
+    c, s, _ = O.lattice([0.0, 0.0], [1.0, 1.0], [2, 3], 1.0)
+    W = O.design(x, c, s)
+    y = np.where(x[:, 0] + 0.3 * x[:, 1] > 0.6, 3.0, 0.0)
+    G, b = O.normal(W, y)
+    for l1, l2 in ((4.59e-4, 4.64e-6), (0.05, 1e-3), (0.3, 0.1)):
+        sols = _brute_force_enet(G, b, l1, l2)
+        assert len(sols) == 1
+        beta, st, stats = O.fit_one(x, y, c, s, l1, l2, cd_sweeps=3)
+        assert st == 0
+        ref = sols[0]
+        assert np.max(np.abs(beta - ref)) <= 1e-9 * max(1.0, np.abs(ref).max())
+
+
+def test_enet_special_cases():
+    rng = np.random.default_rng(7)
+    N, M = 40, 6
+    X = rng.normal(size=(N, M))
+    y = rng.normal(size=N)
+    G, b = X.T @ X, X.T @ y
+    # lambda1 = 0: ridge
+    beta, _ = O.fss(G, b, 0.0, 0.3)
+    assert np.allclose(beta, np.linalg.solve(G + 0.3 * np.eye(M), b), rtol=1e-12, atol=1e-13)
+    # lambda1 = lambda2 = 0: ordinary least squares
+    beta, _ = O.fss(G, b, 0.0, 0.0)
+    ols = np.linalg.lstsq(X, y, rcond=None)[0]
+    assert np.allclose(beta, ols, rtol=1e-10, atol=1e-12)
+    # lambda1 >= ||b||_inf: exactly zero
+    beta, _ = O.fss(G, b, float(np.abs(b).max()) * 1.0000001, 0.1, beta=rng.normal(size=M))
+    assert np.all(beta == 0.0)
+    # KKT certificate of a generic solution
+    beta, _ = O.fss(G, b, 0.2 * float(np.abs(b).max()), 0.05)
+    assert O.kkt(G, b, 0.2 * float(np.abs(b).max()), 0.05, beta) < 1e-12
+
+
+def test_constant_data_reproduced_exactly_by_fit():
+    """Exact reproduction of constant fields: y = const, lambda1 = lambda2 = 0
+    and N >= M give beta = const * 1 (rows of W sum to one)."""
+    x = synth.random_points(2, 120, seed=21)
+    c, s, _ = O.lattice([0.0, 0.0], [1.0, 1.0], [3, 3], 1.0)
+    for const in (2.0, -1.5):
+        beta, st, _ = O.fit_one(x, np.full(len(x), const), c, s, 0.0, 0.0, cd_sweeps=2)
+        assert st == 0
+        assert np.max(np.abs(beta - const)) < 1e-9
+
+
+def test_fit_certificate_and_warm_start_independence():
+    """circle64 subdomain: KKT certificate holds and the unique minimizer does
+    not depend on the number of CD warm-up sweeps or the starting point."""
+    g = synth.circle64()
+    S = O.partition(g)
+    x, y = S["x"][:1225], S["y"][:1225]
+    c, s, _ = O.lattice([0.0, 0.0], [0.5, 0.5], [16, 16], 1.0)
+    W = O.design(x, c, s)
+    G, b = O.normal(W, y)
+    ref, st, stats = O.fit_one(x, y, c, s, synth.LAMBDA1, synth.LAMBDA2, cd_sweeps=0)
+    assert st == 0 and stats[2] < 1e-12
+    assert O.kkt(G, b, synth.LAMBDA1, synth.LAMBDA2, ref) < 1e-12
+    rng = np.random.default_rng(1)
+    for sw, warm in ((1, None), (16, None), (4, rng.normal(size=256))):
+        beta, st, _ = O.fit_one(x, y, c, s, synth.LAMBDA1, synth.LAMBDA2, cd_sweeps=sw, beta=warm)
+        assert np.max(np.abs(beta - ref)) <= 1e-9 * np.abs(ref).max()
+        assert np.array_equal(beta != 0, ref != 0)
+
+
+# ---------------------------------------------------------------- partition / lattice
+def test_partition_half_open_and_overlap():
+    g = synth.circle64()
+    S = O.partition(g)
+    assert list(np.diff(S["off"])) == [1225] * 4          # 35 x 35 with 10 % overlap
+    g0 = synth.circle64(overlap=0.0)
+    S0 = O.partition(g0)
+    # without overlap every cell appears exactly once (half-open partition)
+    flat = S0["cell"][:, 0] + 64 * S0["cell"][:, 1]
+    assert np.array_equal(np.sort(flat), np.arange(64 * 64))
+    # centroids and values
+    assert np.allclose(S0["x"], (S0["cell"] + 0.5) / 64.0, rtol=0, atol=0)
+    assert np.array_equal(S0["y"], g0.y[flat])
+    # first subdomain of the overlapped grid covers cells 0..34 on both axes
+    c0 = S["cell"][:1225]
+    assert c0.min() == 0 and c0.max() == 34
+
+
+def test_partition_uneven_breaks_3d():
+    g = synth.layered3d(nx=12, ny=10, nz=17, sub=(2, 2, 3))
+    S = O.partition(g)
+    sizes = np.diff(S["off"])
+    assert sizes.sum() == 12 * 10 * 17
+    depths = np.diff(g.breaks[2])
+    assert list(depths) == [5, 6, 6]
+    assert sorted(set(sizes)) == sorted(set(6 * 5 * depths))
+
+
+def test_lattice_positions():
+    c, s, lv = O.lattice([0.0, 0.5], [0.5, 1.0], [16, 16], 1.0)
+    assert c[0, 0] == 1.0 / 64 and c[0, 1] == 0.5 + 1.0 / 64
+    assert c[1, 0] == 3.0 / 64 and c[16, 1] == 0.5 + 3.0 / 64
+    assert np.all(s == 1.0 / 32) and np.all(lv == 0)
+
+
+# ---------------------------------------------------------------- indicator / marking / enrichment
+def test_indicator_matches_logistic_closed_form():
+    """R_T through the theorem's two-center logistic, 2-point Gauss per axis."""
+    c, sig = 0.01, 0.004
+    cen = np.array([[c], [-c]])
+    n = 40
+    h = 0.05 / n
+    xs = -0.025 + (np.arange(n) + 0.5) * h
+    y = (xs > 0).astype(float)
+    R = O.indicator(xs[:, None], y, np.full((n, 1), h), cen, np.array([sig, sig]),
+                    np.array([1.0, 0.0]))
+    k = 2.0 * c / sig ** 2
+    off = h / (2 * math.sqrt(3))
+    ref = np.zeros(n)
+    for sgn in (-1, 1):
+        v = 1.0 / (1.0 + np.exp(-k * (xs + sgn * off)))
+        ref += 0.5 * h * (v - y) ** 2
+    assert np.allclose(R, ref, rtol=1e-12, atol=1e-12 * ref.max())
+
+
+def test_indicator_zero_for_reproduced_constant():
+    x = synth.random_points(2, 30, seed=2)
+    c, s, _ = O.lattice([0.0, 0.0], [1.0, 1.0], [3, 3], 1.0)
+    R = O.indicator(x, np.full(30, 1.25), np.full((30, 2), 0.01), c, s, np.full(9, 1.25))
+    assert np.max(R) < 1e-28
+
+
+def test_mark_order_ties_and_threshold():
+    R = np.array([0.5, 2.0, 0.5, 3.0, 1e-9, 2.0, 0.0])
+    assert list(O.mark(R, 4, 1e-6)) == [3, 1, 5, 0]
+    assert list(O.mark(R, 10, 1e-6)) == [3, 1, 5, 0, 2]
+    assert list(O.mark(R, 3, 10.0)) == []
+
+
+def test_enrichment_geometry_hand_computed():
+    lib = O.lib()
+    x = np.array([0.5, 0.25])
+    h = np.array([0.125, 0.0625])
+    cap = 16
+    c = np.zeros(cap * 2); s = np.zeros(cap); lv = np.zeros(cap, np.int32)
+    el = np.zeros(1, np.int32)
+    m = lib.ora_enrich(2, 0, cap, x, h, 1, np.array([0], np.int32), 0.2, 0.5, el, c, s, lv)
+    assert m == 3 and el[0] == 1
+    assert np.array_equal(c[:6].reshape(3, 2), [[0.5625, 0.25], [0.5, 0.28125], [0.5625, 0.28125]])
+    assert np.array_equal(s[:3], [0.1, 0.1, 0.1]) and np.array_equal(lv[:3], [1, 1, 1])
+    m = lib.ora_enrich(2, m, cap, x, h, 1, np.array([0], np.int32), 0.2, 0.5, el, c, s, lv)
+    assert m == 6 and el[0] == 2
+    assert np.array_equal(c[6:12].reshape(3, 2), [[0.53125, 0.25], [0.5, 0.265625], [0.53125, 0.265625]])
+    assert np.array_equal(s[3:6], [0.05] * 3) and np.array_equal(lv[3:6], [2, 2, 2])
+    # capacity: a group that does not fit is not added
+    m2 = lib.ora_enrich(2, 14, cap, x, h, 1, np.array([0], np.int32), 0.2, 0.5, el, c, s, lv)
+    assert m2 == 14
+
+
+def test_table2_center_counts():
+    """Table 2: 32x32 elements, one center per element, K_top = 204, five
+    rounds -> 1024, 1636, 2248, 2860, 3472, 4084 centers."""
+    ref = [int(r[1]) for r in _read_table("table2_center_counts.txt")]
+    g = synth.circle64(n=32, n_sub=1, overlap=0.0)
+    S = O.partition(g)
+    D = O.init_dictionary(g, [32, 32], 4096 + 64)
+    # lambda1 above ||b||_inf keeps the fits trivial (beta = 0); with eps_tol = 0
+    # every element is eligible, so the count sequence is the marking rule's own
+    D2, beta, lvl, info = O.refine_batch(S, D, 1e3, 1e-3, k_top=204, max_rounds=5,
+                                         m_max=100000, eps_tol=0.0, cd_sweeps=2)
+    counts = [int(v) for v in info["round_stats"][0, :, 0]]
+    assert counts == ref
+    M = int(D2.m[0])
+    cs = D2.c[: M * 2].reshape(M, 2)
+    key = {(a, b, s) for (a, b), s in zip(map(tuple, cs), D2.sigma[:M])}
+    assert len(key) == M                                 # no duplicate basis functions
+    assert lvl.sum() * 3 == M - 1024                     # 3 centers per marking in 2-D
+
+
+def test_evaluation_owner_rule():
+    """Step 4: owner by half-open breakpoints (last interval closed); points
+    outside the closed domain are NaN and counted."""
+    axis = [np.array([0.0, 0.25, 1.0]), np.array([0.0, 0.5, 1.0])]
+    D = O.Dictionary(4, 1, 2)
+    D.m[:] = 1
+    D.c[:] = np.array([[0.1, 0.2], [0.6, 0.2], [0.1, 0.7], [0.6, 0.7]]).ravel()
+    D.sigma[:] = 0.3
+    beta = np.array([10.0, 20.0, 30.0, 40.0])
+    pts = np.array([[0.0, 0.0], [0.2499, 0.1], [0.25, 0.1], [1.0, 0.49], [0.1, 0.5], [1.0, 1.0],
+                    [0.3, 0.99], [-0.01, 0.3], [0.3, 1.01]])
+    v, nout = O.evaluate(axis, D, beta, pts)
+    assert np.allclose(v[:7], [10.0, 10.0, 20.0, 20.0, 30.0, 40.0, 40.0], rtol=4e-16, atol=0)
+    assert np.isnan(v[7]) and np.isnan(v[8]) and nout == 2
+    vl, _ = O.evaluate(axis, D, beta, pts[:2], space=1)
+    assert np.allclose(vl, 1e10)
+
+
+def test_refinement_reduces_error_on_facies_subdomain():
+    """Table 2 trend: on one subdomain of the facies field (16x16 elements,
+    8x8 initial centers, K_top = 20 % of the elements), every refinement round
+    lowers the fit-set L2 error (the sum of the indicators)."""
+    g = synth.facies256(n_sub=16)
+    S = O.partition(g)
+    s0 = 119  # an interior subdomain with all three facies
+    j0, j1 = S["off"][s0], S["off"][s0 + 1]
+    assert len(set(S["y"][j0:j1])) == 3
+    sub = dict(off=np.array([0, j1 - j0], np.int64), x=S["x"][j0:j1], y=S["y"][j0:j1],
+               h=S["h"][j0:j1])
+    boxes = O.grid_owned_boxes(g)
+    c, s, _ = O.lattice(boxes[s0][0], boxes[s0][1], [8, 8], 1.0)
+    D = O.Dictionary(1, 64 + 3 * 3 * 51, 2)
+    D.m[:] = 64
+    D.c[: 64 * 2] = c.ravel()
+    D.sigma[:64] = s
+    tol = 1e-4 * (1 / 256) ** 2
+    D2, beta, lvl, info = O.refine_batch(sub, D, synth.LAMBDA1, synth.LAMBDA2, k_top=51,
+                                         max_rounds=3, m_max=100000, eps_tol=tol)
+    rs = info["round_stats"][0]
+    assert info["rounds"][0] == 4 and np.all(info["status"] == 0)
+    assert [int(v) for v in rs[:, 0]] == [64, 217, 370, 523]
+    err = rs[:, 4]
+    assert np.all(np.diff(err) < 0)
