@@ -1,0 +1,228 @@
+/*
+ * pam.h -- C ABI of the MI355X (gfx950) implementation of the PAM
+ * reconstruction hot path: Parallel and Adaptive Mesh-free approximation of
+ * cellwise-constant coefficient data by Shepard-normalized Gaussian RBF
+ * expansions fitted per subdomain with an elastic net, residual-driven
+ * enrichment, and evaluation of the closed-form field at arbitrary points.
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless the comment says [host].
+ *  - The caller allocates and frees every buffer it passes; the library never
+ *    frees caller memory. The context owns its workspace (grown on demand
+ *    with hipMalloc) and its launch caches.
+ *  - Work is enqueued asynchronously on the context's stream (pam_set_stream).
+ *    Argument errors are detected on the host and returned before anything is
+ *    enqueued; data-dependent conditions (non-convergence, denominator
+ *    underflow) are reported per subdomain in the stats arrays.
+ *  - Return values are pam_status codes; pam_last_error() gives a message for
+ *    the last failing call on the calling thread. No C++ exception crosses the
+ *    ABI. A context is not thread-safe.
+ *  - Floating-point inputs are FP64. Subdomains are numbered row-major over
+ *    the subdomain grid with axis 0 fastest; samples of a subdomain are
+ *    contiguous (CSR offsets) in the same row-major cell order.
+ *  - Dictionaries are capacity-padded: subdomain s owns the slots
+ *    [s*m_cap, (s+1)*m_cap) of sigma/level/beta and [s*m_cap*dim, ...) of c.
+ */
+#ifndef PAM_H
+#define PAM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PAM_OK = 0,
+    PAM_ERR_ARG = -1,       /* invalid argument (shape, range, NULL)          */
+    PAM_ERR_CAPACITY = -2,  /* a capacity (m_cap, workspace cap) is too small */
+    PAM_ERR_HIP = -5,       /* a HIP runtime call failed                      */
+    PAM_ERR_NOMEM = -6,     /* workspace allocation failed                    */
+    PAM_ERR_STATE = -7      /* context not usable (destroyed, wrong device)   */
+} pam_status;
+
+/* Per-subdomain status written to pam_fit_stats.status. */
+enum {
+    PAM_ST_OK = 0,
+    PAM_ST_NOCONV = 1,     /* active-set iteration cap reached / singular block */
+    PAM_ST_UNDERFLOW = 2,  /* a Shepard denominator was not a positive normal   */
+    PAM_ST_EMPTY = 3       /* subdomain without samples or centers              */
+};
+
+/* Precision of the normalized design and of its Gram products. The
+ * active-support solve, its residual refinement and the KKT certificate are
+ * FP64 in every mode. */
+typedef enum {
+    PAM_PREC_F64 = 0,   /* FP64 design, FP64 MFMA Gram                         */
+    PAM_PREC_F32 = 1,   /* FP32 design, FP32 MFMA Gram, FP64 refinement        */
+    PAM_PREC_BF16 = 2   /* BF16 design, BF16 MFMA Gram with FP32 accumulation  */
+} pam_precision;
+
+typedef struct pam_ctx pam_ctx;
+
+/* Create a context bound to HIP device `device`. */
+pam_status pam_create(pam_ctx **out, int device);
+/* Release the context and its workspace (synchronizes its stream first). */
+pam_status pam_destroy(pam_ctx *ctx);
+/* Stream used for all later calls (a hipStream_t; NULL = the null stream). */
+pam_status pam_set_stream(pam_ctx *ctx, void *stream);
+/* Block until all work enqueued by the context has finished. */
+pam_status pam_sync(pam_ctx *ctx);
+/* [host] Message of the last failing call on this thread ("" if none). */
+const char *pam_last_error(void);
+/* [host] Library version string. */
+const char *pam_version(void);
+
+/* ------------------------------------------------------------------------
+ * a1. Structured grid and box partition (Sec. 2 Step 1: half-open
+ * non-overlapping subdomains, every element in exactly one; Step 2: one
+ * sample per element at its centroid). With overlap > 0 the fit set of a
+ * subdomain is widened by overlap * width on interior faces; ownership for
+ * evaluation stays half-open.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t dim;            /* 1, 2 or 3                                      */
+    int32_t n_cells[3];     /* cells per axis (unused axes: 1)                */
+    double lo[3], hi[3];    /* domain box                                     */
+    int32_t n_sub[3];       /* subdomains per axis (unused axes: 1)           */
+    const int32_t *breaks;  /* [host] per-axis cell-index breakpoints,
+                               concatenated: n_sub[a]+1 strictly increasing
+                               values from 0 to n_cells[a] for each axis      */
+    double overlap;         /* >= 0, fraction of the subdomain width          */
+} pam_grid;
+
+/* [host] Sample counts: off_host[0..n_sub_total] (CSR offsets, int64) of the
+ * partition; *n_max = largest subdomain sample count. No device work. */
+pam_status pam_partition_count(const pam_grid *grid, int64_t *off_host, int32_t *n_max);
+
+/* a1 on the device: gather centroids x [N_tot*dim], values y [N_tot],
+ * element extents h [N_tot*dim] and integer cell indices cell [N_tot*dim]
+ * from the cell values cell_y [n_cells product, axis 0 fastest].
+ * off: device copy of the offsets from pam_partition_count. */
+pam_status pam_partition_gather(pam_ctx *ctx, const pam_grid *grid, const double *cell_y,
+                                const int64_t *off, double *x, double *y, double *h,
+                                int32_t *cell);
+
+/* ------------------------------------------------------------------------
+ * Dictionary (Sec. 3.1: centers c_m and widths sigma_m; Alg. 1 input).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_sub, dim, m_cap;
+    int32_t *m;        /* [n_sub] current center counts (in/out)               */
+    double *c;         /* [n_sub*m_cap*dim] centers                           */
+    double *sigma;     /* [n_sub*m_cap] widths, > 0                           */
+    int32_t *level;    /* [n_sub*m_cap] refinement level of each center       */
+} pam_dict;
+
+/* a2. Initial dictionary: g[0]*..*g[dim-1] lattice at the cell centers of
+ * each owned box, common width sigma0 = sigma_factor * max_axis(h_c) where
+ * h_c = box width / g per axis (Exp. 1 "g x g lattice with width sigma").
+ * g is [host]; requires product(g) <= m_cap. */
+pam_status pam_init_lattice(pam_ctx *ctx, const pam_grid *grid, const int32_t *g,
+                            double sigma_factor, pam_dict *dict);
+
+/* ------------------------------------------------------------------------
+ * Samples of every subdomain (Alg. 1 input: element sample points and the
+ * data vector of log10 values).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t dim, n_sub;
+    int32_t n_max;            /* largest per-subdomain sample count            */
+    const int64_t *off;       /* [n_sub+1] CSR offsets (device)                */
+    const int64_t *off_host;  /* [host] same offsets                           */
+    const double *x;          /* [N_tot*dim] sample points                     */
+    const double *y;          /* [N_tot] data values (log10 K)                 */
+    const double *h;          /* [N_tot*dim] element extents (indicator, enrichment) */
+} pam_samples;
+
+/* Elastic-net controls (Eq. elastic; lambda1, lambda2 > 0, optionally per
+ * subdomain as the parallel implementation allows). */
+typedef struct {
+    double lambda1, lambda2;
+    const double *lambda1_sub;   /* [n_sub] or NULL                            */
+    const double *lambda2_sub;   /* [n_sub] or NULL                            */
+    int32_t precision;           /* pam_precision                              */
+    int32_t cd_sweeps;           /* cyclic CD warm-up sweeps (>= 0)            */
+    int32_t max_iter;            /* active-set iteration cap (> 0)             */
+    int32_t warm_start;          /* 1: beta holds the starting point           */
+    int32_t batched;             /* 1: one launch per step for all subdomains;
+                                    0: one launch per subdomain (comparator)   */
+    const uint8_t *support_hint; /* [n_sub*m_cap] 1 = start active, or NULL     */
+} pam_enet_opts;
+
+/* Per-subdomain results (device array of n_sub). */
+typedef struct {
+    int32_t status;     /* PAM_ST_*                                           */
+    int32_t cd_sweeps;  /* CD sweeps done                                     */
+    int32_t iters;      /* active-set iterations                              */
+    int32_t support;    /* number of nonzero coefficients                     */
+    double kkt;         /* KKT residual of the returned beta (FP64)           */
+} pam_fit_stats;
+
+/* a3-a6. For every subdomain: Gaussian RBF design at the samples (Eq.
+ * gaussian_rbf), Shepard row normalization W (Def. 1, Eq. shepard_rbf), normal
+ * products G = W'W, b = W'y, and the unique elastic-net minimizer
+ *   argmin 1/2||y - W beta||^2 + lambda1||beta||_1 + lambda2/2||beta||^2
+ * (Eq. elastic, Sec. 3.3): CD warm-up, exact sign-consistent active-set
+ * finish in FP64, KKT certificate. beta [n_sub*m_cap] (in: warm start if
+ * opts->warm_start, out: coefficients; slots >= m[s] are set to 0).
+ * stats: [n_sub] or NULL. */
+pam_status pam_fit_subdomains(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,
+                              const pam_enet_opts *opts, double *beta, pam_fit_stats *stats);
+
+/* Refinement controls (Alg. 1 inputs K_top, M_max, eps_tol; Sec. 3.4 eta). */
+typedef struct {
+    int32_t k_top;              /* elements marked per round                   */
+    const int32_t *k_top_sub;   /* [host] per-subdomain K_top, or NULL          */
+    int32_t max_rounds;         /* enrichment rounds after the first fit        */
+    int32_t m_max;              /* max centers added per subdomain              */
+    double eta;                 /* width factor of new centers, in (0, 1)      */
+    double eps_tol;             /* stop when max R_T < eps_tol; only elements
+                                   with R_T >= eps_tol are marked              */
+    int32_t space;              /* 0: R_T on log10 values, 1: on 10^values     */
+    int32_t *elem_level;        /* [N_tot] times each element was marked (in/out) */
+    int32_t *rounds;            /* [n_sub] fits done per subdomain (out) or NULL */
+    double *round_stats;        /* [n_sub*(max_rounds+1)*5] per round
+                                   {M, support, max R_T, marked, sum R_T}, or NULL */
+} pam_refine_opts;
+
+/* a3-a9 (Alg. 1): fit, residual indicator R_T (Sec. 2 Step 3, 2-point
+ * Gauss-Legendre per axis), stop test, marking of the K_top largest R_T,
+ * enrichment with 2^dim-1 centers per marked element at
+ * x_T + (h_T/2^(l+1)) o, o in {0,1}^dim \ {0}, widths sigma0*eta^(l+1)
+ * (Sec. 3.4), zero-extension of beta and refit, for all subdomains at once.
+ * dict is updated in place; requires m_cap >= m + m_max growth room or the
+ * additions are truncated at m_cap. */
+pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, double *beta,
+                      const pam_enet_opts *opts, const pam_refine_opts *ropts,
+                      pam_fit_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * a10. Global reconstruction (Sec. 2 Step 4): K*(x) = K*_{omega_i}(x) for x
+ * in the owned box omega_i, with the local normalized expansion
+ * sum_m beta_m phi_m(x) / sum_m phi_m(x) over the owner's whole dictionary.
+ * Owners are found per axis from the owned breakpoints (half-open, last
+ * interval closed). Points outside the closed domain give NaN.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t dim;
+    int32_t n_sub_axis[3];
+    const double *axis_x;   /* [host] per-axis owned breakpoint coordinates,
+                               concatenated (n_sub_axis[a]+1 each)             */
+    int32_t sub_base;       /* index of this field's first subdomain in dict  */
+    int64_t q_begin, q_end; /* this field's query range                      */
+} pam_field;
+
+/* Evaluate n_fields fields (subdomains of all fields share dict/beta) at
+ * their query ranges in one pass. dtype 0: xq is float [Q*dim] and out is
+ * float [Q]; dtype 1: double. space 0: log10 values, 1: 10^values.
+ * n_outside: device int64 counter of out-of-domain queries (added to), or
+ * NULL. */
+pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
+                    const pam_dict *dict, const double *beta, int32_t dtype, const void *xq,
+                    int64_t Q, void *out, int32_t space, int64_t *n_outside);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAM_H */

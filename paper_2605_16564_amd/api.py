@@ -1,0 +1,309 @@
+"""Torch-facing wrappers of the C ABI: device buffers come from torch, every
+step of the method runs in libpam.so (see native.py). No CPU fallback."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import native as N
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _require_cuda(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise N.PamError(f"{name} must be a device tensor")
+
+
+class Context:
+    """One pam_ctx bound to a device; work goes on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise N.PamError("no HIP device available")
+        self.device = device
+        h = C.c_void_p()
+        N.check(N.lib().pam_create(C.byref(h), device), "pam_create")
+        self.h = h
+        self.use_current_stream()
+
+    def use_current_stream(self):
+        s = torch.cuda.current_stream(self.device)
+        N.check(N.lib().pam_set_stream(self.h, C.c_void_p(s.cuda_stream)), "pam_set_stream")
+
+    def sync(self):
+        N.check(N.lib().pam_sync(self.h), "pam_sync")
+
+    def close(self):
+        if self.h:
+            N.lib().pam_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- a1
+def _grid_struct(grid):
+    d = grid.dim
+    g = N.PamGrid()
+    g.dim = d
+    brk = np.ascontiguousarray(np.concatenate([np.asarray(b, np.int32) for b in grid.breaks[:d]]),
+                               dtype=np.int32)
+    for a in range(3):
+        g.n_cells[a] = int(grid.n_cells[a]) if a < d else 1
+        g.n_sub[a] = int(grid.n_sub[a]) if a < d else 1
+        g.lo[a] = float(grid.lo[a]) if a < d else 0.0
+        g.hi[a] = float(grid.hi[a]) if a < d else 1.0
+    g.breaks = brk.ctypes.data_as(C.c_void_p)
+    g.overlap = float(grid.overlap)
+    return g, brk  # keep brk alive
+
+
+@dataclass
+class Samples:
+    dim: int
+    n_sub: int
+    n_max: int
+    off: torch.Tensor       # int64 [n_sub+1] device
+    off_host: np.ndarray    # int64 [n_sub+1]
+    x: torch.Tensor         # f64 [N_tot, dim]
+    y: torch.Tensor         # f64 [N_tot]
+    h: torch.Tensor         # f64 [N_tot, dim]
+    cell: Optional[torch.Tensor] = None
+
+    def struct(self):
+        s = N.PamSamples()
+        s.dim, s.n_sub, s.n_max = self.dim, self.n_sub, self.n_max
+        s.off = _p(self.off)
+        s.off_host = self.off_host.ctypes.data_as(C.c_void_p)
+        s.x, s.y, s.h = _p(self.x), _p(self.y), _p(self.h)
+        return s
+
+
+def partition_count(grid):
+    g, brk = _grid_struct(grid)
+    n = int(np.prod(grid.n_sub[: grid.dim]))
+    off = np.zeros(n + 1, np.int64)
+    nmax = C.c_int32()
+    N.check(N.lib().pam_partition_count(C.byref(g), off.ctypes.data_as(C.c_void_p), C.byref(nmax)),
+            "pam_partition_count")
+    return off, int(nmax.value)
+
+
+def partition(ctx: Context, grid, cell_y: Optional[torch.Tensor] = None) -> Samples:
+    """a1: samples of every subdomain, gathered on the device."""
+    dev = torch.device("cuda", ctx.device)
+    off, nmax = partition_count(grid)
+    d = grid.dim
+    tot = int(off[-1])
+    if cell_y is None:
+        cell_y = torch.as_tensor(np.ascontiguousarray(grid.y, np.float64), device=dev)
+    _require_cuda(cell_y, "cell_y")
+    off_d = torch.as_tensor(off, device=dev)
+    x = torch.empty((tot, d), dtype=torch.float64, device=dev)
+    y = torch.empty(tot, dtype=torch.float64, device=dev)
+    h = torch.empty((tot, d), dtype=torch.float64, device=dev)
+    cell = torch.empty((tot, d), dtype=torch.int32, device=dev)
+    g, brk = _grid_struct(grid)
+    ctx.use_current_stream()
+    N.check(N.lib().pam_partition_gather(ctx.h, C.byref(g), _p(cell_y), _p(off_d), _p(x), _p(y),
+                                         _p(h), _p(cell)), "pam_partition_gather")
+    n = int(np.prod(grid.n_sub[:d]))
+    return Samples(d, n, nmax, off_d, off, x, y, h, cell)
+
+
+# ---------------------------------------------------------------- dictionary
+@dataclass
+class Dictionary:
+    n_sub: int
+    dim: int
+    m_cap: int
+    m: torch.Tensor        # int32 [n_sub]
+    c: torch.Tensor        # f64 [n_sub, m_cap, dim]
+    sigma: torch.Tensor    # f64 [n_sub, m_cap]
+    level: torch.Tensor    # int32 [n_sub, m_cap]
+
+    @staticmethod
+    def empty(n_sub, dim, m_cap, device):
+        dev = torch.device("cuda", device) if isinstance(device, int) else device
+        return Dictionary(n_sub, dim, m_cap,
+                          torch.zeros(n_sub, dtype=torch.int32, device=dev),
+                          torch.zeros((n_sub, m_cap, dim), dtype=torch.float64, device=dev),
+                          torch.ones((n_sub, m_cap), dtype=torch.float64, device=dev),
+                          torch.zeros((n_sub, m_cap), dtype=torch.int32, device=dev))
+
+    def clone(self):
+        return Dictionary(self.n_sub, self.dim, self.m_cap, self.m.clone(), self.c.clone(),
+                          self.sigma.clone(), self.level.clone())
+
+    def struct(self):
+        s = N.PamDict()
+        s.n_sub, s.dim, s.m_cap = self.n_sub, self.dim, self.m_cap
+        s.m, s.c, s.sigma, s.level = _p(self.m), _p(self.c), _p(self.sigma), _p(self.level)
+        return s
+
+
+def init_lattice(ctx: Context, grid, g: Sequence[int], m_cap: int, sigma_factor: float = 1.0):
+    """a2: g^d lattice dictionary per owned box."""
+    D = Dictionary.empty(int(np.prod(grid.n_sub[: grid.dim])), grid.dim, m_cap, ctx.device)
+    gs, brk = _grid_struct(grid)
+    garr = np.ascontiguousarray(np.asarray(g[: grid.dim], np.int32))
+    ds = D.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_init_lattice(ctx.h, C.byref(gs), garr.ctypes.data_as(C.c_void_p),
+                                     float(sigma_factor), C.byref(ds)), "pam_init_lattice")
+    return D
+
+
+# ---------------------------------------------------------------- a3-a9
+@dataclass
+class EnetOpts:
+    lambda1: float
+    lambda2: float
+    precision: str = "f64"
+    cd_sweeps: int = 8
+    max_iter: int = 100000
+    batched: bool = True
+    lambda1_sub: Optional[torch.Tensor] = None
+    lambda2_sub: Optional[torch.Tensor] = None
+    support_hint: Optional[torch.Tensor] = None
+
+    def struct(self, warm_start: bool):
+        o = N.PamEnetOpts()
+        o.lambda1, o.lambda2 = float(self.lambda1), float(self.lambda2)
+        o.lambda1_sub, o.lambda2_sub = _p(self.lambda1_sub), _p(self.lambda2_sub)
+        o.precision = N.PREC[self.precision]
+        o.cd_sweeps, o.max_iter = int(self.cd_sweeps), int(self.max_iter)
+        o.warm_start = 1 if warm_start else 0
+        o.batched = 1 if self.batched else 0
+        o.support_hint = _p(self.support_hint)
+        return o
+
+
+STATS_DTYPE = np.dtype([("status", np.int32), ("cd_sweeps", np.int32), ("iters", np.int32),
+                        ("support", np.int32), ("kkt", np.float64)])
+
+
+def new_stats(n_sub, device):
+    return torch.zeros(n_sub * N.STATS_BYTES, dtype=torch.uint8,
+                       device=torch.device("cuda", device) if isinstance(device, int) else device)
+
+
+def stats_to_numpy(stats: torch.Tensor) -> np.ndarray:
+    return stats.cpu().numpy().view(STATS_DTYPE)
+
+
+def fit(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts,
+        beta: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None):
+    """a3-a6 for every subdomain; returns (beta [n_sub, m_cap] f64, stats tensor)."""
+    warm = beta is not None
+    if beta is None:
+        beta = torch.zeros((D.n_sub, D.m_cap), dtype=torch.float64, device=D.m.device)
+    if stats is None:
+        stats = new_stats(D.n_sub, D.m.device)
+    ss, ds, os_ = S.struct(), D.struct(), opts.struct(warm)
+    ctx.use_current_stream()
+    N.check(N.lib().pam_fit_subdomains(ctx.h, C.byref(ss), C.byref(ds), C.byref(os_), _p(beta),
+                                       _p(stats)), "pam_fit_subdomains")
+    return beta, stats
+
+
+@dataclass
+class RefineOpts:
+    k_top: int = 204
+    k_top_sub: Optional[np.ndarray] = None
+    max_rounds: int = 3
+    m_max: int = 1 << 30
+    eta: float = 0.5
+    eps_tol: float = 0.0
+    space: int = 0
+
+
+def refine(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, ropts: RefineOpts,
+           beta: Optional[torch.Tensor] = None, elem_level: Optional[torch.Tensor] = None):
+    """Alg. 1 on every subdomain (D is updated in place).
+    Returns (beta, elem_level, rounds, round_stats [n_sub, R+1, 5], stats)."""
+    dev = D.m.device
+    warm = beta is not None
+    if beta is None:
+        beta = torch.zeros((D.n_sub, D.m_cap), dtype=torch.float64, device=dev)
+    if elem_level is None:
+        elem_level = torch.zeros(int(S.off_host[-1]), dtype=torch.int32, device=dev)
+    rounds = torch.zeros(D.n_sub, dtype=torch.int32, device=dev)
+    rstats = torch.zeros((D.n_sub, ropts.max_rounds + 1, 5), dtype=torch.float64, device=dev)
+    stats = new_stats(D.n_sub, dev)
+    r = N.PamRefineOpts()
+    r.k_top = int(ropts.k_top)
+    kts = None
+    if ropts.k_top_sub is not None:
+        kts = np.ascontiguousarray(ropts.k_top_sub, dtype=np.int32)
+        r.k_top_sub = kts.ctypes.data_as(C.c_void_p)
+    r.max_rounds, r.m_max = int(ropts.max_rounds), int(min(ropts.m_max, 2 ** 31 - 1))
+    r.eta, r.eps_tol, r.space = float(ropts.eta), float(ropts.eps_tol), int(ropts.space)
+    r.elem_level, r.rounds, r.round_stats = _p(elem_level), _p(rounds), _p(rstats)
+    ss, ds, os_ = S.struct(), D.struct(), opts.struct(warm)
+    ctx.use_current_stream()
+    N.check(N.lib().pam_refine(ctx.h, C.byref(ss), C.byref(ds), _p(beta), C.byref(os_),
+                               C.byref(r), _p(stats)), "pam_refine")
+    return beta, elem_level, rounds, rstats, stats
+
+
+# ---------------------------------------------------------------- a10
+def axis_coords(grid) -> List[np.ndarray]:
+    out = []
+    for a in range(grid.dim):
+        hcell = (grid.hi[a] - grid.lo[a]) / grid.n_cells[a]
+        out.append(np.array([grid.lo[a] + float(b) * hcell for b in grid.breaks[a]]))
+    return out
+
+
+def evaluate(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.Tensor,
+             q_counts: Optional[Sequence[int]] = None, sub_bases: Optional[Sequence[int]] = None,
+             space: int = 0, n_outside: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """K*(x) of one or several fields (subdomains concatenated in D) at xq.
+    xq is float32 or float64 [Q, dim]; field f owns q_counts[f] consecutive rows."""
+    if not isinstance(grids, (list, tuple)):
+        grids = [grids]
+    _require_cuda(xq, "xq")
+    dtype = 0 if xq.dtype == torch.float32 else 1
+    if xq.dtype not in (torch.float32, torch.float64):
+        raise N.PamError("xq must be float32 or float64")
+    Q = int(xq.shape[0])
+    if q_counts is None:
+        q_counts = [Q]
+    if sub_bases is None:
+        sub_bases, acc = [], 0
+        for g in grids:
+            sub_bases.append(acc)
+            acc += int(np.prod(g.n_sub[: g.dim]))
+    fields = (N.PamField * len(grids))()
+    keep = []
+    q0 = 0
+    for f, g in enumerate(grids):
+        ax = np.ascontiguousarray(np.concatenate(axis_coords(g)), dtype=np.float64)
+        keep.append(ax)
+        F = fields[f]
+        F.dim = g.dim
+        for a in range(3):
+            F.n_sub_axis[a] = int(g.n_sub[a]) if a < g.dim else 1
+        F.axis_x = ax.ctypes.data_as(C.c_void_p)
+        F.sub_base = int(sub_bases[f])
+        F.q_begin, F.q_end = q0, q0 + int(q_counts[f])
+        q0 += int(q_counts[f])
+    out = torch.empty(Q, dtype=xq.dtype, device=xq.device)
+    ds = D.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_eval(ctx.h, len(grids), fields, C.byref(ds), _p(beta), dtype,
+                             _p(xq.contiguous()), Q, _p(out), int(space), _p(n_outside)),
+            "pam_eval")
+    return out

@@ -1,0 +1,407 @@
+// Host side of the C ABI declared in include/pam.h: context, workspace,
+// argument validation and orchestration of the kernels.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "pam_internal.h"
+
+namespace pam {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+pam_status ensure(pam_ctx *ctx, Buf b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (ctx->ws.bytes[b] >= bytes) return PAM_OK;
+    if (ctx->ws.ptr[b]) {
+        PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+        PAM_CHECK_HIP(hipFree(ctx->ws.ptr[b]));
+        ctx->ws.ptr[b] = nullptr;
+        ctx->ws.bytes[b] = 0;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("workspace allocation of " + std::to_string(bytes) + " bytes failed");
+        return PAM_ERR_NOMEM;
+    }
+    ctx->ws.ptr[b] = p;
+    ctx->ws.bytes[b] = bytes;
+    return PAM_OK;
+}
+
+// Small host tables go through the context's pinned staging buffer.
+pam_status upload_to(pam_ctx *ctx, void *dst, const void *host, size_t bytes) {
+    if (bytes == 0) return PAM_OK;
+    Staging &sg = ctx->staging;
+    if (sg.done) PAM_CHECK_HIP(hipEventSynchronize(sg.done));
+    if (sg.bytes < bytes) {
+        if (sg.host) PAM_CHECK_HIP(hipHostFree(sg.host));
+        sg.host = nullptr;
+        sg.bytes = 0;
+        PAM_CHECK_HIP(hipHostMalloc(&sg.host, bytes));
+        sg.bytes = bytes;
+    }
+    if (!sg.done) PAM_CHECK_HIP(hipEventCreateWithFlags(&sg.done, hipEventDisableTiming));
+    memcpy(sg.host, host, bytes);
+    PAM_CHECK_HIP(hipMemcpyAsync(dst, sg.host, bytes, hipMemcpyHostToDevice, ctx->stream));
+    PAM_CHECK_HIP(hipEventRecord(sg.done, ctx->stream));
+    return PAM_OK;
+}
+
+pam_status upload(pam_ctx *ctx, Buf b, const void *host, size_t bytes) {
+    pam_status st = ensure(ctx, b, bytes);
+    if (st != PAM_OK) return st;
+    return upload_to(ctx, ctx->ws.ptr[b], host, bytes);
+}
+
+// setup kernels (k_setup.hip)
+pam_status launch_gather(pam_ctx *ctx, const pam_grid *g, const void *tab_dev, int n_sub,
+                         int32_t n_max, const double *cell_y, const int64_t *off, double *x,
+                         double *y, double *h, int32_t *cell);
+pam_status launch_lattice(pam_ctx *ctx, int dim, const int32_t *g, int n_sub, int m_cap,
+                          const void *tab_dev, pam_dict *dict);
+size_t gather_table_bytes(int n_sub);
+size_t lattice_table_bytes(int n_sub);
+void build_gather_table(const pam_grid *g, void *host_tab);
+void build_lattice_table(const pam_grid *g, const int32_t *gl, double sigma_factor, void *host_tab);
+void axis_range(int n_cells, int n_sub, const int32_t *brk, int k, double overlap, int *first, int *last);
+// eval (k_eval.hip)
+pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, const pam_dict *dict,
+                       const double *beta, int dtype, const void *xq, int64_t Q, void *out,
+                       int space, int64_t *n_outside);
+
+static pam_status check_grid(const pam_grid *g, int *n_sub_total) {
+    PAM_REQUIRE(g, "grid is NULL");
+    PAM_REQUIRE(g->dim >= 1 && g->dim <= 3, "grid dim must be 1, 2 or 3");
+    PAM_REQUIRE(g->breaks, "grid breaks are NULL");
+    PAM_REQUIRE(g->overlap >= 0.0 && g->overlap < 1.0, "overlap must be in [0, 1)");
+    int pos = 0, tot = 1;
+    for (int a = 0; a < g->dim; ++a) {
+        PAM_REQUIRE(g->n_cells[a] >= 1 && g->n_sub[a] >= 1, "cell and subdomain counts must be >= 1");
+        PAM_REQUIRE(g->hi[a] > g->lo[a], "domain box must have hi > lo");
+        const int32_t *b = g->breaks + pos;
+        PAM_REQUIRE(b[0] == 0 && b[g->n_sub[a]] == g->n_cells[a], "breaks must span 0..n_cells");
+        for (int k = 0; k < g->n_sub[a]; ++k) PAM_REQUIRE(b[k + 1] > b[k], "breaks must increase");
+        pos += g->n_sub[a] + 1;
+        tot *= g->n_sub[a];
+    }
+    *n_sub_total = tot;
+    return PAM_OK;
+}
+
+static size_t ws_budget() {
+    const char *e = getenv("PAM_WS_BYTES");
+    if (e) return (size_t)strtoull(e, nullptr, 10);
+    return (size_t)48 << 30;
+}
+
+static size_t wbytes(int prec) { return prec == PAM_PREC_F64 ? 8 : (prec == PAM_PREC_F32 ? 4 : 2); }
+static size_t gbytes(int prec) { return prec == PAM_PREC_F64 ? 8 : 4; }
+
+// Validate and run a3-a6 for subdomains [0, n_sub) in batches that fit the
+// workspace budget (batched = 0: one subdomain per launch).
+static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
+                          const pam_enet_opts *o, double *beta, pam_fit_stats *stats,
+                          const int32_t *active, int warm_start) {
+    FitArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n_sub = S->n_sub;
+    a.dim = S->dim;
+    a.m_cap = D->m_cap;
+    a.mpad = mpad_of(D->m_cap);
+    a.npad = npad_of(S->n_max);
+    a.n_max = S->n_max;
+    a.off = S->off;
+    a.x = S->x;
+    a.y = S->y;
+    a.m = D->m;
+    a.c = D->c;
+    a.sigma = D->sigma;
+    a.lambda1 = o->lambda1;
+    a.lambda2 = o->lambda2;
+    a.lambda1_sub = o->lambda1_sub;
+    a.lambda2_sub = o->lambda2_sub;
+    a.precision = o->precision;
+    a.cd_sweeps = o->cd_sweeps;
+    a.max_iter = o->max_iter;
+    a.warm_start = warm_start;
+    a.hint = o->support_hint;
+    a.beta = beta;
+    a.stats = stats;
+    a.active = active;
+    const size_t per_sub = (size_t)a.mpad * a.npad * wbytes(a.precision) +
+                           (size_t)a.mpad * a.mpad * gbytes(a.precision) +
+                           (size_t)a.m_cap * a.m_cap * 8 + (size_t)a.m_cap * 8 * 8 +
+                           (size_t)a.m_cap * 3 * 4;
+    int batch = o->batched ? (int)std::max<size_t>(1, ws_budget() / std::max<size_t>(per_sub, 1)) : 1;
+    batch = std::min(batch, a.n_sub);
+    pam_status st;
+    if ((st = ensure(ctx, BUF_WT, (size_t)batch * a.mpad * a.npad * wbytes(a.precision))) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_G, (size_t)batch * a.mpad * a.mpad * gbytes(a.precision))) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_H, (size_t)batch * a.m_cap * a.m_cap * 8)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_VEC, (size_t)batch * a.m_cap * 8 * 8)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_IVEC, (size_t)batch * a.m_cap * 3 * 4)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_FLAGS, (size_t)a.n_sub * 4)) != PAM_OK) return st;
+    PAM_CHECK_HIP(hipMemsetAsync(ctx->ws.ptr[BUF_FLAGS], 0, (size_t)a.n_sub * 4, ctx->stream));
+    for (int b0 = 0; b0 < a.n_sub; b0 += batch) {
+        a.sub_begin = b0;
+        a.sub_count = std::min(batch, a.n_sub - b0);
+        if ((st = launch_assemble(ctx, a)) != PAM_OK) return st;
+        if ((st = launch_gram(ctx, a)) != PAM_OK) return st;
+        if ((st = launch_solve(ctx, a)) != PAM_OK) return st;
+    }
+    return PAM_OK;
+}
+
+static pam_status check_fit_args(const pam_samples *S, const pam_dict *D, const pam_enet_opts *o,
+                                 const double *beta) {
+    PAM_REQUIRE(S && D && o && beta, "NULL argument");
+    PAM_REQUIRE(S->dim >= 1 && S->dim <= 3 && S->dim == D->dim, "dimension mismatch");
+    PAM_REQUIRE(S->n_sub >= 1 && S->n_sub == D->n_sub, "subdomain count mismatch");
+    PAM_REQUIRE(S->off && S->off_host && S->x && S->y, "sample arrays are NULL");
+    PAM_REQUIRE(D->m && D->c && D->sigma && D->level, "dictionary arrays are NULL");
+    PAM_REQUIRE(D->m_cap >= 1, "m_cap must be >= 1");
+    PAM_REQUIRE(o->lambda1_sub || o->lambda1 >= 0.0, "lambda1 must be >= 0");
+    PAM_REQUIRE(o->lambda2_sub || o->lambda2 >= 0.0, "lambda2 must be >= 0");
+    PAM_REQUIRE(o->precision >= PAM_PREC_F64 && o->precision <= PAM_PREC_BF16, "unknown precision");
+    PAM_REQUIRE(o->cd_sweeps >= 0 && o->max_iter >= 1, "cd_sweeps >= 0 and max_iter >= 1 required");
+    int64_t nmax = 0;
+    for (int s = 0; s < S->n_sub; ++s) {
+        const int64_t n = S->off_host[s + 1] - S->off_host[s];
+        PAM_REQUIRE(n >= 0, "sample offsets must be non-decreasing");
+        nmax = std::max(nmax, n);
+    }
+    PAM_REQUIRE(nmax <= S->n_max, "n_max is smaller than the largest subdomain");
+    return PAM_OK;
+}
+
+static pam_status check_ctx(pam_ctx *ctx) {
+    if (!ctx || !ctx->alive) {
+        set_error("invalid context");
+        return PAM_ERR_STATE;
+    }
+    PAM_CHECK_HIP(hipSetDevice(ctx->device));
+    return PAM_OK;
+}
+
+}  // namespace pam
+
+using namespace pam;
+
+extern "C" {
+
+const char *pam_last_error(void) { return g_last_error.c_str(); }
+const char *pam_version(void) { return "pam-mi355x 0.1 (gfx950)"; }
+
+pam_status pam_create(pam_ctx **out, int device) {
+    if (!out) {
+        set_error("out is NULL");
+        return PAM_ERR_ARG;
+    }
+    int n = 0;
+    PAM_CHECK_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) {
+        set_error("no such HIP device");
+        return PAM_ERR_ARG;
+    }
+    PAM_CHECK_HIP(hipSetDevice(device));
+    pam_ctx *c = new pam_ctx();
+    c->device = device;
+    *out = c;
+    return PAM_OK;
+}
+
+pam_status pam_destroy(pam_ctx *ctx) {
+    if (!ctx) return PAM_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int b = 0; b < BUF_COUNT; ++b)
+        if (ctx->ws.ptr[b]) (void)hipFree(ctx->ws.ptr[b]);
+    if (ctx->staging.host) (void)hipHostFree(ctx->staging.host);
+    if (ctx->staging.done) (void)hipEventDestroy(ctx->staging.done);
+    ctx->alive = false;
+    delete ctx;
+    return PAM_OK;
+}
+
+pam_status pam_set_stream(pam_ctx *ctx, void *stream) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    ctx->stream = (hipStream_t)stream;
+    return PAM_OK;
+}
+
+pam_status pam_sync(pam_ctx *ctx) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    return PAM_OK;
+}
+
+pam_status pam_partition_count(const pam_grid *grid, int64_t *off_host, int32_t *n_max) {
+    int n_sub = 0;
+    pam_status st = check_grid(grid, &n_sub);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(off_host && n_max, "NULL output");
+    std::vector<char> tab(gather_table_bytes(n_sub));
+    build_gather_table(grid, tab.data());
+    const int32_t *t = (const int32_t *)tab.data();  // first[3], last[3] per subdomain
+    off_host[0] = 0;
+    int64_t mx = 0;
+    for (int s = 0; s < n_sub; ++s) {
+        int64_t cnt = 1;
+        for (int a = 0; a < grid->dim; ++a) cnt *= (int64_t)(t[s * 6 + 3 + a] - t[s * 6 + a]);
+        off_host[s + 1] = off_host[s] + cnt;
+        mx = std::max(mx, cnt);
+    }
+    *n_max = (int32_t)mx;
+    return PAM_OK;
+}
+
+pam_status pam_partition_gather(pam_ctx *ctx, const pam_grid *grid, const double *cell_y,
+                                const int64_t *off, double *x, double *y, double *h, int32_t *cell) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    int n_sub = 0;
+    if ((st = check_grid(grid, &n_sub)) != PAM_OK) return st;
+    PAM_REQUIRE(cell_y && off && x && y && h && cell, "NULL argument");
+    std::vector<int64_t> offh(n_sub + 1);
+    int32_t n_max = 0;
+    if ((st = pam_partition_count(grid, offh.data(), &n_max)) != PAM_OK) return st;
+    std::vector<char> tab(gather_table_bytes(n_sub));
+    build_gather_table(grid, tab.data());
+    if ((st = upload(ctx, BUF_TABLE, tab.data(), tab.size())) != PAM_OK) return st;
+    return launch_gather(ctx, grid, ctx->ws.ptr[BUF_TABLE], n_sub, n_max, cell_y, off, x, y, h, cell);
+}
+
+pam_status pam_init_lattice(pam_ctx *ctx, const pam_grid *grid, const int32_t *g,
+                            double sigma_factor, pam_dict *dict) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    int n_sub = 0;
+    if ((st = check_grid(grid, &n_sub)) != PAM_OK) return st;
+    PAM_REQUIRE(g && dict && dict->m && dict->c && dict->sigma && dict->level, "NULL argument");
+    PAM_REQUIRE(dict->n_sub == n_sub && dict->dim == grid->dim, "dictionary does not match grid");
+    PAM_REQUIRE(sigma_factor > 0.0, "sigma_factor must be > 0");
+    int64_t M = 1;
+    for (int a = 0; a < grid->dim; ++a) {
+        PAM_REQUIRE(g[a] >= 1, "lattice counts must be >= 1");
+        M *= g[a];
+    }
+    if (M > dict->m_cap) {
+        set_error("m_cap too small for the lattice: need " + std::to_string(M));
+        return PAM_ERR_CAPACITY;
+    }
+    std::vector<char> tab(lattice_table_bytes(n_sub));
+    build_lattice_table(grid, g, sigma_factor, tab.data());
+    if ((st = upload(ctx, BUF_TABLE, tab.data(), tab.size())) != PAM_OK) return st;
+    return launch_lattice(ctx, grid->dim, g, n_sub, dict->m_cap, ctx->ws.ptr[BUF_TABLE], dict);
+}
+
+pam_status pam_fit_subdomains(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,
+                              const pam_enet_opts *opts, double *beta, pam_fit_stats *stats) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    if ((st = check_fit_args(samples, dict, opts, beta)) != PAM_OK) return st;
+    return run_fit(ctx, samples, dict, opts, beta, stats, nullptr, opts->warm_start);
+}
+
+pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, double *beta,
+                      const pam_enet_opts *opts, const pam_refine_opts *r, pam_fit_stats *stats) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    if ((st = check_fit_args(samples, dict, opts, beta)) != PAM_OK) return st;
+    PAM_REQUIRE(r && r->elem_level && samples->h, "refinement arguments are NULL");
+    PAM_REQUIRE(r->max_rounds >= 0 && r->m_max >= 0, "max_rounds and m_max must be >= 0");
+    PAM_REQUIRE(r->eta > 0.0 && r->eta < 1.0, "eta must be in (0, 1)");
+    PAM_REQUIRE(r->k_top >= 0 || r->k_top_sub, "k_top must be >= 0");
+    PAM_REQUIRE(r->space == 0 || r->space == 1, "space must be 0 or 1");
+    const int n = samples->n_sub;
+    // per-subdomain int tables: active, m0, k_top
+    std::vector<int32_t> tab((size_t)3 * n);
+    for (int s = 0; s < n; ++s) {
+        tab[s] = 1;
+        tab[2 * n + s] = r->k_top_sub ? r->k_top_sub[s] : r->k_top;
+    }
+    if ((st = upload(ctx, BUF_TABLE, tab.data(), tab.size() * 4)) != PAM_OK) return st;
+    int32_t *active = wsp<int32_t>(ctx, BUF_TABLE);
+    int32_t *m0 = active + n;
+    int32_t *ktop = active + 2 * n;
+    PAM_CHECK_HIP(hipMemcpyAsync(m0, dict->m, (size_t)n * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    int64_t n_tot = samples->off_host[n];
+    if ((st = ensure(ctx, BUF_R, (size_t)std::max<int64_t>(n_tot, 1) * 8)) != PAM_OK) return st;
+    RefineArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.n_sub = n;
+    ra.dim = samples->dim;
+    ra.m_cap = dict->m_cap;
+    ra.n_max = samples->n_max;
+    ra.off = samples->off;
+    ra.x = samples->x;
+    ra.y = samples->y;
+    ra.h = samples->h;
+    ra.m = dict->m;
+    ra.c = dict->c;
+    ra.sigma = dict->sigma;
+    ra.level = dict->level;
+    ra.beta = beta;
+    ra.k_top = ktop;
+    ra.m_max = r->m_max;
+    ra.space = r->space;
+    ra.max_rounds = r->max_rounds;
+    ra.eta = r->eta;
+    ra.eps_tol = r->eps_tol;
+    ra.elem_level = r->elem_level;
+    ra.active = active;
+    ra.m0 = m0;
+    ra.rounds = r->rounds;
+    ra.round_stats = r->round_stats;
+    ra.stats = stats;
+    for (int round = 0; round <= r->max_rounds; ++round) {
+        const int warm = round == 0 ? opts->warm_start : 1;
+        if ((st = run_fit(ctx, samples, dict, opts, beta, stats, active, warm)) != PAM_OK) return st;
+        ra.round = round;
+        if ((st = launch_indicator(ctx, ra)) != PAM_OK) return st;
+        if ((st = launch_mark_enrich(ctx, ra)) != PAM_OK) return st;
+    }
+    return PAM_OK;
+}
+
+pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields, const pam_dict *dict,
+                    const double *beta, int32_t dtype, const void *xq, int64_t Q, void *out,
+                    int32_t space, int64_t *n_outside) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(n_fields >= 1 && fields && dict && beta, "NULL argument");
+    PAM_REQUIRE(Q >= 0 && (Q == 0 || (xq && out)), "query arrays are NULL");
+    PAM_REQUIRE(dtype == 0 || dtype == 1, "dtype must be 0 (f32) or 1 (f64)");
+    PAM_REQUIRE(space == 0 || space == 1, "space must be 0 or 1");
+    int64_t prev = 0;
+    for (int f = 0; f < n_fields; ++f) {
+        const pam_field &F = fields[f];
+        PAM_REQUIRE(F.dim == dict->dim && F.axis_x, "field dimension mismatch");
+        PAM_REQUIRE(F.q_begin == prev && F.q_end >= F.q_begin && F.q_end <= Q,
+                    "field query ranges must tile [0, Q) in order");
+        prev = F.q_end;
+        int nsub = 1, pos = 0;
+        for (int d = 0; d < F.dim; ++d) {
+            PAM_REQUIRE(F.n_sub_axis[d] >= 1, "n_sub_axis must be >= 1");
+            for (int i = 0; i < F.n_sub_axis[d]; ++i)
+                PAM_REQUIRE(F.axis_x[pos + i + 1] > F.axis_x[pos + i], "axis breakpoints must increase");
+            pos += F.n_sub_axis[d] + 1;
+            nsub *= F.n_sub_axis[d];
+        }
+        PAM_REQUIRE(F.sub_base >= 0 && F.sub_base + nsub <= dict->n_sub,
+                    "field subdomains exceed the dictionary");
+    }
+    PAM_REQUIRE(prev == Q, "field query ranges must cover [0, Q)");
+    return launch_eval(ctx, n_fields, fields, dict, beta, dtype, xq, Q, out, space, n_outside);
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Internal declarations of the PAM HIP library (gfx950). Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pam.h"
+
+namespace pam {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+
+#define PAM_CHECK_HIP(expr)                                                           \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess) {                                                       \
+            ::pam::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));      \
+            return PAM_ERR_HIP;                                                       \
+        }                                                                             \
+    } while (0)
+
+#define PAM_REQUIRE(cond, msg)                                                        \
+    do {                                                                              \
+        if (!(cond)) {                                                                \
+            ::pam::set_error(msg);                                                    \
+            return PAM_ERR_ARG;                                                       \
+        }                                                                             \
+    } while (0)
+
+// ---------------------------------------------------------------- workspace
+enum Buf {
+    BUF_WT = 0,     // normalized design, transposed [n_sub][mpad][npad] (f64/f32/bf16)
+    BUF_G,          // Gram incl. data row [n_sub][mpad][mpad] (f64 or f32)
+    BUF_H,          // inverse of the active block [n_sub][m_cap][m_cap] f64
+    BUF_VEC,        // per-subdomain f64 vectors (gradient, scratch) [n_sub][8][m_cap]
+    BUF_IVEC,       // per-subdomain int vectors (active list, positions) [n_sub][3][m_cap]
+    BUF_TABLE,      // small launch tables (per-subdomain parameters)
+    BUF_R,          // indicator values [N_tot] f64
+    BUF_MARK,       // marked element lists [n_sub][n_max] int32
+    BUF_EVAL,       // query binning workspace
+    BUF_FLAGS,      // per-subdomain flags / counters
+    BUF_COUNT
+};
+
+struct Workspace {
+    void *ptr[BUF_COUNT] = {};
+    size_t bytes[BUF_COUNT] = {};
+};
+
+// Pinned staging buffer for small host tables; `done` marks the end of the
+// previous upload so the buffer is not overwritten while a copy is pending.
+struct Staging {
+    void *host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+};
+
+}  // namespace pam
+
+struct pam_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    pam::Workspace ws;
+    pam::Staging staging;
+    bool alive = true;
+};
+
+namespace pam {
+
+// Grow buffer `b` of the context to at least `bytes` (synchronizes the stream
+// before releasing an older, smaller allocation).
+pam_status ensure(pam_ctx *ctx, Buf b, size_t bytes);
+template <typename T>
+T *wsp(pam_ctx *ctx, Buf b) { return reinterpret_cast<T *>(ctx->ws.ptr[b]); }
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Host-side helpers shared by the API files.
+pam_status upload(pam_ctx *ctx, Buf b, const void *host, size_t bytes);
+// Copy `bytes` of host data to device address `dst` through the staging buffer.
+pam_status upload_to(pam_ctx *ctx, void *dst, const void *host, size_t bytes);
+
+// Padded sizes of the design/Gram workspace for a dictionary capacity.
+inline int32_t mpad_of(int32_t m_cap) { return (int32_t)round_up((int64_t)m_cap + 1, 64); }
+inline int32_t npad_of(int32_t n_max) { return (int32_t)round_up(n_max > 0 ? n_max : 1, 32); }
+
+// ---------------------------------------------------------------- launchers
+// (defined in the .hip files; every launcher enqueues on ctx->stream and
+// returns PAM_OK or PAM_ERR_HIP).
+struct FitArgs {
+    int32_t n_sub, dim, m_cap, mpad, npad, n_max;
+    int32_t sub_begin, sub_count;   // subdomain range of this launch
+    const int64_t *off;
+    const double *x, *y;
+    const int32_t *m;
+    const double *c, *sigma;
+    double lambda1, lambda2;
+    const double *lambda1_sub, *lambda2_sub;
+    int32_t precision, cd_sweeps, max_iter, warm_start;
+    const uint8_t *hint;
+    double *beta;
+    pam_fit_stats *stats;
+    const int32_t *active;          // [n_sub] 1 = fit this subdomain (refinement), or NULL
+};
+
+pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);
+pam_status launch_gram(pam_ctx *ctx, const FitArgs &a);
+pam_status launch_solve(pam_ctx *ctx, const FitArgs &a);
+
+struct RefineArgs {
+    int32_t n_sub, dim, m_cap, n_max;
+    const int64_t *off;
+    const double *x, *y, *h;
+    int32_t *m;
+    double *c, *sigma;
+    int32_t *level;
+    double *beta;
+    const int32_t *k_top;           // [n_sub] device
+    int32_t m_max, space, round, max_rounds;
+    double eta, eps_tol;
+    int32_t *elem_level;
+    int32_t *active;                // [n_sub] in/out: 1 while refining
+    int32_t *m0;                    // [n_sub] center count before the first round
+    int32_t *rounds;
+    double *round_stats;
+    pam_fit_stats *stats;
+};
+
+pam_status launch_indicator(pam_ctx *ctx, const RefineArgs &a);
+pam_status launch_mark_enrich(pam_ctx *ctx, const RefineArgs &a);
+
+}  // namespace pam

@@ -1,0 +1,112 @@
+"""ctypes binding of the C ABI in include/pam.h (argument marshalling only).
+
+Every computation runs in libpam.so's HIP kernels; this module only lays out
+the C structs and forwards device pointers. Loading fails loudly when the
+library has not been built (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+LIB_PATH = Path(__file__).resolve().parent / "_build" / "libpam.so"
+
+PAM_OK = 0
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+ST_OK, ST_NOCONV, ST_UNDERFLOW, ST_EMPTY = 0, 1, 2, 3
+
+EXPORTS = [
+    "pam_create", "pam_destroy", "pam_set_stream", "pam_sync", "pam_last_error", "pam_version",
+    "pam_partition_count", "pam_partition_gather", "pam_init_lattice", "pam_fit_subdomains",
+    "pam_refine", "pam_eval",
+]
+
+
+class PamGrid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_cells", C.c_int32 * 3), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("n_sub", C.c_int32 * 3), ("breaks", C.c_void_p),
+                ("overlap", C.c_double)]
+
+
+class PamDict(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("dim", C.c_int32), ("m_cap", C.c_int32),
+                ("m", C.c_void_p), ("c", C.c_void_p), ("sigma", C.c_void_p),
+                ("level", C.c_void_p)]
+
+
+class PamSamples(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_sub", C.c_int32), ("n_max", C.c_int32),
+                ("off", C.c_void_p), ("off_host", C.c_void_p), ("x", C.c_void_p),
+                ("y", C.c_void_p), ("h", C.c_void_p)]
+
+
+class PamEnetOpts(C.Structure):
+    _fields_ = [("lambda1", C.c_double), ("lambda2", C.c_double),
+                ("lambda1_sub", C.c_void_p), ("lambda2_sub", C.c_void_p),
+                ("precision", C.c_int32), ("cd_sweeps", C.c_int32), ("max_iter", C.c_int32),
+                ("warm_start", C.c_int32), ("batched", C.c_int32),
+                ("support_hint", C.c_void_p)]
+
+
+class PamFitStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("cd_sweeps", C.c_int32), ("iters", C.c_int32),
+                ("support", C.c_int32), ("kkt", C.c_double)]
+
+
+class PamRefineOpts(C.Structure):
+    _fields_ = [("k_top", C.c_int32), ("k_top_sub", C.c_void_p), ("max_rounds", C.c_int32),
+                ("m_max", C.c_int32), ("eta", C.c_double), ("eps_tol", C.c_double),
+                ("space", C.c_int32), ("elem_level", C.c_void_p), ("rounds", C.c_void_p),
+                ("round_stats", C.c_void_p)]
+
+
+class PamField(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_sub_axis", C.c_int32 * 3), ("axis_x", C.c_void_p),
+                ("sub_base", C.c_int32), ("q_begin", C.c_int64), ("q_end", C.c_int64)]
+
+
+STATS_BYTES = C.sizeof(PamFitStats)
+
+_lib = None
+
+
+class PamError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libpam.so (built by paper_2605_16564_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise PamError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(str(LIB_PATH))
+        P = C.c_void_p
+        L.pam_create.argtypes = [C.POINTER(P), C.c_int]
+        L.pam_destroy.argtypes = [P]
+        L.pam_set_stream.argtypes = [P, P]
+        L.pam_sync.argtypes = [P]
+        L.pam_last_error.restype = C.c_char_p
+        L.pam_last_error.argtypes = []
+        L.pam_version.restype = C.c_char_p
+        L.pam_version.argtypes = []
+        L.pam_partition_count.argtypes = [C.POINTER(PamGrid), P, P]
+        L.pam_partition_gather.argtypes = [P, C.POINTER(PamGrid), P, P, P, P, P, P]
+        L.pam_init_lattice.argtypes = [P, C.POINTER(PamGrid), P, C.c_double, C.POINTER(PamDict)]
+        L.pam_fit_subdomains.argtypes = [P, C.POINTER(PamSamples), C.POINTER(PamDict),
+                                         C.POINTER(PamEnetOpts), P, P]
+        L.pam_refine.argtypes = [P, C.POINTER(PamSamples), C.POINTER(PamDict), P,
+                                 C.POINTER(PamEnetOpts), C.POINTER(PamRefineOpts), P]
+        L.pam_eval.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P, C.c_int32,
+                               P, C.c_int64, P, C.c_int32, P]
+        for name in EXPORTS:
+            if name not in ("pam_last_error", "pam_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str):
+    if status != PAM_OK:
+        msg = lib().pam_last_error().decode(errors="replace")
+        raise PamError(f"{what} failed with status {status}: {msg}")
