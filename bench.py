@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Benchmark of the PAM reconstruction hot path on one MI355X.
+
+One step = the whole path on one batch of synthetic input, inputs resident in
+HBM: sample gathering (a1), lattice dictionary (a2), Shepard design, MFMA
+Gram, elastic-net solve, indicator, marking and enrichment for every
+subdomain and round (a3-a9), then evaluation of the fitted field at the
+4x4 Gauss points of every cell (a10, mesh transfer to a finer quadrature).
+
+Default workload `facies256`: 256x256 three-facies field, 8x8 subdomains,
+12x12 initial centers, up to 3 enrichment rounds (K_top = 204). The metric is
+subdomain fits per second (one fit = one subdomain-round); evaluation
+throughput and the field's L1 error are reported beside it.
+
+Prints one JSON line. `--gpus N` with N > 1 is refused: this build runs on
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+if str(ROOT) not in sys.path:
+    sys.path.insert(0, str(ROOT))
+
+# MI355X published peaks used for the roofline fractions.
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # TFLOP/s, dense
+CU, LANES, CLOCK = 256, 64, 2.4e9                          # non-packed VALU lanes per CU
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="facies256")
+    ap.add_argument("--precision", default=None, help="Gram precision override (f64|f32|bf16)")
+    ap.add_argument("--cd-sweeps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-subdomains", type=int, default=4)
+    return ap.parse_args()
+
+
+def cpu_baseline(grid, wl, n_sub_sample: int):
+    """Time the FP64 CPU oracle on a bounded sample of the same workload:
+    full Alg. 1 (all rounds) on the first `n_sub_sample` subdomains, one
+    OpenMP thread per subdomain. Returns the record for the JSON line."""
+    from oracle import oracle as O
+    S = O.partition(grid)
+    n = min(n_sub_sample, len(S["off"]) - 1)
+    # an interior band of subdomains (row 3 of the 8x8 grid) with all facies
+    first = min(3 * grid.n_sub[0], len(S["off"]) - 1 - n)
+    j0, j1 = S["off"][first], S["off"][first + n]
+    sub = dict(off=S["off"][first:first + n + 1] - j0, x=S["x"][j0:j1], y=S["y"][j0:j1],
+               h=S["h"][j0:j1])
+    D = O.init_dictionary(grid, wl.g, wl.m0 + wl.max_rounds * wl.k_top * (2 ** grid.dim - 1))
+    Ds = O.Dictionary(n, D.m_cap, grid.dim)
+    Ds.m = D.m[first:first + n].copy()
+    Ds.c = D.c[first * D.m_cap * grid.dim:(first + n) * D.m_cap * grid.dim].copy()
+    Ds.sigma = D.sigma[first * D.m_cap:(first + n) * D.m_cap].copy()
+    Ds.level = D.level[first * D.m_cap:(first + n) * D.m_cap].copy()
+    eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    _, _, _, info = O.refine_batch(sub, Ds, wl.lambda1, wl.lambda2, k_top=wl.k_top,
+                                   max_rounds=wl.max_rounds, m_max=1 << 30, eps_tol=eps)
+    dt = time.perf_counter() - t0
+    fits = int(info["rounds"].sum())
+    return {"value": fits / dt, "unit": "subdomain fits/s", "cores": min(threads, n),
+            "kind": "oracle",
+            "sample": f"Alg. 1 with all {wl.max_rounds} enrichment rounds on {n} of "
+                      f"{len(S['off']) - 1} subdomains ({fits} fits, {dt:.1f} s, FP64, "
+                      f"one OpenMP thread per subdomain)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs the hot path on one GPU; --gpus {args.gpus} is not "
+              "supported (see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2605_16564_amd import api, synth
+
+    wl = synth.workload(args.workload)
+    prec = args.precision or wl.precision
+    grid = wl.grids[0]
+    ctx = api.Context(0)
+    dev = torch.device("cuda", 0)
+    cell_y = torch.as_tensor(grid.y, dtype=torch.float64, device=dev)
+    per = 2 ** grid.dim - 1
+    m_cap = wl.m0 + wl.max_rounds * wl.k_top * per
+    pts, wts, cell_of = synth.metric_points(grid, 4 if grid.dim < 3 else 2)
+    xq = torch.as_tensor(pts, dtype=torch.float32, device=dev)
+    w_d = torch.as_tensor(wts, dtype=torch.float64, device=dev)
+    ycell = cell_y[torch.as_tensor(cell_of, device=dev)]
+    Q = xq.shape[0]
+    eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
+    opts = api.EnetOpts(wl.lambda1, wl.lambda2, prec, cd_sweeps=args.cd_sweeps)
+    ropts = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta)
+
+    def step():
+        S = api.partition(ctx, grid, cell_y)
+        D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
+        beta, lvl, rounds, rs, stats = api.refine(ctx, S, D, opts, ropts)
+        out = api.evaluate(ctx, grid, D, beta, xq)
+        return S, D, beta, rounds, rs, stats, out
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tk = ctx.timing_read(reset=True)
+    ctx.timing(False)
+    S, D, beta, rounds, rs, stats, out = res
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    rounds_h = rounds.cpu().numpy()
+    rs_h = rs.cpu().numpy()
+    st = api.stats_to_numpy(stats)
+    fits_step = int(rounds_h.sum())
+    value = fits_step * args.steps / elapsed
+    # field error of the GPU reconstruction (log10 units), metric quadrature
+    area = float(np.prod([grid.hi[a] - grid.lo[a] for a in range(grid.dim)]))
+    l1 = float((w_d * (out.double() - ycell).abs()).sum().item()) / area
+
+    # algorithmic work of the timed steps (per step, from the per-round counts)
+    n_of = np.diff(S.off_host)
+    solve_bytes = float(rs_h[..., 5].sum())
+    gram_flops = 0.0
+    pairs_design = 0.0
+    pairs_ind = 0.0
+    for s in range(D.n_sub):
+        for r in range(int(rounds_h[s])):
+            M = float(rs_h[s, r, 0])
+            gram_flops += float(n_of[s]) * (M + 1.0) * (M + 2.0)   # symmetric (M+1)^2 product
+            pairs_design += 2.0 * n_of[s] * M                      # two exp passes
+            pairs_ind += (2 ** grid.dim) * n_of[s] * M
+    m_final = D.m.cpu().numpy().astype(np.float64)
+    # queries are the metric points (the same count in every cell), so each
+    # subdomain receives its owned cells' share of them
+    owned = np.ones(D.n_sub)
+    ns = list(grid.n_sub[: grid.dim]) + [1] * (3 - grid.dim)
+    s_id = 0
+    for k2 in range(ns[2]):
+        for k1 in range(ns[1]):
+            for k0 in range(ns[0]):
+                kk = (k0, k1, k2)
+                owned[s_id] = np.prod([grid.breaks[a][kk[a] + 1] - grid.breaks[a][kk[a]]
+                                       for a in range(grid.dim)])
+                s_id += 1
+    eval_pairs = float(np.sum(owned / owned.sum() * Q * m_final))
+    per_kernel = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
+                  for k, v in tk.items() if v[1] > 0}
+    dominant = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
+
+    def roofline_for(kind):
+        ms = per_kernel[kind]["ms_per_step"]
+        launches = per_kernel[kind]["launches_per_step"]
+        avg_s = ms / 1e3 / launches
+        if kind == "gram":
+            per_launch = gram_flops / launches
+            ach = per_launch / avg_s / 1e12
+            peak = PEAK_MFMA[prec]
+            return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                    "frac": ach / peak, "traffic": None, "kernel": "k_gram_" + prec}
+        if kind == "eval":
+            # FP32 pair = 7 VALU lane-ops + one quarter-rate exp (4 issue slots)
+            peak_pairs = CU * LANES * CLOCK / 11.0
+            per_launch = eval_pairs / launches
+            ach = per_launch / avg_s
+            return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
+                    "unit": "Tpair/s", "frac": ach / peak_pairs, "traffic": None,
+                    "kernel": "k_eval_chunks<float>"}
+        if kind == "solve":
+            # the active-set iteration streams the Gram rows and the inverse of
+            # the active block; algorithmic bytes counted by the kernel itself
+            per_launch = solve_bytes / launches
+            ach = per_launch / avg_s / 1e9
+            return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                    "kernel": "k_solve<" + ("double" if prec == "f64" else "float") + ">"}
+        if kind == "indicator":
+            # FP64 pair: software exp (about 20 FP64 lane-ops) + 12 others
+            peak_pairs = CU * LANES * CLOCK / 32.0
+            per_launch = pairs_ind / launches
+            ach = per_launch / avg_s
+            return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
+                    "unit": "Tpair/s", "frac": ach / peak_pairs, "traffic": None,
+                    "kernel": "k_indicator"}
+        if kind == "assemble":
+            peak_pairs = CU * LANES * CLOCK / (32.0 if prec == "f64" else 11.0)
+            per_launch = pairs_design / launches
+            ach = per_launch / avg_s
+            return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
+                    "unit": "Tpair/s", "frac": ach / peak_pairs, "traffic": None,
+                    "kernel": "k_assemble"}
+        return None
+
+    roof = roofline_for(dominant) or roofline_for("gram")
+    eval_ms = per_kernel.get("eval", {}).get("ms_per_step", float("nan")) + \
+        per_kernel.get("eval_bin", {}).get("ms_per_step", 0.0)
+    rec = {
+        "metric": "subdomain fits/s",
+        "value": value,
+        "unit": "fits/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_subdomains": int(D.n_sub),
+                   "fits_per_step": fits_step, "initial_centers": int(wl.m0),
+                   "max_rounds": wl.max_rounds, "k_top": wl.k_top, "queries_per_step": int(Q),
+                   "parallelism": "single GPU"},
+        "query_evals_per_s": float(Q) / (eval_ms / 1e3) if eval_ms == eval_ms else None,
+        "field_l1_log10": l1,
+        "kkt_max": float(st["kkt"].max()),
+        "fit_status_ok": bool(np.all(st["status"] == 0)),
+        "centers_final_mean": float(m_final.mean()),
+        "kernels": per_kernel,
+        "dominant_kernel": dominant,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(grid, wl, args.cpu_sample_subdomains)
+    print(json.dumps(rec))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,8 @@ typedef struct {
     int32_t iters;      /* active-set iterations                              */
     int32_t support;    /* number of nonzero coefficients                     */
     double kkt;         /* KKT residual of the returned beta (FP64)           */
+    double stream_bytes; /* bytes of Gram rows and active-block inverse the
+                            solve had to stream (algorithmic traffic)        */
 } pam_fit_stats;
 
 /* a3-a6. For every subdomain: Gaussian RBF design at the samples (Eq.
@@ -182,8 +184,9 @@ typedef struct {
     int32_t space;              /* 0: R_T on log10 values, 1: on 10^values     */
     int32_t *elem_level;        /* [N_tot] times each element was marked (in/out) */
     int32_t *rounds;            /* [n_sub] fits done per subdomain (out) or NULL */
-    double *round_stats;        /* [n_sub*(max_rounds+1)*5] per round
-                                   {M, support, max R_T, marked, sum R_T}, or NULL */
+    double *round_stats;        /* [n_sub*(max_rounds+1)*6] per round
+                                   {M, support, max R_T, marked, sum R_T,
+                                   solve stream bytes}, or NULL                */
 } pam_refine_opts;
 
 /* a3-a9 (Alg. 1): fit, residual indicator R_T (Sec. 2 Step 3, 2-point
@@ -221,6 +224,21 @@ typedef struct {
 pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
                     const pam_dict *dict, const double *beta, int32_t dtype, const void *xq,
                     int64_t Q, void *out, int32_t space, int64_t *n_outside);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (observability). When enabled, every kernel launch of the
+ * context is bracketed by HIP events on the context's stream.
+ * pam_timing_read synchronizes the stream and returns, per kernel kind, the
+ * summed device time in milliseconds and the number of launches since the
+ * last reset; reset = 1 clears the totals afterwards.
+ * ------------------------------------------------------------------------ */
+enum {
+    PAM_TK_GATHER = 0, PAM_TK_LATTICE, PAM_TK_ASSEMBLE, PAM_TK_GRAM, PAM_TK_SOLVE,
+    PAM_TK_INDICATOR, PAM_TK_MARK, PAM_TK_EVAL_BIN, PAM_TK_EVAL, PAM_TK_COUNT
+};
+pam_status pam_timing_enable(pam_ctx *ctx, int32_t on);
+pam_status pam_timing_read(pam_ctx *ctx, double *ms /*[host] PAM_TK_COUNT*/,
+                           int64_t *launches /*[host] PAM_TK_COUNT*/, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,19 @@ class Context:
     def sync(self):
         N.check(N.lib().pam_sync(self.h), "pam_sync")
 
+    def timing(self, on: bool = True):
+        N.check(N.lib().pam_timing_enable(self.h, 1 if on else 0), "pam_timing_enable")
+
+    def timing_read(self, reset: bool = True):
+        """{kernel kind: (total ms, launches)} since the last reset."""
+        k = len(N.TIMING_KINDS)
+        ms = np.zeros(k)
+        cnt = np.zeros(k, np.int64)
+        N.check(N.lib().pam_timing_read(self.h, ms.ctypes.data_as(C.c_void_p),
+                                        cnt.ctypes.data_as(C.c_void_p), 1 if reset else 0),
+                "pam_timing_read")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(N.TIMING_KINDS)}
+
     def close(self):
         if self.h:
             N.lib().pam_destroy(self.h)
@@ -191,7 +204,8 @@ class EnetOpts:
 
 
 STATS_DTYPE = np.dtype([("status", np.int32), ("cd_sweeps", np.int32), ("iters", np.int32),
-                        ("support", np.int32), ("kkt", np.float64)])
+                        ("support", np.int32), ("kkt", np.float64),
+                        ("stream_bytes", np.float64)])
 
 
 def new_stats(n_sub, device):
@@ -232,7 +246,7 @@ class RefineOpts:
 def refine(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, ropts: RefineOpts,
            beta: Optional[torch.Tensor] = None, elem_level: Optional[torch.Tensor] = None):
     """Alg. 1 on every subdomain (D is updated in place).
-    Returns (beta, elem_level, rounds, round_stats [n_sub, R+1, 5], stats)."""
+    Returns (beta, elem_level, rounds, round_stats [n_sub, R+1, 6], stats)."""
     dev = D.m.device
     warm = beta is not None
     if beta is None:
@@ -240,7 +254,7 @@ def refine(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, ropts: Refin
     if elem_level is None:
         elem_level = torch.zeros(int(S.off_host[-1]), dtype=torch.int32, device=dev)
     rounds = torch.zeros(D.n_sub, dtype=torch.int32, device=dev)
-    rstats = torch.zeros((D.n_sub, ropts.max_rounds + 1, 5), dtype=torch.float64, device=dev)
+    rstats = torch.zeros((D.n_sub, ropts.max_rounds + 1, 6), dtype=torch.float64, device=dev)
     stats = new_stats(D.n_sub, dev)
     r = N.PamRefineOpts()
     r.k_top = int(ropts.k_top)

@@ -14,7 +14,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "_build" / "libpam.so"
-SOURCES = ["pam_api.hip", "k_setup.hip", "k_fit.hip", "k_refine.hip", "k_eval.hip"]
+SOURCES = ["pam_api.hip", "k_setup.hip", "k_fit.hip", "k_solve.hip", "k_refine.hip", "k_eval.hip"]
 ARCH = os.environ.get("PAM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -36,25 +36,27 @@ def _run(cmd):
         raise subprocess.CalledProcessError(p.returncode, cmd)
 
 
-def build(verbose: bool = False) -> Path:
+def build(verbose: bool = False, out: Path = OUT, defines=()) -> Path:
     """Compile all sources (always; callers decide whether to rebuild)."""
-    OUT.parent.mkdir(parents=True, exist_ok=True)
+    out = Path(out)
+    out.parent.mkdir(parents=True, exist_ok=True)
     objs = []
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-I", str(ROOT / "include"), "-I", str(CSRC), "-Wall", "-Wno-unused-function"]
+             "-I", str(ROOT / "include"), "-I", str(CSRC), "-Wall", "-Wno-unused-function",
+             *[f"-D{d}" for d in defines]]
     for src in SOURCES:
-        obj = OUT.parent / (Path(src).stem + ".o")
+        obj = out.parent / (Path(src).stem + ".o")
         cmd = [hipcc(), *flags, "-c", str(CSRC / src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
         _run(cmd)
         objs.append(str(obj))
-    tmp = OUT.with_suffix(".so.tmp")
+    tmp = out.with_suffix(".so.tmp")
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", str(tmp), *objs]
     _run(cmd)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

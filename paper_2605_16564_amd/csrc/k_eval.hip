@@ -277,6 +277,8 @@ pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, cons
     int64_t *chstart = (int64_t *)(w + o_chstart);
     int32_t *chlen = (int32_t *)(w + o_chlen);
     const int grid_q = (int)std::min<int64_t>((Q + kE - 1) / kE, 65536);
+    {
+    KernelTimer kt_bin(ctx, PAM_TK_EVAL_BIN);
     if (Q > 0) {
         if (dtype == 0)
             hipLaunchKernelGGL((k_owner<float>), dim3(grid_q), dim3(kE), 0, ctx->stream, t,
@@ -299,6 +301,8 @@ pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, cons
     hipLaunchKernelGGL(k_chunks, dim3((n_sub_total + kE - 1) / kE), dim3(kE), 0, ctx->stream,
                        n_sub_total, hist, base, cbase, chsub, chstart, chlen);
     PAM_CHECK_HIP(hipGetLastError());
+    }
+    KernelTimer kt_eval(ctx, PAM_TK_EVAL);
     if (Q > 0) {
         if (dtype == 0)
             hipLaunchKernelGGL((k_eval_chunks<float>), dim3((unsigned)max_chunks), dim3(kE), 0,

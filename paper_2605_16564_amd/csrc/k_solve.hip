@@ -1,0 +1,817 @@
+// Elastic-net solve for every subdomain (gfx950): the unique minimizer of
+//   1/2 ||y - W beta||^2 + lambda1 ||beta||_1 + lambda2/2 ||beta||^2
+// (Eq. elastic) from the normal products G = W'W, b = W'y (Sec. 3.3: the
+// problem is convex and coordinate descent reaches its minimizer).
+//
+// One block (four waves) per subdomain:
+//  1. cyclic coordinate descent sweeps in creation order (warm-up);
+//  2. exact sign-consistent active-set iteration (feature-sign search):
+//     solve (G_SS + lambda2 I) beta_S = b_S - lambda1 theta_S on the signed
+//     active set, discrete line search over the zero crossings, activation of
+//     the worst KKT violators; the inverse H of the active block is kept in
+//     HBM/L2 and updated by (blocked) bordering when coordinates enter and by
+//     a Schur downdate when they leave;
+//  3. residual refinement of the reduced system and a KKT certificate in FP64.
+// All vectors of the iteration live in LDS; only H and the Gram rows stream
+// from memory, in coalesced row order.
+#include <float.h>
+
+#include "pam_internal.h"
+
+#ifdef PAM_PHASE_PROFILE
+#define PHASE_MARK(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); ph[k] += _t - ph_last; ph_last = _t; } } while (0)
+#else
+#define PHASE_MARK(k) do { } while (0)
+#endif
+
+namespace pam {
+
+static constexpr int kT = 512;
+static constexpr int kW = kT / 64;
+static constexpr int kB = 8;       // coordinates activated per blocked bordering step
+static constexpr int kR = 1;       // GEMV outputs per thread per pass
+static constexpr int kTile = 128;  // rows staged in LDS per bordering tile
+static constexpr int kPass = kR * kT;
+
+__host__ __device__ size_t solve_ldh(int m_cap) { return (size_t)round_up(m_cap, kPass); }
+__host__ __device__ size_t solve_h_elems(int m_cap) { return (size_t)(m_cap + 1) * solve_ldh(m_cap); }
+__host__ __device__ size_t solve_scratch_elems(int m_cap) { return (size_t)3 * kB * m_cap; }
+size_t solve_lds_bytes(int m_cap) { return (size_t)49 * round_up(m_cap, 8) + 64; }
+
+// ---------------------------------------------------------------- reductions
+struct Red {
+    double v[kW * kB];
+    int i[kW];
+    int flag;
+    int count;
+};
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double bsum(double v, Red &r) {
+    v = wsum(v);
+    if ((threadIdx.x & 63) == 0) r.v[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kW; ++w) t += r.v[w];
+    __syncthreads();
+    return t;
+}
+
+template <int K>
+__device__ __forceinline__ void bsum_vec(double (&v)[K], Red &r) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double x = wsum(v[k]);
+        if ((threadIdx.x & 63) == 0) r.v[(threadIdx.x >> 6) * K + k] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kW; ++w) t += r.v[w * K + k];
+        v[k] = t;
+    }
+    __syncthreads();
+}
+
+struct VI { double v; int i; };
+__device__ __forceinline__ VI vmax(VI a, VI b) {
+    if (b.i < 0) return a;
+    if (a.i < 0) return b;
+    if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
+    return a;
+}
+__device__ __forceinline__ VI bargmax(VI x, Red &r) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        VI y;
+        y.v = __shfl_xor(x.v, o, 64);
+        y.i = __shfl_xor(x.i, o, 64);
+        x = vmax(x, y);
+    }
+    if ((threadIdx.x & 63) == 0) { r.v[threadIdx.x >> 6] = x.v; r.i[threadIdx.x >> 6] = x.i; }
+    __syncthreads();
+    VI t; t.v = -1.0; t.i = -1;
+#pragma unroll
+    for (int w = 0; w < kW; ++w) { VI y; y.v = r.v[w]; y.i = r.i[w]; t = vmax(t, y); }
+    __syncthreads();
+    return t;
+}
+__device__ __forceinline__ double bmax(double v, Red &r) {
+    VI x; x.v = v; x.i = threadIdx.x;
+    return bargmax(x, r).v;
+}
+// AND over the block of a per-thread predicate.
+__device__ __forceinline__ bool ball(bool p, Red &r) {
+    if (threadIdx.x == 0) r.flag = 1;
+    __syncthreads();
+    if (!p) r.flag = 0;
+    __syncthreads();
+    const bool res = r.flag != 0;
+    __syncthreads();
+    return res;
+}
+
+__device__ __forceinline__ double sgn(double v) { return v > 0.0 ? 1.0 : (v < 0.0 ? -1.0 : 0.0); }
+
+// ---------------------------------------------------------------- state
+template <typename TG>
+struct Sv {
+    const TG *G;           // Gram [mpad][mpad]; column M holds b
+    int mpad, M, m_cap;
+    size_t ldh;
+    double l1, l2;
+    double *H;             // [m_cap+1][ldh] inverse of the active block
+    double *Ag, *U, *V;    // [kB][m_cap] scratch for blocked bordering
+    double *g, *beta;      // LDS, by coordinate
+    double *z, *rhs, *u;   // LDS, by active position
+    int *S, *pos;          // LDS
+    signed char *th;       // LDS
+    int s;                 // active-set size (uniform)
+    double bytes;          // algorithmic bytes streamed (Gram rows, H)
+};
+
+template <typename TG>
+__device__ __forceinline__ double Gat(const Sv<TG> &v, int i, int j) {
+    return (double)v.G[(size_t)i * v.mpad + j];
+}
+
+// out_i = sum_j H[j][i] in_j, i < s (H symmetric; rows streamed coalesced,
+// four rows in flight per thread).
+template <typename TG>
+__device__ void hgemv(const Sv<TG> &v, const double *in, double *out) {
+    constexpr int kQ = 16;   // rows loaded before use
+    const int s = v.s;
+    const_cast<Sv<TG> &>(v).bytes += 8.0 * (double)s * (double)s;
+    for (int base = 0; base < s; base += kPass) {
+        double acc = 0.0;
+        const double *Hc = v.H + base + threadIdx.x;
+        int jj = 0;
+        for (; jj + kQ <= s; jj += kQ) {
+            double h[kQ];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) h[q] = Hc[(size_t)(jj + q) * v.ldh];
+#pragma unroll
+            for (int q = 0; q < kQ; ++q) acc += h[q] * in[jj + q];
+        }
+        for (; jj < s; ++jj) acc += Hc[(size_t)jj * v.ldh] * in[jj];
+        const int i = base + threadIdx.x;
+        if (i < s) out[i] = acc;
+    }
+    __syncthreads();
+}
+
+// Blocked bordering: append the nb (<= kB) coordinates ks[] to the active
+// set. With A_SB = G[S, B], U = H A_SB, C = A_BB + lambda2 I - A_SB' U,
+//   H <- [[H + U C^-1 U', -U C^-1], [-C^-1 U', C^-1]].
+// Returns false (set unchanged) if C is not numerically positive definite.
+// Rows of A_SB and of V = U C^-1 are staged through LDS in tiles so that
+// the streaming passes over H read them as broadcasts.
+template <typename TG>
+__device__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile) {
+    const int s = v.s;
+    v.bytes += 24.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
+    for (int q = 0; q < nb; ++q)
+        for (int i = threadIdx.x; i < s; i += kT) v.Ag[(size_t)q * v.m_cap + i] = Gat(v, ks[q], v.S[i]);
+    __syncthreads();
+    // U = H A_SB: one pass over H for all nb columns
+    for (int base = 0; base < s; base += kPass) {
+        double acc[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) acc[q] = 0.0;
+        const double *Hc = v.H + base + threadIdx.x;
+        for (int t0 = 0; t0 < s; t0 += kTile) {
+            const int tn = min(kTile, s - t0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < kB * kTile; e += kT) {
+                const int q = e / kTile, r = e - q * kTile;
+                tile[e] = (q < nb && r < tn) ? v.Ag[(size_t)q * v.m_cap + t0 + r] : 0.0;
+            }
+            __syncthreads();
+            int r = 0;
+            for (; r + 8 <= tn; r += 8) {
+                double h[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[e] = Hc[(size_t)(t0 + r + e) * v.ldh];
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int q = 0; q < kB; ++q) acc[q] += h[e] * tile[q * kTile + r + e];
+            }
+            for (; r < tn; ++r) {
+                const double h0 = Hc[(size_t)(t0 + r) * v.ldh];
+#pragma unroll
+                for (int q = 0; q < kB; ++q) acc[q] += h0 * tile[q * kTile + r];
+            }
+        }
+        const int i = base + threadIdx.x;
+        if (i < s)
+            for (int q = 0; q < nb; ++q) v.U[(size_t)q * v.m_cap + i] = acc[q];
+    }
+    __syncthreads();
+    // C = A_BB + lambda2 I - A_SB' U: 16 threads per (p, q) pair
+    for (int pair0 = 0; pair0 < kB * kB; pair0 += kT / 16) {
+        const int pair = pair0 + (threadIdx.x >> 4), l16 = threadIdx.x & 15;
+        const int p = pair / kB, q = pair % kB;
+        double acc = 0.0;
+        if (pair < kB * kB && p < nb && q < nb)
+            for (int i = l16; i < s; i += 16) acc += v.Ag[(size_t)p * v.m_cap + i] * v.U[(size_t)q * v.m_cap + i];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+        if (l16 == 0 && pair < kB * kB) tile[pair] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // small Cholesky inverse in LDS (cinv holds L, then the inverse);
+        // tile[0 .. kB*kB) holds A_SB' U, tile[kB*kB .. 2*kB*kB) is scratch
+        double *L = cinv, *Li = tile + kB * kB;
+        int ok = 1;
+        for (int p = 0; p < nb && ok; ++p)
+            for (int q = 0; q <= p; ++q) {
+                double val = Gat(v, ks[p], ks[q]) - tile[p * kB + q];
+                if (p == q) val += v.l2;
+                for (int k = 0; k < q; ++k) val -= L[p * kB + k] * L[q * kB + k];
+                if (p == q) {
+                    const double dref = Gat(v, ks[p], ks[p]) + v.l2;
+                    if (!(val > 1e-14 * dref)) { ok = 0; break; }
+                    L[p * kB + p] = sqrt(val);
+                } else {
+                    L[p * kB + q] = val / L[q * kB + q];
+                }
+            }
+        if (ok) {
+            for (int q = 0; q < nb; ++q)
+                for (int p = 0; p < nb; ++p) {
+                    double val = p == q ? 1.0 : 0.0;
+                    for (int k = q; k < p; ++k) val -= L[p * kB + k] * Li[k * kB + q];
+                    Li[p * kB + q] = p < q ? 0.0 : val / L[p * kB + p];
+                }
+            for (int p = 0; p < nb; ++p)
+                for (int q = 0; q < nb; ++q) {
+                    double val = 0.0;
+                    for (int k = max(p, q); k < nb; ++k) val += Li[k * kB + p] * Li[k * kB + q];
+                    cinv[p * kB + q] = val;   // L no longer needed below the diagonal pass
+                }
+        }
+        red.flag = ok;
+    }
+    __syncthreads();
+    const bool ok = red.flag != 0;
+    __syncthreads();
+    if (!ok) return false;
+    // V = U C^-1
+    for (int i = threadIdx.x; i < s; i += kT) {
+        double uu[kB];
+#pragma unroll
+        for (int p = 0; p < kB; ++p) uu[p] = p < nb ? v.U[(size_t)p * v.m_cap + i] : 0.0;
+        for (int q = 0; q < nb; ++q) {
+            double val = 0.0;
+#pragma unroll
+            for (int p = 0; p < kB; ++p) val += uu[p] * (p < nb ? cinv[p * kB + q] : 0.0);
+            v.V[(size_t)q * v.m_cap + i] = val;
+        }
+    }
+    __syncthreads();
+    // H[i][j] += sum_q V[q][i] U[q][j] over the old block (V rows staged in LDS)
+    for (int jb = 0; jb < s; jb += kT) {
+        const int j = jb + threadIdx.x;
+        const bool live = j < s;
+        double uj[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) uj[q] = (live && q < nb) ? v.U[(size_t)q * v.m_cap + j] : 0.0;
+        double *Hc = v.H + j;
+        for (int t0 = 0; t0 < s; t0 += kTile) {
+            const int tn = min(kTile, s - t0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < kB * kTile; e += kT) {
+                const int q = e / kTile, r = e - q * kTile;
+                tile[e] = (q < nb && r < tn) ? v.V[(size_t)q * v.m_cap + t0 + r] : 0.0;
+            }
+            __syncthreads();
+            if (!live) continue;
+            int r = 0;
+            for (; r + 8 <= tn; r += 8) {
+                double *h = Hc + (size_t)(t0 + r) * v.ldh;
+                double hv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) hv[e] = h[(size_t)e * v.ldh];
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int q = 0; q < kB; ++q) hv[e] += tile[q * kTile + r + e] * uj[q];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[(size_t)e * v.ldh] = hv[e];
+            }
+            for (; r < tn; ++r) {
+                double *h = Hc + (size_t)(t0 + r) * v.ldh;
+                double h0 = h[0];
+#pragma unroll
+                for (int q = 0; q < kB; ++q) h0 += tile[q * kTile + r] * uj[q];
+                h[0] = h0;
+            }
+        }
+        if (live)
+            for (int q = 0; q < nb; ++q) {
+                const double val = -v.V[(size_t)q * v.m_cap + j];
+                v.H[(size_t)(s + q) * v.ldh + j] = val;
+                v.H[(size_t)j * v.ldh + s + q] = val;
+            }
+    }
+    if (threadIdx.x < nb * nb) {
+        const int p = threadIdx.x / nb, q = threadIdx.x % nb;
+        v.H[(size_t)(s + p) * v.ldh + s + q] = cinv[p * kB + q];
+    }
+    if (threadIdx.x < nb) {
+        v.S[s + threadIdx.x] = ks[threadIdx.x];
+        v.pos[ks[threadIdx.x]] = s + threadIdx.x;
+    }
+    __syncthreads();
+    v.s = s + nb;
+    return true;
+}
+
+// Remove active position p: H <- H_{-p,-p} - h h' / H_pp (h = H[-p, p]),
+// then the last position moves into p.
+template <typename TG>
+__device__ void remove_at(Sv<TG> &v, int p) {
+    const int s = v.s;
+    v.bytes += 16.0 * (double)s * (double)s;
+    const double hp = v.H[(size_t)p * v.ldh + p];
+    for (int i = threadIdx.x; i < s; i += kT) v.u[i] = v.H[(size_t)i * v.ldh + p];
+    __syncthreads();
+    const double ih = 1.0 / hp;
+    // row p and column p are left stale: they are overwritten by the move
+    // below or fall outside the shrunken block.
+    for (int j = threadIdx.x; j < s; j += kT) {
+        const double uj = v.u[j] * ih;
+        double *Hc = v.H + j;
+        int i = 0;
+        for (; i + 16 <= s; i += 16) {
+            double *h = Hc + (size_t)i * v.ldh;
+            double hv[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) hv[e] = h[(size_t)e * v.ldh];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) h[(size_t)e * v.ldh] = hv[e] - v.u[i + e] * uj;
+        }
+        for (; i < s; ++i) Hc[(size_t)i * v.ldh] -= v.u[i] * uj;
+    }
+    __syncthreads();
+    const int last = s - 1;
+    const int kp = v.S[p];
+    if (p != last) {
+        for (int j = threadIdx.x; j < last; j += kT) {
+            if (j == p) continue;
+            const double val = v.H[(size_t)last * v.ldh + j];
+            v.H[(size_t)p * v.ldh + j] = val;
+            v.H[(size_t)j * v.ldh + p] = val;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            v.H[(size_t)p * v.ldh + p] = v.H[(size_t)last * v.ldh + last];
+            const int kl = v.S[last];
+            v.S[p] = kl;
+            v.pos[kl] = p;
+        }
+    }
+    if (threadIdx.x == 0) v.pos[kp] = -1;
+    __syncthreads();
+    v.s = s - 1;
+}
+
+// g = b - G beta - lambda2 beta over all coordinates (rows of the active set).
+template <typename TG>
+__device__ void full_gradient(Sv<TG> &v) {
+    const int s = v.s;
+    v.bytes += (double)s * v.M * sizeof(TG);
+    for (int m = threadIdx.x; m < v.M; m += kT) {
+        double acc = Gat(v, m, v.M) - v.l2 * v.beta[m];
+        int i = 0;
+        for (; i + 8 <= s; i += 8) {
+            double gv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) gv[e] = (double)v.G[(size_t)v.S[i + e] * v.mpad + m];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc -= gv[e] * v.beta[v.S[i + e]];
+        }
+        for (; i < s; ++i) {
+            const int k = v.S[i];
+            acc -= (double)v.G[(size_t)k * v.mpad + m] * v.beta[k];
+        }
+        v.g[m] = acc;
+    }
+    __syncthreads();
+}
+
+// Activate the listed coordinates (blocked; single fallback on failure).
+// Coordinates that cannot enter are deactivated. Returns false if none of a
+// requested set could enter.
+template <typename TG>
+__device__ bool activate(Sv<TG> &v, int *list, int n, Red &red, double *cinv, int *blk, double *tile) {
+    bool any = false;
+    for (int b0 = 0; b0 < n; b0 += kB) {
+        const int nb = min(kB, n - b0);
+        if (threadIdx.x < nb) blk[threadIdx.x] = list[b0 + threadIdx.x];
+        __syncthreads();
+        if (add_block(v, blk, nb, red, cinv, tile)) {
+            any = true;
+            continue;
+        }
+        for (int q = 0; q < nb; ++q) {
+            const int k = list[b0 + q];
+            if (threadIdx.x == 0) blk[0] = k;
+            __syncthreads();
+            if (add_block(v, blk, 1, red, cinv, tile)) {
+                any = true;
+            } else if (threadIdx.x == 0) {
+                v.th[k] = 0;
+                v.beta[k] = 0.0;
+            }
+            __syncthreads();
+        }
+    }
+    return any;
+}
+
+template <typename TG>
+__global__ void __launch_bounds__(kT)
+k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
+        double *__restrict__ scratch, const int32_t *__restrict__ flags) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    __shared__ Red red;
+    __shared__ double cinv[kB * kB];
+    __shared__ int blk[kB];
+    __shared__ int list[kB];
+    __shared__ double tile[kB * kTile];
+    const int s_id = a.sub_begin + blockIdx.x;
+    if (a.active && !a.active[s_id]) return;
+    const int loc = s_id - a.sub_begin;
+    Sv<TG> v;
+    v.G = Gall + (size_t)loc * a.mpad * a.mpad;
+    v.mpad = a.mpad;
+    v.M = max(0, min(a.m[s_id], a.m_cap));
+    v.m_cap = a.m_cap;
+    v.ldh = solve_ldh(a.m_cap);
+    v.l1 = a.lambda1_sub ? a.lambda1_sub[s_id] : a.lambda1;
+    v.l2 = a.lambda2_sub ? a.lambda2_sub[s_id] : a.lambda2;
+    v.H = Hall + (size_t)loc * solve_h_elems(a.m_cap);
+    double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap);
+    v.Ag = sc;
+    v.U = sc + (size_t)kB * a.m_cap;
+    v.V = sc + (size_t)2 * kB * a.m_cap;
+    const int Mc = (int)round_up(a.m_cap, 8);
+    double *ld = reinterpret_cast<double *>(lds_raw);
+    v.g = ld;
+    v.beta = ld + Mc;
+    v.z = ld + 2 * Mc;
+    v.rhs = ld + 3 * Mc;
+    v.u = ld + 4 * Mc;
+    v.S = reinterpret_cast<int *>(ld + 5 * Mc);
+    v.pos = v.S + Mc;
+    v.th = reinterpret_cast<signed char *>(v.pos + Mc);
+    v.s = 0;
+    v.bytes = 0.0;
+    const int M = v.M;
+#ifdef PAM_PHASE_PROFILE
+    long long ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    long long ph_last = wall_clock64();
+    int n_rm = 0, n_add = 0, n_ls = 0, n_cons = 0;
+#endif
+    double *beta_out = a.beta + (size_t)s_id * a.m_cap;
+    pam_fit_stats *st = a.stats ? a.stats + s_id : nullptr;
+
+    if ((flags[s_id] & 1) || M <= 0 || a.off[s_id + 1] <= a.off[s_id]) {
+        for (int m = threadIdx.x; m < a.m_cap; m += kT) beta_out[m] = 0.0;
+        if (st && threadIdx.x == 0) {
+            st->status = (flags[s_id] & 1) ? PAM_ST_UNDERFLOW : PAM_ST_EMPTY;
+            st->cd_sweeps = 0; st->iters = 0; st->support = 0; st->kkt = 0.0;
+            st->stream_bytes = 0.0;
+        }
+        return;
+    }
+    // ---- start point and gradient
+    for (int m = threadIdx.x; m < M; m += kT) {
+        v.beta[m] = a.warm_start ? beta_out[m] : 0.0;
+        v.pos[m] = -1;
+        v.g[m] = Gat(v, m, M);
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < M; m += kT) v.g[m] -= v.l2 * v.beta[m];
+    if (a.warm_start) {
+        for (int k = 0; k < M; ++k) {
+            const double bk = v.beta[k];
+            if (bk == 0.0) continue;
+            for (int m = threadIdx.x; m < M; m += kT) v.g[m] -= (double)v.G[(size_t)k * v.mpad + m] * bk;
+        }
+    }
+    __syncthreads();
+    PHASE_MARK(0);
+    // ---- cyclic coordinate descent warm-up, creation order
+    int sweeps = 0;
+    // warm starts (previous round, caller's point) go straight to the
+    // active-set iteration: CD from a good point only densifies the support
+    const int cd_sweeps = a.warm_start ? 0 : a.cd_sweeps;
+    for (; sweeps < cd_sweeps; ++sweeps) {
+        double dmax = 0.0;
+        for (int m = 0; m < M; ++m) {
+            const double amm = Gat(v, m, m) + v.l2;
+            const double bm = v.beta[m];
+            const double zz = v.g[m] + amm * bm;
+            const double az = fabs(zz) - v.l1;
+            const double nb = az > 0.0 ? sgn(zz) * az / amm : 0.0;
+            const double d = nb - bm;
+            if (d != 0.0) {
+                dmax = fmax(dmax, fabs(d));
+                v.bytes += (double)M * sizeof(TG);
+                __syncthreads();
+                for (int k = threadIdx.x; k < M; k += kT) v.g[k] -= (double)v.G[(size_t)m * v.mpad + k] * d;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    v.g[m] -= v.l2 * d;
+                    v.beta[m] = nb;
+                }
+                __syncthreads();
+            }
+        }
+        if (dmax == 0.0) { ++sweeps; break; }
+    }
+    PHASE_MARK(1);
+    // ---- signed active set from the start point (and the support hint)
+    const uint8_t *hint = a.hint ? a.hint + (size_t)s_id * a.m_cap : nullptr;
+    for (int m = threadIdx.x; m < M; m += kT) {
+        int t = (int)sgn(v.beta[m]);
+        if (t == 0 && hint && hint[m]) t = (int)sgn(v.g[m]);
+        v.th[m] = (signed char)t;
+    }
+    __syncthreads();
+    // initial active block, ascending coordinate order, kB at a time
+    for (int m0 = 0; m0 < M; m0 += kT) {
+        const int m = m0 + threadIdx.x;
+        const bool on = m < M && v.th[m] != 0;
+        // compact this chunk in order with a block scan of the flags
+        const unsigned long long bal = __ballot(on);
+        const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) red.i[wid] = __popcll(bal);
+        __syncthreads();
+        int wbase = 0, tot = 0;
+        for (int w = 0; w < kW; ++w) {
+            if (w < wid) wbase += red.i[w];
+            tot += red.i[w];
+        }
+        __syncthreads();
+        if (on) v.rhs[wbase + pre] = (double)m;   // rhs is free here
+        __syncthreads();
+        for (int b0 = 0; b0 < tot; b0 += kB) {
+            const int nb = min(kB, tot - b0);
+            if (threadIdx.x < nb) list[threadIdx.x] = (int)v.rhs[b0 + threadIdx.x];
+            __syncthreads();
+            activate(v, list, nb, red, cinv, blk, tile);
+            __syncthreads();
+        }
+    }
+    for (int m = threadIdx.x; m < M; m += kT)
+        if (v.th[m] == 0) v.beta[m] = 0.0;
+    __syncthreads();
+    full_gradient(v);
+    PHASE_MARK(2);
+#ifdef PAM_PHASE_PROFILE
+    const int s_init = v.s;
+#endif
+
+    // ---- exact sign-consistent active-set iteration
+    const double bnorm = bmax([&] {
+        double t = 0.0;
+        for (int m = threadIdx.x; m < M; m += kT) t = fmax(t, fabs(Gat(v, m, M)));
+        return t;
+    }(), red);
+    const double viol_tol = v.l1 * (1.0 + 1e-12) + 1e-14 * bnorm;
+    int it = 0, status = PAM_ST_NOCONV, refines = 0;
+    bool skip_solve = false;
+    while (it < a.max_iter) {
+        ++it;
+        if (v.s > 0 && !skip_solve) {
+            const int s = v.s;
+            for (int i = threadIdx.x; i < s; i += kT) {
+                const int k = v.S[i];
+                v.rhs[i] = Gat(v, k, M) - v.l1 * (double)v.th[k];
+            }
+            __syncthreads();
+            hgemv(v, v.rhs, v.z);
+            PHASE_MARK(3);
+            bool mine = true;
+            for (int i = threadIdx.x; i < s; i += kT)
+                if ((int)sgn(v.z[i]) != v.th[v.S[i]]) mine = false;
+            if (!ball(mine, red)) {
+                // discrete line search from beta_S to z over the zero crossings
+                double p1 = 0.0, p2 = 0.0, p3 = 0.0;
+                for (int i = threadIdx.x; i < s; i += kT) {
+                    const int k = v.S[i];
+                    const double b0 = v.beta[k], d = v.z[i] - b0;
+                    p1 -= v.g[k] * d;
+                    p2 += d * (v.g[k] - v.l1 * (double)v.th[k]);
+                    p3 += fabs(v.z[i]) - fabs(b0);
+                }
+                double cc[3] = {p1, p2, p3};
+                bsum_vec<3>(cc, red);
+                const double c1 = cc[0], c2 = cc[1];
+                double best_f = c1 + 0.5 * c2 + v.l1 * cc[2];   // t = 1
+                double best_t = 1.0;
+                // candidates in position order: compacted with a block scan
+                for (int c0 = 0; c0 < s; c0 += kT) {
+                    const int i = c0 + threadIdx.x;
+                    double t = 2.0;
+                    if (i < s) {
+                        const double b0 = v.beta[v.S[i]], zi = v.z[i];
+                        if (b0 != 0.0 && sgn(zi) != sgn(b0)) {
+                            const double tt = b0 / (b0 - zi);
+                            if (tt > 0.0 && tt < 1.0) t = tt;
+                        }
+                    }
+                    const bool is_c = t < 1.0;
+                    const unsigned long long bal = __ballot(is_c);
+                    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+                    if (lane == 0) red.i[wid] = __popcll(bal);
+                    __syncthreads();
+                    int wbase = 0, tot = 0;
+                    for (int w = 0; w < kW; ++w) {
+                        if (w < wid) wbase += red.i[w];
+                        tot += red.i[w];
+                    }
+                    __syncthreads();
+                    if (is_c) v.u[wbase + pre] = t;      // u is free here
+                    __syncthreads();
+                    for (int q0 = 0; q0 < tot; q0 += kB) {
+                        const int nq = min(kB, tot - q0);
+                        double tq[kB], f[kB];
+#pragma unroll
+                        for (int q = 0; q < kB; ++q) {
+                            tq[q] = q < nq ? v.u[q0 + q] : 0.0;
+                            f[q] = 0.0;
+                        }
+                        for (int jq = threadIdx.x; jq < s; jq += kT) {
+                            const double b0 = v.beta[v.S[jq]], d = v.z[jq] - b0;
+                            const double ab0 = fabs(b0);
+#pragma unroll
+                            for (int q = 0; q < kB; ++q) f[q] += fabs(b0 + tq[q] * d) - ab0;
+                        }
+                        bsum_vec<kB>(f, red);
+                        for (int q = 0; q < nq; ++q) {
+                            const double fq = tq[q] * c1 + 0.5 * tq[q] * tq[q] * c2 + v.l1 * f[q];
+                            if (fq < best_f) { best_f = fq; best_t = tq[q]; }
+                        }
+                    }
+                }
+                const double tstar = best_t;
+                PHASE_MARK(4);
+                for (int i = threadIdx.x; i < s; i += kT) {
+                    const int k = v.S[i];
+                    const double b0 = v.beta[k], zi = v.z[i];
+                    double nb = b0 + tstar * (zi - b0);
+                    if (tstar < 1.0 && b0 != 0.0 && sgn(zi) != sgn(b0) && b0 / (b0 - zi) == tstar) nb = 0.0;
+                    v.g[k] -= tstar * (v.g[k] - v.l1 * (double)v.th[k]);
+                    v.beta[k] = nb;
+                    v.th[k] = (signed char)sgn(nb);
+                }
+                __syncthreads();
+                for (int p = v.s - 1; p >= 0; --p)
+                    if (v.th[v.S[p]] == 0) {
+                        remove_at(v, p);
+#ifdef PAM_PHASE_PROFILE
+                        ++n_rm;
+#endif
+                    }
+                PHASE_MARK(5);
+#ifdef PAM_PHASE_PROFILE
+                ++n_ls;
+#endif
+                continue;
+            }
+            for (int i = threadIdx.x; i < s; i += kT) v.beta[v.S[i]] = v.z[i];
+            __syncthreads();
+        }
+        skip_solve = false;
+        full_gradient(v);
+        PHASE_MARK(6);
+#ifdef PAM_PHASE_PROFILE
+        ++n_cons;
+#endif
+        // worst inactive violations (up to kB, by |g| then index)
+        int nadd = 0;
+        for (int q = 0; q < kB; ++q) {
+            VI x; x.v = -1.0; x.i = -1;
+            for (int m = threadIdx.x; m < M; m += kT) {
+                if (v.pos[m] >= 0) continue;
+                bool taken = false;
+                for (int e = 0; e < nadd; ++e) taken |= list[e] == m;
+                if (taken) continue;
+                VI c; c.v = fabs(v.g[m]); c.i = m;
+                x = vmax(x, c);
+            }
+            x = bargmax(x, red);
+            if (x.i < 0 || x.v <= viol_tol) break;
+            if (threadIdx.x == 0) {
+                list[nadd] = x.i;
+                v.th[x.i] = (signed char)sgn(v.g[x.i]);
+            }
+            __syncthreads();
+            ++nadd;
+            // after many iterations fall back to one activation per step
+            if (it > 4 * M) break;
+        }
+        if (nadd > 0) {
+#ifdef PAM_PHASE_PROFILE
+            n_add += nadd;
+#endif
+            if (!activate(v, list, nadd, red, cinv, blk, tile)) break;
+            PHASE_MARK(7);
+            continue;
+        }
+        // optimal up to the reduced-system residual r_S = g_S - lambda1 theta_S
+        const int s = v.s;
+        double rp = 0.0;
+        for (int i = threadIdx.x; i < s; i += kT) {
+            const int k = v.S[i];
+            v.rhs[i] = v.g[k] - v.l1 * (double)v.th[k];
+            rp = fmax(rp, fabs(v.rhs[i]));
+        }
+        const double rmax = bmax(rp, red);
+        if (s == 0 || rmax <= 1e-15 * fmax(1.0, bnorm) || refines >= 3) {
+            status = PAM_ST_OK;
+            break;
+        }
+        ++refines;
+        hgemv(v, v.rhs, v.z);   // correction H r
+        bool keep_mine = true;
+        for (int i = threadIdx.x; i < s; i += kT) {
+            const int k = v.S[i];
+            if ((int)sgn(v.beta[k] + v.z[i]) != v.th[k]) keep_mine = false;
+        }
+        if (ball(keep_mine, red)) {
+            for (int i = threadIdx.x; i < s; i += kT) v.beta[v.S[i]] += v.z[i];
+            __syncthreads();
+            skip_solve = true;
+        }
+    }
+    // ---- outputs and KKT residual
+    __syncthreads();
+    full_gradient(v);
+    double kk = 0.0, nz = 0.0;
+    for (int m = threadIdx.x; m < M; m += kT) {
+        const double b = v.beta[m];
+        const double e = b != 0.0 ? fabs(v.g[m] - v.l1 * sgn(b)) : fmax(fabs(v.g[m]) - v.l1, 0.0);
+        kk = fmax(kk, e);
+        nz += b != 0.0 ? 1.0 : 0.0;
+    }
+    const double kkt = bmax(kk, red);
+    const double nzs = bsum(nz, red);
+    for (int m = threadIdx.x; m < a.m_cap; m += kT) beta_out[m] = m < M ? v.beta[m] : 0.0;
+#ifdef PAM_PHASE_PROFILE
+    if (threadIdx.x == 0)
+        printf("PH sub=%d M=%d s_init=%d s=%d it=%d cons=%d ls=%d rm=%d add=%d sweeps=%d us: grad0=%.0f cd=%.0f init=%.0f solve=%.0f ls=%.0f rm=%.0f fullg=%.0f act=%.0f\n",
+               s_id, M, s_init, v.s, it, n_cons, n_ls, n_rm, n_add, sweeps, ph[0] * 0.01, ph[1] * 0.01,
+               ph[2] * 0.01, ph[3] * 0.01, ph[4] * 0.01, ph[5] * 0.01, ph[6] * 0.01, ph[7] * 0.01);
+#endif
+    if (st && threadIdx.x == 0) {
+        st->status = status;
+        st->cd_sweeps = sweeps;
+        st->iters = it;
+        st->support = (int)nzs;
+        st->kkt = kkt;
+        st->stream_bytes = v.bytes;
+    }
+}
+
+pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
+    const size_t lds = solve_lds_bytes(a.m_cap);
+    if (lds > 150 * 1024) {
+        set_error("m_cap too large for the LDS-resident solve (max 3100)");
+        return PAM_ERR_CAPACITY;
+    }
+    double *H = wsp<double>(ctx, BUF_H);
+    double *scr = wsp<double>(ctx, BUF_VEC);
+    const int32_t *flags = wsp<int32_t>(ctx, BUF_FLAGS);
+    if (a.precision == PAM_PREC_F64) {
+        PAM_CHECK_HIP(hipFuncSetAttribute((const void *)k_solve<double>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_solve<double>, dim3(a.sub_count), dim3(kT), lds, ctx->stream, a,
+                           wsp<double>(ctx, BUF_G), H, scr, flags);
+    } else {
+        PAM_CHECK_HIP(hipFuncSetAttribute((const void *)k_solve<float>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_solve<float>, dim3(a.sub_count), dim3(kT), lds, ctx->stream, a,
+                           wsp<float>(ctx, BUF_G), H, scr, flags);
+    }
+    PAM_CHECK_HIP(hipGetLastError());
+    return PAM_OK;
+}
+
+}  // namespace pam

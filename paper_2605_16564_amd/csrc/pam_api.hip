@@ -60,6 +60,32 @@ pam_status upload(pam_ctx *ctx, Buf b, const void *host, size_t bytes) {
     return upload_to(ctx, ctx->ws.ptr[b], host, bytes);
 }
 
+static hipEvent_t timing_event(pam_ctx *ctx) {
+    Timing &t = ctx->timing;
+    if (!t.pool.empty()) {
+        hipEvent_t e = t.pool.back();
+        t.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+KernelTimer::KernelTimer(pam_ctx *ctx, int kind) : ctx_(ctx), kind_(kind) {
+    if (!ctx_->timing.on) return;
+    start_ = timing_event(ctx_);
+    if (start_) (void)hipEventRecord(start_, ctx_->stream);
+}
+
+KernelTimer::~KernelTimer() {
+    if (!start_) return;
+    hipEvent_t stop = timing_event(ctx_);
+    if (!stop) return;
+    (void)hipEventRecord(stop, ctx_->stream);
+    ctx_->timing.pending.push_back({kind_, {start_, stop}});
+}
+
 // setup kernels (k_setup.hip)
 pam_status launch_gather(pam_ctx *ctx, const pam_grid *g, const void *tab_dev, int n_sub,
                          int32_t n_max, const double *cell_y, const int64_t *off, double *x,
@@ -137,24 +163,31 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
     a.active = active;
     const size_t per_sub = (size_t)a.mpad * a.npad * wbytes(a.precision) +
                            (size_t)a.mpad * a.mpad * gbytes(a.precision) +
-                           (size_t)a.m_cap * a.m_cap * 8 + (size_t)a.m_cap * 8 * 8 +
-                           (size_t)a.m_cap * 3 * 4;
+                           solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap) * 8;
     int batch = o->batched ? (int)std::max<size_t>(1, ws_budget() / std::max<size_t>(per_sub, 1)) : 1;
     batch = std::min(batch, a.n_sub);
     pam_status st;
     if ((st = ensure(ctx, BUF_WT, (size_t)batch * a.mpad * a.npad * wbytes(a.precision))) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_G, (size_t)batch * a.mpad * a.mpad * gbytes(a.precision))) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_H, (size_t)batch * a.m_cap * a.m_cap * 8)) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_VEC, (size_t)batch * a.m_cap * 8 * 8)) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_IVEC, (size_t)batch * a.m_cap * 3 * 4)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_H, (size_t)batch * solve_h_elems(a.m_cap) * 8)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_VEC, (size_t)batch * solve_scratch_elems(a.m_cap) * 8)) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_FLAGS, (size_t)a.n_sub * 4)) != PAM_OK) return st;
     PAM_CHECK_HIP(hipMemsetAsync(ctx->ws.ptr[BUF_FLAGS], 0, (size_t)a.n_sub * 4, ctx->stream));
     for (int b0 = 0; b0 < a.n_sub; b0 += batch) {
         a.sub_begin = b0;
         a.sub_count = std::min(batch, a.n_sub - b0);
-        if ((st = launch_assemble(ctx, a)) != PAM_OK) return st;
-        if ((st = launch_gram(ctx, a)) != PAM_OK) return st;
-        if ((st = launch_solve(ctx, a)) != PAM_OK) return st;
+        {
+            KernelTimer kt(ctx, PAM_TK_ASSEMBLE);
+            if ((st = launch_assemble(ctx, a)) != PAM_OK) return st;
+        }
+        {
+            KernelTimer kt(ctx, PAM_TK_GRAM);
+            if ((st = launch_gram(ctx, a)) != PAM_OK) return st;
+        }
+        {
+            KernelTimer kt(ctx, PAM_TK_SOLVE);
+            if ((st = launch_solve(ctx, a)) != PAM_OK) return st;
+        }
     }
     return PAM_OK;
 }
@@ -223,6 +256,11 @@ pam_status pam_destroy(pam_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (int b = 0; b < BUF_COUNT; ++b)
         if (ctx->ws.ptr[b]) (void)hipFree(ctx->ws.ptr[b]);
+    for (auto &p : ctx->timing.pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : ctx->timing.pool) (void)hipEventDestroy(e);
     if (ctx->staging.host) (void)hipHostFree(ctx->staging.host);
     if (ctx->staging.done) (void)hipEventDestroy(ctx->staging.done);
     ctx->alive = false;
@@ -241,6 +279,39 @@ pam_status pam_sync(pam_ctx *ctx) {
     pam_status st = check_ctx(ctx);
     if (st != PAM_OK) return st;
     PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    return PAM_OK;
+}
+
+pam_status pam_timing_enable(pam_ctx *ctx, int32_t on) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    ctx->timing.on = on != 0;
+    return PAM_OK;
+}
+
+pam_status pam_timing_read(pam_ctx *ctx, double *ms, int64_t *launches, int32_t reset) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(ms && launches, "NULL output");
+    Timing &t = ctx->timing;
+    PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto &p : t.pending) {
+        float e = 0.0f;
+        PAM_CHECK_HIP(hipEventElapsedTime(&e, p.second.first, p.second.second));
+        t.ms[p.first] += e;
+        t.count[p.first] += 1;
+        t.pool.push_back(p.second.first);
+        t.pool.push_back(p.second.second);
+    }
+    t.pending.clear();
+    for (int k = 0; k < PAM_TK_COUNT; ++k) {
+        ms[k] = t.ms[k];
+        launches[k] = t.count[k];
+        if (reset) {
+            t.ms[k] = 0.0;
+            t.count[k] = 0;
+        }
+    }
     return PAM_OK;
 }
 
@@ -277,6 +348,7 @@ pam_status pam_partition_gather(pam_ctx *ctx, const pam_grid *grid, const double
     std::vector<char> tab(gather_table_bytes(n_sub));
     build_gather_table(grid, tab.data());
     if ((st = upload(ctx, BUF_TABLE, tab.data(), tab.size())) != PAM_OK) return st;
+    KernelTimer kt(ctx, PAM_TK_GATHER);
     return launch_gather(ctx, grid, ctx->ws.ptr[BUF_TABLE], n_sub, n_max, cell_y, off, x, y, h, cell);
 }
 
@@ -301,6 +373,7 @@ pam_status pam_init_lattice(pam_ctx *ctx, const pam_grid *grid, const int32_t *g
     std::vector<char> tab(lattice_table_bytes(n_sub));
     build_lattice_table(grid, g, sigma_factor, tab.data());
     if ((st = upload(ctx, BUF_TABLE, tab.data(), tab.size())) != PAM_OK) return st;
+    KernelTimer kt(ctx, PAM_TK_LATTICE);
     return launch_lattice(ctx, grid->dim, g, n_sub, dict->m_cap, ctx->ws.ptr[BUF_TABLE], dict);
 }
 
@@ -367,8 +440,14 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
         const int warm = round == 0 ? opts->warm_start : 1;
         if ((st = run_fit(ctx, samples, dict, opts, beta, stats, active, warm)) != PAM_OK) return st;
         ra.round = round;
-        if ((st = launch_indicator(ctx, ra)) != PAM_OK) return st;
-        if ((st = launch_mark_enrich(ctx, ra)) != PAM_OK) return st;
+        {
+            KernelTimer kt(ctx, PAM_TK_INDICATOR);
+            if ((st = launch_indicator(ctx, ra)) != PAM_OK) return st;
+        }
+        {
+            KernelTimer kt(ctx, PAM_TK_MARK);
+            if ((st = launch_mark_enrich(ctx, ra)) != PAM_OK) return st;
+        }
     }
     return PAM_OK;
 }

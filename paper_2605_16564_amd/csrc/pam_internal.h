@@ -35,9 +35,8 @@ void set_error(const std::string &msg);
 enum Buf {
     BUF_WT = 0,     // normalized design, transposed [n_sub][mpad][npad] (f64/f32/bf16)
     BUF_G,          // Gram incl. data row [n_sub][mpad][mpad] (f64 or f32)
-    BUF_H,          // inverse of the active block [n_sub][m_cap][m_cap] f64
-    BUF_VEC,        // per-subdomain f64 vectors (gradient, scratch) [n_sub][8][m_cap]
-    BUF_IVEC,       // per-subdomain int vectors (active list, positions) [n_sub][3][m_cap]
+    BUF_H,          // inverse of the active block, per subdomain (solve_h_elems) f64
+    BUF_VEC,        // per-subdomain scratch of the blocked bordering (solve_scratch_elems) f64
     BUF_TABLE,      // small launch tables (per-subdomain parameters)
     BUF_R,          // indicator values [N_tot] f64
     BUF_MARK,       // marked element lists [n_sub][n_max] int32
@@ -59,6 +58,15 @@ struct Staging {
     hipEvent_t done = nullptr;
 };
 
+// Opt-in per-launch event timing (pam_timing_enable).
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> pool;                // free events
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double ms[PAM_TK_COUNT] = {};
+    int64_t count[PAM_TK_COUNT] = {};
+};
+
 }  // namespace pam
 
 struct pam_ctx {
@@ -66,6 +74,7 @@ struct pam_ctx {
     hipStream_t stream = nullptr;
     pam::Workspace ws;
     pam::Staging staging;
+    pam::Timing timing;
     bool alive = true;
 };
 
@@ -77,7 +86,7 @@ pam_status ensure(pam_ctx *ctx, Buf b, size_t bytes);
 template <typename T>
 T *wsp(pam_ctx *ctx, Buf b) { return reinterpret_cast<T *>(ctx->ws.ptr[b]); }
 
-inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+__host__ __device__ inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Host-side helpers shared by the API files.
 pam_status upload(pam_ctx *ctx, Buf b, const void *host, size_t bytes);
@@ -87,6 +96,18 @@ pam_status upload_to(pam_ctx *ctx, void *dst, const void *host, size_t bytes);
 // Padded sizes of the design/Gram workspace for a dictionary capacity.
 inline int32_t mpad_of(int32_t m_cap) { return (int32_t)round_up((int64_t)m_cap + 1, 64); }
 inline int32_t npad_of(int32_t n_max) { return (int32_t)round_up(n_max > 0 ? n_max : 1, 32); }
+
+// Brackets the launches made during its lifetime with timing events of
+// kind `kind` when timing is enabled on the context.
+class KernelTimer {
+  public:
+    KernelTimer(pam_ctx *ctx, int kind);
+    ~KernelTimer();
+  private:
+    pam_ctx *ctx_;
+    int kind_;
+    hipEvent_t start_ = nullptr;
+};
 
 // ---------------------------------------------------------------- launchers
 // (defined in the .hip files; every launcher enqueues on ctx->stream and
@@ -110,6 +131,8 @@ struct FitArgs {
 pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_gram(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a);
+__host__ __device__ size_t solve_h_elems(int m_cap);
+__host__ __device__ size_t solve_scratch_elems(int m_cap);
 
 struct RefineArgs {
     int32_t n_sub, dim, m_cap, n_max;

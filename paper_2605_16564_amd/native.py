@@ -7,9 +7,10 @@ library has not been built (there is no CPU fallback).
 from __future__ import annotations
 
 import ctypes as C
+import os
 from pathlib import Path
 
-LIB_PATH = Path(__file__).resolve().parent / "_build" / "libpam.so"
+LIB_PATH = Path(os.environ.get("PAM_LIB", str(Path(__file__).resolve().parent / "_build" / "libpam.so")))
 
 PAM_OK = 0
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
@@ -18,8 +19,10 @@ ST_OK, ST_NOCONV, ST_UNDERFLOW, ST_EMPTY = 0, 1, 2, 3
 EXPORTS = [
     "pam_create", "pam_destroy", "pam_set_stream", "pam_sync", "pam_last_error", "pam_version",
     "pam_partition_count", "pam_partition_gather", "pam_init_lattice", "pam_fit_subdomains",
-    "pam_refine", "pam_eval",
+    "pam_refine", "pam_eval", "pam_timing_enable", "pam_timing_read",
 ]
+TIMING_KINDS = ["gather", "lattice", "assemble", "gram", "solve", "indicator", "mark",
+                "eval_bin", "eval"]
 
 
 class PamGrid(C.Structure):
@@ -50,7 +53,7 @@ class PamEnetOpts(C.Structure):
 
 class PamFitStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("cd_sweeps", C.c_int32), ("iters", C.c_int32),
-                ("support", C.c_int32), ("kkt", C.c_double)]
+                ("support", C.c_int32), ("kkt", C.c_double), ("stream_bytes", C.c_double)]
 
 
 class PamRefineOpts(C.Structure):
@@ -99,6 +102,8 @@ def lib():
                                  C.POINTER(PamEnetOpts), C.POINTER(PamRefineOpts), P]
         L.pam_eval.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P, C.c_int32,
                                P, C.c_int64, P, C.c_int32, P]
+        L.pam_timing_enable.argtypes = [P, C.c_int32]
+        L.pam_timing_read.argtypes = [P, P, P, C.c_int32]
         for name in EXPORTS:
             if name not in ("pam_last_error", "pam_version"):
                 getattr(L, name).restype = C.c_int
