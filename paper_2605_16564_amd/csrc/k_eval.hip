@@ -51,10 +51,21 @@ __device__ __forceinline__ int owner_of(const EvalTables &t, int f, const TQ *xq
     return F.sub_base + sub;
 }
 
+// Owner of every query and the per-subdomain query counts. Counts go to an
+// LDS histogram per block and are flushed with one global atomic per
+// touched bin (queries arrive in spatially coherent runs, so global atomics
+// per query would serialize on a handful of counters).
+static constexpr int kBinsLds = 8192;
+
 template <typename TQ>
 __global__ void __launch_bounds__(kE)
-k_owner(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int32_t *__restrict__ owner,
+k_owner(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, int32_t *__restrict__ owner,
         int32_t *__restrict__ hist, TQ *__restrict__ out, unsigned long long *__restrict__ n_out) {
+    __shared__ int32_t lh[kBinsLds];
+    const bool local = n_sub <= kBinsLds;
+    if (local)
+        for (int b = threadIdx.x; b < n_sub; b += kE) lh[b] = 0;
+    __syncthreads();
     for (int64_t q = (int64_t)blockIdx.x * kE + threadIdx.x; q < Q; q += (int64_t)gridDim.x * kE) {
         int f = 0;
         while (f + 1 < t.n_fields && q >= t.fields[f].q_end) ++f;
@@ -62,12 +73,17 @@ k_owner(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int32_t *__restrict_
         if (q >= t.fields[f].q_begin && q < t.fields[f].q_end) o = owner_of(t, f, xq, q);
         owner[q] = o;
         if (o >= 0) {
-            atomicAdd(&hist[o], 1);
+            if (local) atomicAdd(&lh[o], 1);
+            else atomicAdd(&hist[o], 1);
         } else {
             out[q] = (TQ)NAN;
             if (n_out) atomicAdd(n_out, 1ull);
         }
     }
+    __syncthreads();
+    if (local)
+        for (int b = threadIdx.x; b < n_sub; b += kE)
+            if (lh[b]) atomicAdd(&hist[b], lh[b]);
 }
 
 // Single-block exclusive scan of the owner histogram; also the chunk
@@ -108,14 +124,45 @@ k_scan(int n_sub, const int32_t *__restrict__ hist, int64_t *__restrict__ base,
     if (threadIdx.x == 0) *n_chunks = carry_c;
 }
 
+// Binned positions: each block takes kScatter consecutive queries, ranks
+// them inside their bins in LDS, reserves one range per touched bin with a
+// global atomic, and writes the permutation.
+static constexpr int kScatterPer = 16;
+static constexpr int kScatter = kE * kScatterPer;
+
 __global__ void __launch_bounds__(kE)
-k_scatter(int64_t Q, const int32_t *__restrict__ owner, const int64_t *__restrict__ base,
+k_scatter(int64_t Q, int n_sub, const int32_t *__restrict__ owner, const int64_t *__restrict__ base,
           int32_t *__restrict__ cursor, int64_t *__restrict__ perm) {
-    for (int64_t q = (int64_t)blockIdx.x * kE + threadIdx.x; q < Q; q += (int64_t)gridDim.x * kE) {
-        const int o = owner[q];
-        if (o < 0) continue;
-        const int r = atomicAdd(&cursor[o], 1);
-        perm[base[o] + r] = q;
+    __shared__ int32_t lcount[kBinsLds];
+    __shared__ int32_t lbase[kBinsLds];
+    const int64_t q0 = (int64_t)blockIdx.x * kScatter;
+    if (n_sub > kBinsLds) {
+        for (int e = 0; e < kScatterPer; ++e) {
+            const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
+            if (q >= Q) break;
+            const int o = owner[q];
+            if (o < 0) continue;
+            perm[base[o] + atomicAdd(&cursor[o], 1)] = q;
+        }
+        return;
+    }
+    for (int b = threadIdx.x; b < n_sub; b += kE) lcount[b] = 0;
+    __syncthreads();
+    int ow[kScatterPer], rk[kScatterPer];
+#pragma unroll
+    for (int e = 0; e < kScatterPer; ++e) {
+        const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
+        ow[e] = q < Q ? owner[q] : -1;
+        rk[e] = ow[e] >= 0 ? atomicAdd(&lcount[ow[e]], 1) : 0;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < n_sub; b += kE)
+        if (lcount[b]) lbase[b] = atomicAdd(&cursor[b], lcount[b]);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kScatterPer; ++e) {
+        const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
+        if (ow[e] >= 0) perm[base[ow[e]] + lbase[ow[e]] + rk[e]] = q;
     }
 }
 
@@ -276,17 +323,18 @@ pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, cons
     int32_t *chsub = (int32_t *)(w + o_chsub);
     int64_t *chstart = (int64_t *)(w + o_chstart);
     int32_t *chlen = (int32_t *)(w + o_chlen);
-    const int grid_q = (int)std::min<int64_t>((Q + kE - 1) / kE, 65536);
+    // owner pass: a few thousand resident blocks, each flushing one histogram
+    const int grid_o = (int)std::max<int64_t>(1, std::min<int64_t>((Q + kE - 1) / kE, 2048));
     {
     KernelTimer kt_bin(ctx, PAM_TK_EVAL_BIN);
     if (Q > 0) {
         if (dtype == 0)
-            hipLaunchKernelGGL((k_owner<float>), dim3(grid_q), dim3(kE), 0, ctx->stream, t,
-                               (const float *)xq, Q, owner, hist, (float *)out,
+            hipLaunchKernelGGL((k_owner<float>), dim3(grid_o), dim3(kE), 0, ctx->stream, t,
+                               (const float *)xq, Q, n_sub_total, owner, hist, (float *)out,
                                (unsigned long long *)n_outside);
         else
-            hipLaunchKernelGGL((k_owner<double>), dim3(grid_q), dim3(kE), 0, ctx->stream, t,
-                               (const double *)xq, Q, owner, hist, (double *)out,
+            hipLaunchKernelGGL((k_owner<double>), dim3(grid_o), dim3(kE), 0, ctx->stream, t,
+                               (const double *)xq, Q, n_sub_total, owner, hist, (double *)out,
                                (unsigned long long *)n_outside);
         PAM_CHECK_HIP(hipGetLastError());
     }
@@ -294,8 +342,8 @@ pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, cons
                        cursor, nch);
     PAM_CHECK_HIP(hipGetLastError());
     if (Q > 0) {
-        hipLaunchKernelGGL(k_scatter, dim3(grid_q), dim3(kE), 0, ctx->stream, Q, owner, base,
-                           cursor, perm);
+        hipLaunchKernelGGL(k_scatter, dim3((unsigned)((Q + kScatter - 1) / kScatter)), dim3(kE), 0,
+                           ctx->stream, Q, n_sub_total, owner, base, cursor, perm);
         PAM_CHECK_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_chunks, dim3((n_sub_total + kE - 1) / kE), dim3(kE), 0, ctx->stream,
