@@ -31,16 +31,18 @@ static constexpr int kW = kT / 64;
 static constexpr int kB = 8;       // coordinates activated per blocked bordering step
 static constexpr int kR = 1;       // GEMV outputs per thread per pass
 static constexpr int kTile = 128;  // rows staged in LDS per bordering tile
+static constexpr int kFz = 8;      // coordinates frozen before one batched downdate
+static constexpr int kQ = 16;      // rows of the low-rank update scratch (>= kB, kFz)
 static constexpr int kPass = kR * kT;
 
 __host__ __device__ size_t solve_ldh(int m_cap) { return (size_t)round_up(m_cap, kPass); }
 __host__ __device__ size_t solve_h_elems(int m_cap) { return (size_t)(m_cap + 1) * solve_ldh(m_cap); }
-__host__ __device__ size_t solve_scratch_elems(int m_cap) { return (size_t)3 * kB * m_cap; }
+__host__ __device__ size_t solve_scratch_elems(int m_cap) { return (size_t)3 * kQ * m_cap; }
 size_t solve_lds_bytes(int m_cap) { return (size_t)49 * round_up(m_cap, 8) + 64; }
 
 // ---------------------------------------------------------------- reductions
 struct Red {
-    double v[kW * kB];
+    double v[kW * 16];
     int i[kW];
     int flag;
     int count;
@@ -136,6 +138,9 @@ struct Sv {
     signed char *th;       // LDS
     int s;                 // active-set size (uniform)
     double bytes;          // algorithmic bytes streamed (Gram rows, H)
+    int r;                 // frozen positions awaiting the batched downdate
+    int *Rp;               // LDS [kFz] frozen positions
+    double *Cri;           // LDS [kFz*kFz] inverse of H[R, R]
 };
 
 template <typename TG>
@@ -145,25 +150,97 @@ __device__ __forceinline__ double Gat(const Sv<TG> &v, int i, int j) {
 
 // out_i = sum_j H[j][i] in_j, i < s (H symmetric; rows streamed coalesced,
 // four rows in flight per thread).
-template <typename TG>
-__device__ void hgemv(const Sv<TG> &v, const double *in, double *out) {
-    constexpr int kQ = 16;   // rows loaded before use
+template <int R, typename TG>
+__device__ void hgemv_r(Sv<TG> &v, const double *in, double *out) {
+    constexpr int kRows = 8;   // rows loaded before use
     const int s = v.s;
-    const_cast<Sv<TG> &>(v).bytes += 8.0 * (double)s * (double)s;
-    for (int base = 0; base < s; base += kPass) {
-        double acc = 0.0;
+    for (int base = 0; base < s; base += R * kT) {
+        double acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
         const double *Hc = v.H + base + threadIdx.x;
         int jj = 0;
-        for (; jj + kQ <= s; jj += kQ) {
-            double h[kQ];
+        for (; jj + kRows <= s; jj += kRows) {
+            double h[kRows][R];
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) h[q] = Hc[(size_t)(jj + q) * v.ldh];
+            for (int q = 0; q < kRows; ++q)
 #pragma unroll
-            for (int q = 0; q < kQ; ++q) acc += h[q] * in[jj + q];
+                for (int r = 0; r < R; ++r) h[q][r] = Hc[(size_t)(jj + q) * v.ldh + r * kT];
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) {
+                const double x = in[jj + q];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += h[q][r] * x;
+            }
         }
-        for (; jj < s; ++jj) acc += Hc[(size_t)jj * v.ldh] * in[jj];
-        const int i = base + threadIdx.x;
-        if (i < s) out[i] = acc;
+        for (; jj < s; ++jj) {
+            const double x = in[jj];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += Hc[(size_t)jj * v.ldh + r * kT] * x;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = base + threadIdx.x + r * kT;
+            if (i < s) out[i] = acc[r];
+        }
+    }
+    __syncthreads();
+}
+
+// out_i = sum_j H[j][i] in_j, i < s (H symmetric; rows streamed coalesced,
+// up to four outputs per thread so that more rows are in flight).
+template <typename TG>
+__device__ void hgemv(Sv<TG> &v, const double *in, double *out) {
+    v.bytes += 8.0 * (double)v.s * (double)v.s;
+    if (v.s <= kT) hgemv_r<1>(v, in, out);
+    else if (v.s <= 2 * kT) hgemv_r<2>(v, in, out);
+    else hgemv_r<4>(v, in, out);
+}
+
+// H[i][j] += sum_q Vr[q][i] Ur[q][j] for i, j < s and q < nq (nq <= kQ):
+// thread-owned columns j keep Ur[.][j] in registers, rows i stream in
+// batches of eight with Vr[.][i] staged in LDS tiles.
+template <int NQ, typename TG>
+__device__ void hupdate(Sv<TG> &v, int s, int nq, const double *Vr, const double *Ur, double *tile) {
+    for (int jb = 0; jb < s; jb += kT) {
+        const int j = jb + threadIdx.x;
+        const bool live = j < s;
+        double uj[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) uj[q] = (live && q < nq) ? Ur[(size_t)q * v.m_cap + j] : 0.0;
+        double *Hc = v.H + j;
+        for (int t0 = 0; t0 < s; t0 += kTile) {
+            const int tn = min(kTile, s - t0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < NQ * kTile; e += kT) {
+                const int q = e / kTile, r = e - q * kTile;
+                tile[e] = (q < nq && r < tn) ? Vr[(size_t)q * v.m_cap + t0 + r] : 0.0;
+            }
+            __syncthreads();
+            if (!live) continue;
+            int r = 0;
+            for (; r + 8 <= tn; r += 8) {
+                double *h = Hc + (size_t)(t0 + r) * v.ldh;
+                double hv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) hv[e] = h[(size_t)e * v.ldh];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const double uq = uj[q];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) hv[e] += tile[q * kTile + r + e] * uq;
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) h[(size_t)e * v.ldh] = hv[e];
+            }
+            for (; r < tn; ++r) {
+                double *h = Hc + (size_t)(t0 + r) * v.ldh;
+                double h0 = h[0];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) h0 += tile[q * kTile + r] * uj[q];
+                h[0] = h0;
+            }
+        }
     }
     __syncthreads();
 }
@@ -279,51 +356,14 @@ __device__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *ci
         }
     }
     __syncthreads();
-    // H[i][j] += sum_q V[q][i] U[q][j] over the old block (V rows staged in LDS)
-    for (int jb = 0; jb < s; jb += kT) {
-        const int j = jb + threadIdx.x;
-        const bool live = j < s;
-        double uj[kB];
-#pragma unroll
-        for (int q = 0; q < kB; ++q) uj[q] = (live && q < nb) ? v.U[(size_t)q * v.m_cap + j] : 0.0;
-        double *Hc = v.H + j;
-        for (int t0 = 0; t0 < s; t0 += kTile) {
-            const int tn = min(kTile, s - t0);
-            __syncthreads();
-            for (int e = threadIdx.x; e < kB * kTile; e += kT) {
-                const int q = e / kTile, r = e - q * kTile;
-                tile[e] = (q < nb && r < tn) ? v.V[(size_t)q * v.m_cap + t0 + r] : 0.0;
-            }
-            __syncthreads();
-            if (!live) continue;
-            int r = 0;
-            for (; r + 8 <= tn; r += 8) {
-                double *h = Hc + (size_t)(t0 + r) * v.ldh;
-                double hv[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) hv[e] = h[(size_t)e * v.ldh];
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-#pragma unroll
-                    for (int q = 0; q < kB; ++q) hv[e] += tile[q * kTile + r + e] * uj[q];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) h[(size_t)e * v.ldh] = hv[e];
-            }
-            for (; r < tn; ++r) {
-                double *h = Hc + (size_t)(t0 + r) * v.ldh;
-                double h0 = h[0];
-#pragma unroll
-                for (int q = 0; q < kB; ++q) h0 += tile[q * kTile + r] * uj[q];
-                h[0] = h0;
-            }
+    // H[i][j] += sum_q V[q][i] U[q][j] over the old block
+    hupdate<kB>(v, s, nb, v.V, v.U, tile);
+    for (int j = threadIdx.x; j < s; j += kT)
+        for (int q = 0; q < nb; ++q) {
+            const double val = -v.V[(size_t)q * v.m_cap + j];
+            v.H[(size_t)(s + q) * v.ldh + j] = val;
+            v.H[(size_t)j * v.ldh + s + q] = val;
         }
-        if (live)
-            for (int q = 0; q < nb; ++q) {
-                const double val = -v.V[(size_t)q * v.m_cap + j];
-                v.H[(size_t)(s + q) * v.ldh + j] = val;
-                v.H[(size_t)j * v.ldh + s + q] = val;
-            }
-    }
     if (threadIdx.x < nb * nb) {
         const int p = threadIdx.x / nb, q = threadIdx.x % nb;
         v.H[(size_t)(s + p) * v.ldh + s + q] = cinv[p * kB + q];
@@ -335,6 +375,141 @@ __device__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *ci
     __syncthreads();
     v.s = s + nb;
     return true;
+}
+
+// Drop active position p (no update of H): the last position moves into p.
+template <typename TG>
+__device__ void drop_position(Sv<TG> &v, int p) {
+    const int last = v.s - 1;
+    const int kp = v.S[p];
+    if (p != last) {
+        for (int j = threadIdx.x; j < last; j += kT) {
+            if (j == p) continue;
+            const double val = v.H[(size_t)last * v.ldh + j];
+            v.H[(size_t)p * v.ldh + j] = val;
+            v.H[(size_t)j * v.ldh + p] = val;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            v.H[(size_t)p * v.ldh + p] = v.H[(size_t)last * v.ldh + last];
+            const int kl = v.S[last];
+            v.S[p] = kl;
+            v.pos[kl] = p;
+        }
+    }
+    if (threadIdx.x == 0) v.pos[kp] = -1;
+    __syncthreads();
+    v.s = last;
+}
+
+// Freeze active position p: its coordinate is held at zero without touching
+// H. With W = H[:, R] (rows of H, by symmetry) and C = H[R, R], the inverse of
+// the remaining block is H - W C^-1 W'; C^-1 grows by bordering.
+template <typename TG>
+__device__ void freeze(Sv<TG> &v, int p) {
+    const int s = v.s, r = v.r;
+    v.bytes += 8.0 * s;
+    for (int i = threadIdx.x; i < s; i += kT) v.U[(size_t)r * v.m_cap + i] = v.H[(size_t)p * v.ldh + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double *c = v.Cri + kFz * kFz, *u = c + kFz;   // scratch after C^-1
+        for (int q = 0; q < r; ++q) c[q] = v.U[(size_t)q * v.m_cap + p];
+        double delta = v.H[(size_t)p * v.ldh + p];
+        for (int q = 0; q < r; ++q) {
+            double t = 0.0;
+            for (int k = 0; k < r; ++k) t += v.Cri[q * kFz + k] * c[k];
+            u[q] = t;
+            delta -= c[q] * t;
+        }
+        const double id = 1.0 / delta;
+        for (int q = 0; q < r; ++q) {
+            for (int k = 0; k < r; ++k) v.Cri[q * kFz + k] += u[q] * u[k] * id;
+            v.Cri[q * kFz + r] = -u[q] * id;
+            v.Cri[r * kFz + q] = -u[q] * id;
+        }
+        v.Cri[r * kFz + r] = id;
+        v.Rp[r] = p;
+    }
+    __syncthreads();
+    v.r = r + 1;
+}
+
+// Apply the frozen set to H (one rank-r pass: H <- H - W' C^-1 W) and drop
+// the frozen positions from the active list.
+template <typename TG>
+__device__ void compact(Sv<TG> &v, double *tile) {
+    const int r = v.r;
+    if (r == 0) return;
+    const int s = v.s;
+    v.bytes += 16.0 * (double)s * (double)s;
+    // V = -C^-1 W (r x s)
+    for (int i = threadIdx.x; i < s; i += kT) {
+        double w[kFz];
+#pragma unroll
+        for (int q = 0; q < kFz; ++q) w[q] = q < r ? v.U[(size_t)q * v.m_cap + i] : 0.0;
+        for (int q = 0; q < r; ++q) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < kFz; ++k) t += (k < r ? v.Cri[q * kFz + k] : 0.0) * w[k];
+            v.V[(size_t)q * v.m_cap + i] = -t;
+        }
+    }
+    __syncthreads();
+    if (r <= kB) hupdate<kB>(v, s, r, v.V, v.U, tile);
+    else hupdate<kFz>(v, s, r, v.V, v.U, tile);
+    // drop frozen positions in descending order (each hole takes the last live one)
+    for (int n = 0; n < r; ++n) {
+        int best = -1;
+        for (int q = 0; q < r; ++q) best = max(best, v.Rp[q]);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int q = 0; q < r; ++q)
+                if (v.Rp[q] == best) { v.Rp[q] = -1; break; }
+        __syncthreads();
+        drop_position(v, best);
+    }
+    v.r = 0;
+}
+
+// z = (inverse of the active block without the frozen positions) * in,
+// with in and z zero at frozen positions.
+template <typename TG>
+__device__ void solve_active(Sv<TG> &v, double *in, double *out, Red &red) {
+    const int s = v.s, r = v.r;
+    if (r > 0) {
+        if ((int)threadIdx.x < r) in[v.Rp[threadIdx.x]] = 0.0;
+        __syncthreads();
+    }
+    hgemv(v, in, out);
+    if (r == 0) return;
+    double t[kFz];
+#pragma unroll
+    for (int q = 0; q < kFz; ++q) t[q] = 0.0;
+    for (int i = threadIdx.x; i < s; i += kT) {
+        const double x = in[i];
+#pragma unroll
+        for (int q = 0; q < kFz; ++q)
+            if (q < r) t[q] += v.U[(size_t)q * v.m_cap + i] * x;
+    }
+    bsum_vec<kFz>(t, red);
+    double y[kFz];
+#pragma unroll
+    for (int q = 0; q < kFz; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kFz; ++k) acc += (q < r && k < r) ? v.Cri[q * kFz + k] * t[k] : 0.0;
+        y[q] = acc;
+    }
+    for (int i = threadIdx.x; i < s; i += kT) {
+        double acc = out[i];
+#pragma unroll
+        for (int q = 0; q < kFz; ++q)
+            if (q < r) acc -= v.U[(size_t)q * v.m_cap + i] * y[q];
+        out[i] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < r) out[v.Rp[threadIdx.x]] = 0.0;
+    __syncthreads();
 }
 
 // Remove active position p: H <- H_{-p,-p} - h h' / H_pp (h = H[-p, p]),
@@ -386,25 +561,25 @@ __device__ void remove_at(Sv<TG> &v, int p) {
     v.s = s - 1;
 }
 
-// g = b - G beta - lambda2 beta over all coordinates (rows of the active set).
+// g = b - G beta - lambda2 beta over all coordinates (rows of the active
+// set), one coordinate per thread and pass, sixteen Gram rows in flight.
 template <typename TG>
 __device__ void full_gradient(Sv<TG> &v) {
+    constexpr int kRows = 16;
     const int s = v.s;
     v.bytes += (double)s * v.M * sizeof(TG);
     for (int m = threadIdx.x; m < v.M; m += kT) {
         double acc = Gat(v, m, v.M) - v.l2 * v.beta[m];
+        const TG *col = v.G + m;
         int i = 0;
-        for (; i + 8 <= s; i += 8) {
-            double gv[8];
+        for (; i + kRows <= s; i += kRows) {
+            double gv[kRows];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) gv[e] = (double)v.G[(size_t)v.S[i + e] * v.mpad + m];
+            for (int e = 0; e < kRows; ++e) gv[e] = (double)col[(size_t)v.S[i + e] * v.mpad];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) acc -= gv[e] * v.beta[v.S[i + e]];
+            for (int e = 0; e < kRows; ++e) acc -= gv[e] * v.beta[v.S[i + e]];
         }
-        for (; i < s; ++i) {
-            const int k = v.S[i];
-            acc -= (double)v.G[(size_t)k * v.mpad + m] * v.beta[k];
-        }
+        for (; i < s; ++i) acc -= (double)col[(size_t)v.S[i] * v.mpad] * v.beta[v.S[i]];
         v.g[m] = acc;
     }
     __syncthreads();
@@ -449,7 +624,9 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __shared__ double cinv[kB * kB];
     __shared__ int blk[kB];
     __shared__ int list[kB];
-    __shared__ double tile[kB * kTile];
+    __shared__ double tile[kQ * kTile];
+    __shared__ int frz[kFz];
+    __shared__ double cri[kFz * kFz + 2 * kFz];
     const int s_id = a.sub_begin + blockIdx.x;
     if (a.active && !a.active[s_id]) return;
     const int loc = s_id - a.sub_begin;
@@ -464,8 +641,8 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.H = Hall + (size_t)loc * solve_h_elems(a.m_cap);
     double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap);
     v.Ag = sc;
-    v.U = sc + (size_t)kB * a.m_cap;
-    v.V = sc + (size_t)2 * kB * a.m_cap;
+    v.U = sc + (size_t)kQ * a.m_cap;
+    v.V = sc + (size_t)2 * kQ * a.m_cap;
     const int Mc = (int)round_up(a.m_cap, 8);
     double *ld = reinterpret_cast<double *>(lds_raw);
     v.g = ld;
@@ -478,6 +655,9 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.th = reinterpret_cast<signed char *>(v.pos + Mc);
     v.s = 0;
     v.bytes = 0.0;
+    v.r = 0;
+    v.Rp = frz;
+    v.Cri = cri;
     const int M = v.M;
 #ifdef PAM_PHASE_PROFILE
     long long ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -604,7 +784,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
                 v.rhs[i] = Gat(v, k, M) - v.l1 * (double)v.th[k];
             }
             __syncthreads();
-            hgemv(v, v.rhs, v.z);
+            solve_active(v, v.rhs, v.z, red);
             PHASE_MARK(3);
             bool mine = true;
             for (int i = threadIdx.x; i < s; i += kT)
@@ -682,13 +862,28 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
                     v.th[k] = (signed char)sgn(nb);
                 }
                 __syncthreads();
-                for (int p = v.s - 1; p >= 0; --p)
-                    if (v.th[v.S[p]] == 0) {
-                        remove_at(v, p);
-#ifdef PAM_PHASE_PROFILE
-                        ++n_rm;
-#endif
+                // freeze the coordinates that reached zero (batched downdate)
+                for (;;) {
+                    VI x; x.v = -1.0; x.i = -1;
+                    for (int p = threadIdx.x; p < v.s; p += kT) {
+                        if (v.th[v.S[p]] != 0) continue;
+                        bool fr = false;
+                        for (int q = 0; q < v.r; ++q) fr |= v.Rp[q] == p;
+                        if (fr) continue;
+                        VI c; c.v = (double)p; c.i = p;
+                        x = vmax(x, c);
                     }
+                    x = bargmax(x, red);
+                    if (x.i < 0) break;
+                    if (v.r == kFz) {
+                        compact(v, tile);
+                        continue;   // positions moved: search again
+                    }
+                    freeze(v, x.i);
+#ifdef PAM_PHASE_PROFILE
+                    ++n_rm;
+#endif
+                }
                 PHASE_MARK(5);
 #ifdef PAM_PHASE_PROFILE
                 ++n_ls;
@@ -697,6 +892,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
             }
             for (int i = threadIdx.x; i < s; i += kT) v.beta[v.S[i]] = v.z[i];
             __syncthreads();
+            compact(v, tile);
         }
         skip_solve = false;
         full_gradient(v);
@@ -749,7 +945,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
             break;
         }
         ++refines;
-        hgemv(v, v.rhs, v.z);   // correction H r
+        solve_active(v, v.rhs, v.z, red);   // correction H r
         bool keep_mine = true;
         for (int i = threadIdx.x; i < s; i += kT) {
             const int k = v.S[i];
