@@ -147,7 +147,14 @@ typedef struct {
     int32_t warm_start;          /* 1: beta holds the starting point           */
     int32_t batched;             /* 1: one launch per step for all subdomains;
                                     0: one launch per subdomain (comparator)   */
-    const uint8_t *support_hint; /* [n_sub*m_cap] 1 = start active, or NULL     */
+    const uint8_t *support_hint; /* [n_sub*m_cap] 1 = start active, or NULL.
+                                    Used by cold fits only (warm_start = 0):
+                                    replaces the CD warm-up by the hinted set
+                                    S0, whose signs come from one FP64 ridge
+                                    solve on S0; the exact iteration and KKT
+                                    certificate follow, so beta is the same
+                                    minimizer with or without a hint. In
+                                    pam_refine it seeds the first fit only.  */
 } pam_enet_opts;
 
 /* Per-subdomain results (device array of n_sub). */
@@ -226,6 +233,70 @@ pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
                     int64_t Q, void *out, int32_t space, int64_t *n_outside);
 
 /* ------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method: a support prior for
+ * the cold elastic-net fits). A four-layer convolutional network, 5x5
+ * "same" convolutions with zero padding, 1 -> 32 -> 32 -> 32 -> 2 channels,
+ * ReLU after the first three, on 16x16 patches of cell values. Output
+ * channel 0: per-cell refinement logit (target: the cell is marked in the
+ * first refinement round); channel 1: per-cell support logit (target: the
+ * center lying in the cell is active in the cold fit).
+ *
+ * Parameters: float [pam_cnn_param_count()] = 53,698, FP32, per layer
+ * w[cout][cin][5][5] followed by b[cout], layers in order. Patches float
+ * [B][1][16][16], logits and targets float [B][2][16][16], row-major with the
+ * cell's axis-0 index fastest. All device pointers, caller-owned.
+ * ------------------------------------------------------------------------ */
+int64_t pam_cnn_param_count(void);
+
+/* logits = network(params, x) for B >= 1 patches. */
+pam_status pam_cnn_forward(pam_ctx *ctx, const float *params, int32_t B, const float *x,
+                           float *logits);
+
+/* Masked binary cross-entropy with logits over both channels,
+ *   L = sum mask * (max(z,0) - z*t + log(1 + exp(-|z|))) / sum mask,
+ * and its gradient with respect to every parameter (grads, same layout as
+ * params, overwritten). loss: device float scalar or NULL. A batch with an
+ * all-zero mask gives L = 0 and zero gradients. */
+pam_status pam_cnn_loss_grad(pam_ctx *ctx, const float *params, int32_t B, const float *x,
+                             const float *target, const float *mask, float *grads, float *loss);
+
+/* One Adam step (Kingma and Ba, 2015) with bias correction at step >= 1:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). m, v: device
+ * float [param_count] moment buffers, zero before step 1. */
+pam_status pam_cnn_adam(pam_ctx *ctx, float *params, const float *grads, float *m, float *v,
+                        int32_t step, float lr, float beta1, float beta2, float eps);
+
+/* Cut the owned box of every subdomain of a 2-D grid (its sides must be
+ * positive multiples of 16 cells) into 16x16 patches, numbered by
+ * subdomain, then row-major over the patch grid (axis 0 fastest); patch
+ * value = scale * cell_y. cell_y: device double [n_cells0*n_cells1] with
+ * axis 0 fastest. *n_patches [host] receives the count; patches == NULL
+ * makes this a count query. */
+pam_status pam_grid_patches(pam_ctx *ctx, const pam_grid *grid, const double *cell_y, float scale,
+                            int32_t *n_patches, float *patches);
+
+/* Support hint from the network's logits over the patches of the same grid
+ * (pam_grid_patches order): center k < m[s] of subdomain s reads the cell
+ * containing it (floor of its cell coordinate, clamped into the owned box)
+ * and is hinted active when that cell's support logit exceeds threshold
+ * (0 = probability 1/2). hint: device uint8 [n_sub*m_cap]; slots >= m[s]
+ * are set to 0. */
+pam_status pam_support_hint(pam_ctx *ctx, const pam_grid *grid, const pam_dict *dict,
+                            const float *logits, float threshold, uint8_t *hint);
+
+/* Training targets and masks [n_patches][2][16][16] from the method's own
+ * results on the same grid (the dictionary and samples of its partition):
+ * support channel: cells holding a center (located as in pam_support_hint)
+ * get mask 1 and target 1 iff a center in the cell has beta != 0 (beta: the
+ * cold fit); refinement channel: owned cells of the samples get mask 1 and
+ * target 1 iff elem_level > 0 (after one refinement round). Everything else
+ * gets mask 0, target 0. */
+pam_status pam_cnn_labels(pam_ctx *ctx, const pam_grid *grid, const pam_samples *samples,
+                          const pam_dict *dict, const double *beta, const int32_t *elem_level,
+                          float *target, float *mask);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (observability). When enabled, every kernel launch of the
  * context is bracketed by HIP events on the context's stream.
  * pam_timing_read synchronizes the stream and returns, per kernel kind, the
@@ -234,7 +305,7 @@ pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
  * ------------------------------------------------------------------------ */
 enum {
     PAM_TK_GATHER = 0, PAM_TK_LATTICE, PAM_TK_ASSEMBLE, PAM_TK_GRAM, PAM_TK_SOLVE,
-    PAM_TK_INDICATOR, PAM_TK_MARK, PAM_TK_EVAL_BIN, PAM_TK_EVAL, PAM_TK_COUNT
+    PAM_TK_INDICATOR, PAM_TK_MARK, PAM_TK_EVAL_BIN, PAM_TK_EVAL, PAM_TK_CNN, PAM_TK_COUNT
 };
 pam_status pam_timing_enable(pam_ctx *ctx, int32_t on);
 pam_status pam_timing_read(pam_ctx *ctx, double *ms /*[host] PAM_TK_COUNT*/,

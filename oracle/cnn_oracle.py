@@ -44,16 +44,6 @@ def unpack(params):
     return out
 
 
-def he_init(seed: int) -> np.ndarray:
-    """He-normal weights (std sqrt(2 / fan_in)), zero biases, from numpy's PCG64."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    parts = []
-    for ci, co in zip(CIN, COUT):
-        parts.append(rng.standard_normal(co * ci * K * K) * np.sqrt(2.0 / (ci * K * K)))
-        parts.append(np.zeros(co))
-    return np.concatenate(parts)
-
-
 # ---------------------------------------------------------------- network
 def conv_same(x, w, b=None):
     """x [B, Ci, H, W], w [Co, Ci, 5, 5] -> [B, Co, H, W] (zero padding 2)."""

@@ -321,3 +321,147 @@ def evaluate(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.T
                              _p(xq.contiguous()), Q, _p(out), int(space), _p(n_outside)),
             "pam_eval")
     return out
+
+
+# ---------------------------------------------------------------- learned warm start
+CNN_PATCH = 16
+
+
+def cnn_param_count() -> int:
+    return int(N.lib().pam_cnn_param_count())
+
+
+def _f32_dev(t: torch.Tensor, name: str) -> torch.Tensor:
+    _require_cuda(t, name)
+    if t.dtype != torch.float32:
+        raise N.PamError(f"{name} must be float32")
+    return t.contiguous()
+
+
+def _patch_count(t: torch.Tensor, per: int, name: str) -> int:
+    if t.numel() % per:
+        raise N.PamError(f"{name} must hold whole 16x16 patches")
+    return t.numel() // per
+
+
+def cnn_forward(ctx: Context, params: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
+    """Logits [B, 2, 16, 16] of patches x [B, 1, 16, 16]."""
+    params, x = _f32_dev(params, "params"), _f32_dev(x, "x")
+    B = _patch_count(x, 256, "x")
+    out = torch.empty((B, 2, 16, 16), dtype=torch.float32, device=x.device)
+    ctx.use_current_stream()
+    N.check(N.lib().pam_cnn_forward(ctx.h, _p(params), B, _p(x), _p(out)), "pam_cnn_forward")
+    return out
+
+
+def cnn_loss_grad(ctx: Context, params: torch.Tensor, x: torch.Tensor, target: torch.Tensor,
+                  mask: torch.Tensor, grads: Optional[torch.Tensor] = None,
+                  loss: Optional[torch.Tensor] = None):
+    """(grads [P], loss scalar tensor) of the masked BCE over a batch."""
+    params, x = _f32_dev(params, "params"), _f32_dev(x, "x")
+    target, mask = _f32_dev(target, "target"), _f32_dev(mask, "mask")
+    B = _patch_count(x, 256, "x")
+    if _patch_count(target, 512, "target") != B or _patch_count(mask, 512, "mask") != B:
+        raise N.PamError("target / mask must be [B, 2, 16, 16]")
+    if grads is None:
+        grads = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float32, device=x.device)
+    ctx.use_current_stream()
+    N.check(N.lib().pam_cnn_loss_grad(ctx.h, _p(params), B, _p(x), _p(target), _p(mask),
+                                      _p(grads), _p(loss)), "pam_cnn_loss_grad")
+    return grads, loss
+
+
+def cnn_adam(ctx: Context, params, grads, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9,
+             beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step in place on params, m, v."""
+    for t, n in ((params, "params"), (grads, "grads"), (m, "m"), (v, "v")):
+        _f32_dev(t, n)
+        if not t.is_contiguous():
+            raise N.PamError(f"{n} must be contiguous")
+    ctx.use_current_stream()
+    N.check(N.lib().pam_cnn_adam(ctx.h, _p(params), _p(grads), _p(m), _p(v), int(step), float(lr),
+                                 float(beta1), float(beta2), float(eps)), "pam_cnn_adam")
+
+
+def grid_patches(ctx: Context, grid, cell_y: Optional[torch.Tensor] = None,
+                 scale: float = 1.0 / 3.0) -> torch.Tensor:
+    """16x16 patches [n, 1, 16, 16] of every owned box (value = scale * y)."""
+    dev = torch.device("cuda", ctx.device)
+    if cell_y is None:
+        cell_y = torch.as_tensor(np.ascontiguousarray(grid.y, np.float64), device=dev)
+    _require_cuda(cell_y, "cell_y")
+    g, brk = _grid_struct(grid)
+    n = C.c_int32()
+    N.check(N.lib().pam_grid_patches(ctx.h, C.byref(g), None, C.c_float(scale), C.byref(n), None),
+            "pam_grid_patches")
+    out = torch.empty((n.value, 1, 16, 16), dtype=torch.float32, device=dev)
+    ctx.use_current_stream()
+    N.check(N.lib().pam_grid_patches(ctx.h, C.byref(g), _p(cell_y), C.c_float(scale), C.byref(n),
+                                     _p(out)), "pam_grid_patches")
+    return out
+
+
+def support_hint(ctx: Context, grid, D: Dictionary, logits: torch.Tensor,
+                 threshold: float = 0.0) -> torch.Tensor:
+    """uint8 [n_sub, m_cap] hint from the support logits of the grid's patches."""
+    logits = _f32_dev(logits, "logits")
+    g, brk = _grid_struct(grid)
+    out = torch.empty((D.n_sub, D.m_cap), dtype=torch.uint8, device=logits.device)
+    ds = D.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_support_hint(ctx.h, C.byref(g), C.byref(ds), _p(logits), float(threshold),
+                                     _p(out)), "pam_support_hint")
+    return out
+
+
+def cnn_labels(ctx: Context, grid, S: Samples, D: Dictionary, beta: torch.Tensor,
+               elem_level: torch.Tensor):
+    """(target, mask) [n, 2, 16, 16] from a cold fit's beta and one round's marks."""
+    g, brk = _grid_struct(grid)
+    n = C.c_int32()
+    N.check(N.lib().pam_grid_patches(ctx.h, C.byref(g), None, C.c_float(1.0), C.byref(n), None),
+            "pam_grid_patches")
+    t = torch.empty((n.value, 2, 16, 16), dtype=torch.float32, device=beta.device)
+    m = torch.empty_like(t)
+    ss, ds = S.struct(), D.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_cnn_labels(ctx.h, C.byref(g), C.byref(ss), C.byref(ds), _p(beta),
+                                   _p(elem_level), _p(t), _p(m)), "pam_cnn_labels")
+    return t, m
+
+
+def cnn_init(seed: int, device) -> torch.Tensor:
+    """He-normal FP32 parameters on the device (seeded, see synth.cnn_init)."""
+    from .synth import cnn_init as _init
+    dev = torch.device("cuda", device) if isinstance(device, int) else device
+    return torch.as_tensor(_init(seed), device=dev)
+
+
+def cnn_train(ctx: Context, params: torch.Tensor, x: torch.Tensor, target: torch.Tensor,
+              mask: torch.Tensor, epochs: int, batch: int = 256, lr: float = 2e-3, seed: int = 0,
+              state=None):
+    """Adam on the masked BCE over shuffled minibatches; params updated in
+    place. Returns (mean loss per epoch, optimizer state (m, v, step))."""
+    n = x.shape[0]
+    if state is None:
+        state = [torch.zeros_like(params), torch.zeros_like(params), 0]
+    m, v = state[0], state[1]
+    grads = torch.empty_like(params)
+    gen = torch.Generator().manual_seed(seed)
+    losses = []
+    for _ in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(x.device)
+        acc = torch.zeros((), dtype=torch.float64, device=x.device)
+        nb = 0
+        for b0 in range(0, n, batch):
+            idx = perm[b0:b0 + batch]
+            _, loss = cnn_loss_grad(ctx, params, x.index_select(0, idx), target.index_select(0, idx),
+                                    mask.index_select(0, idx), grads)
+            state[2] += 1
+            cnn_adam(ctx, params, grads, m, v, state[2], lr)
+            acc += loss
+            nb += 1
+        losses.append(float(acc) / max(nb, 1))
+    return losses, state

@@ -697,7 +697,9 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     int sweeps = 0;
     // warm starts (previous round, caller's point) go straight to the
     // active-set iteration: CD from a good point only densifies the support
-    const int cd_sweeps = a.warm_start ? 0 : a.cd_sweeps;
+    // and a support hint (cold fits only) replaces the warm-up
+    const uint8_t *hint = (a.hint && !a.warm_start) ? a.hint + (size_t)s_id * a.m_cap : nullptr;
+    const int cd_sweeps = (a.warm_start || hint) ? 0 : a.cd_sweeps;
     for (; sweeps < cd_sweeps; ++sweeps) {
         double dmax = 0.0;
         for (int m = 0; m < M; ++m) {
@@ -724,7 +726,6 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     }
     PHASE_MARK(1);
     // ---- signed active set from the start point (and the support hint)
-    const uint8_t *hint = a.hint ? a.hint + (size_t)s_id * a.m_cap : nullptr;
     for (int m = threadIdx.x; m < M; m += kT) {
         int t = (int)sgn(v.beta[m]);
         if (t == 0 && hint && hint[m]) t = (int)sgn(v.g[m]);
@@ -760,6 +761,19 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     for (int m = threadIdx.x; m < M; m += kT)
         if (v.th[m] == 0) v.beta[m] = 0.0;
     __syncthreads();
+    if (hint && v.s > 0) {
+        // signs of the hinted set from the ridge solution on it (lambda1
+        // dropped): near the minimizer's support these are its signs, which
+        // the gradient at zero often is not
+        for (int i = threadIdx.x; i < v.s; i += kT) v.rhs[i] = Gat(v, v.S[i], M);
+        __syncthreads();
+        solve_active(v, v.rhs, v.z, red);
+        for (int i = threadIdx.x; i < v.s; i += kT) {
+            const int t = (int)sgn(v.z[i]);
+            if (t != 0) v.th[v.S[i]] = (signed char)t;
+        }
+        __syncthreads();
+    }
     full_gradient(v);
     PHASE_MARK(2);
 #ifdef PAM_PHASE_PROFILE

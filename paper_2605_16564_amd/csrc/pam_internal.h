@@ -42,6 +42,7 @@ enum Buf {
     BUF_MARK,       // marked element lists [n_sub][n_max] int32
     BUF_EVAL,       // query binning workspace
     BUF_FLAGS,      // per-subdomain flags / counters
+    BUF_CNN,        // network activations, packed weights, gradient partials
     BUF_COUNT
 };
 

@@ -20,9 +20,11 @@ EXPORTS = [
     "pam_create", "pam_destroy", "pam_set_stream", "pam_sync", "pam_last_error", "pam_version",
     "pam_partition_count", "pam_partition_gather", "pam_init_lattice", "pam_fit_subdomains",
     "pam_refine", "pam_eval", "pam_timing_enable", "pam_timing_read",
+    "pam_cnn_param_count", "pam_cnn_forward", "pam_cnn_loss_grad", "pam_cnn_adam",
+    "pam_grid_patches", "pam_support_hint", "pam_cnn_labels",
 ]
 TIMING_KINDS = ["gather", "lattice", "assemble", "gram", "solve", "indicator", "mark",
-                "eval_bin", "eval"]
+                "eval_bin", "eval", "cnn"]
 
 
 class PamGrid(C.Structure):
@@ -104,9 +106,19 @@ def lib():
                                P, C.c_int64, P, C.c_int32, P]
         L.pam_timing_enable.argtypes = [P, C.c_int32]
         L.pam_timing_read.argtypes = [P, P, P, C.c_int32]
+        L.pam_cnn_param_count.argtypes = []
+        L.pam_cnn_forward.argtypes = [P, P, C.c_int32, P, P]
+        L.pam_cnn_loss_grad.argtypes = [P, P, C.c_int32, P, P, P, P, P]
+        L.pam_cnn_adam.argtypes = [P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                   C.c_float]
+        L.pam_grid_patches.argtypes = [P, C.POINTER(PamGrid), P, C.c_float, P, P]
+        L.pam_support_hint.argtypes = [P, C.POINTER(PamGrid), C.POINTER(PamDict), P, C.c_float, P]
+        L.pam_cnn_labels.argtypes = [P, C.POINTER(PamGrid), C.POINTER(PamSamples),
+                                     C.POINTER(PamDict), P, P, P, P]
         for name in EXPORTS:
             if name not in ("pam_last_error", "pam_version"):
                 getattr(L, name).restype = C.c_int
+        L.pam_cnn_param_count.restype = C.c_int64
         _lib = L
     return _lib
 

@@ -264,3 +264,41 @@ def workload(name: str) -> Workload:
         return Workload(name, multifield(), [16, 16], precision="f32",
                         queries_per_field=1_000_000)
     raise KeyError(name)
+
+
+# ---------------------------------------------------------------- network inputs
+CNN_LAYERS = ((1, 32), (32, 32), (32, 32), (32, 2))   # (cin, cout) of the 5x5 layers
+CNN_SCALE = 1.0 / 3.0                                   # patch value = y / 3
+
+
+def cnn_init(seed: int) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / (cin * 25))) and zero biases, float32,
+    per layer w[cout][cin][5][5] then b[cout]."""
+    rng = _rng(seed)
+    parts = []
+    for ci, co in CNN_LAYERS:
+        parts.append(rng.standard_normal(co * ci * 25) * np.sqrt(2.0 / (ci * 25)))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def cnn_batch(seed: int, B: int, p_target: float = 0.4, p_mask: float = 0.7):
+    """Random patches [B,1,16,16] (three-level values / 3 with noise), binary
+    targets and masks [B,2,16,16], float32."""
+    rng = _rng(seed)
+    x = (rng.integers(-1, 2, (B, 1, 16, 16)) * 2 + 1) / 3.0 + 0.05 * rng.standard_normal((B, 1, 16, 16))
+    t = (rng.random((B, 2, 16, 16)) < p_target).astype(np.float32)
+    m = (rng.random((B, 2, 16, 16)) < p_mask).astype(np.float32)
+    return x.astype(np.float32), t, m
+
+
+def random_coefficients(seed: int, n_sub: int, m_cap: int, m) -> np.ndarray:
+    """Coefficients [n_sub, m_cap] of field-like size (normal, std 2) with
+    about a quarter exactly zero; slots >= m[s] are zero."""
+    rng = _rng(seed)
+    b = 2.0 * rng.standard_normal((n_sub, m_cap))
+    b[rng.random((n_sub, m_cap)) < 0.25] = 0.0
+    for s in range(n_sub):
+        b[s, int(m[s]):] = 0.0
+    return b
+

@@ -13,7 +13,7 @@ from paper_2605_16564_amd import synth
 def test_parameter_count():
     # 4 layers of 5x5 convolutions 1-32-32-32-2 with biases
     assert CO.param_count() == 53698
-    assert CO.he_init(0).size == 53698
+    assert synth.cnn_init(0).size == 53698
 
 
 def test_conv_matches_library_correlation():
@@ -30,7 +30,7 @@ def test_conv_matches_library_correlation():
 
 def _problem(seed, B=2):
     rng = np.random.default_rng(seed)
-    p = CO.he_init(seed)
+    p = synth.cnn_init(seed).astype(np.float64)
     p += 0.05 * rng.standard_normal(p.size)          # nonzero biases too
     x = rng.standard_normal((B, 1, 16, 16))
     t = (rng.random((B, 2, 16, 16)) < 0.4).astype(np.float64)

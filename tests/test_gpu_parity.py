@@ -33,17 +33,10 @@ def _t(x):
     return x.detach().cpu().numpy()
 
 
-def _oracle_dict(D: api.Dictionary) -> O.Dictionary:
-    od = O.Dictionary(D.n_sub, D.m_cap, D.dim)
-    od.m = _t(D.m).astype(np.int32)
-    od.c = _t(D.c).ravel().copy()
-    od.sigma = _t(D.sigma).ravel().copy()
-    od.level = _t(D.level).ravel().astype(np.int32)
-    return od
-
-
-def _samples_np(S: api.Samples):
-    return dict(off=S.off_host.copy(), x=_t(S.x), y=_t(S.y), h=_t(S.h))
+def _coefficients(od: O.Dictionary, seed):
+    """Seeded coefficients for the evaluation tests (same values on both sides)."""
+    b = synth.random_coefficients(seed, od.n_sub, od.m_cap, od.m)
+    return b, torch.as_tensor(b, device="cuda")
 
 
 def _margins(x, y, c, sig, beta, l1, l2):
@@ -136,8 +129,8 @@ def test_fit_f64_matches_oracle(ctx, case):
     st = api.stats_to_numpy(stats)
     assert np.all(st["status"] == 0), st
     assert np.all(st["kkt"] < 1e-10), st["kkt"]
-    Sn = _samples_np(S)
-    od = _oracle_dict(D)
+    Sn = O.partition(g)
+    od = O.init_dictionary(g, lat, cap)
     bo, sto, _ = O.fit_batch(Sn, od, L1, L2, cd_sweeps=8)
     assert np.all(sto == 0)
     worst = _check_fit(Sn, od, _t(beta), bo, L1, L2, 1e-9)
@@ -194,13 +187,13 @@ def test_refine_matches_oracle_small(ctx):
     S = api.partition(ctx, g)
     m_cap = 64 + 3 * 3 * 51
     D = api.init_lattice(ctx, g, [8, 8], m_cap=m_cap)
-    od0 = _oracle_dict(D)
+    od0 = O.init_dictionary(g, [8, 8], m_cap)
     tol = 1e-4 * (1 / 64) ** 2
     opts = api.EnetOpts(L1, L2, "f64", cd_sweeps=8)
     ro = api.RefineOpts(k_top=51, max_rounds=3, eps_tol=tol)
     beta, lvl, rounds, rs, stats = api.refine(ctx, S, D, opts, ro)
     torch.cuda.synchronize()
-    Sn = _samples_np(S)
+    Sn = O.partition(g)
     odr, bo, lvo, info = O.refine_batch(Sn, od0, L1, L2, k_top=51, max_rounds=3, m_max=1 << 30,
                                         eps_tol=tol)
     assert np.array_equal(_t(D.m), odr.m)
@@ -223,9 +216,9 @@ def test_refine_matches_oracle_small(ctx):
 # ---------------------------------------------------------------- a10
 def test_eval_matches_oracle(ctx):
     g = synth.circle64()
-    S = api.partition(ctx, g)
     D = api.init_lattice(ctx, g, [16, 16], m_cap=256)
-    beta, _ = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64"))
+    od = O.init_dictionary(g, [16, 16], 256)
+    bnp, beta = _coefficients(od, 41)
     xq = synth.uniform_queries(2, 20000, seed=77, dtype=np.float64)
     xq[:3] = [[0.0, 0.0], [1.0, 1.0], [0.5, 0.5]]   # closed boundary and interior breakpoint
     xq_d = torch.as_tensor(xq, device="cuda")
@@ -233,23 +226,37 @@ def test_eval_matches_oracle(ctx):
     out32 = api.evaluate(ctx, g, D, beta, xq_d.float())
     lin = api.evaluate(ctx, g, D, beta, xq_d, space=1)
     torch.cuda.synchronize()
-    od = _oracle_dict(D)
-    ref, nout = O.evaluate(O.grid_axis_coords(g), od, _t(beta).ravel(), xq)
+    ref, nout = O.evaluate(O.grid_axis_coords(g), od, bnp.ravel(), xq)
     assert nout == 0
     assert np.max(np.abs(_t(out64) - ref)) <= 1e-12 * np.abs(ref).max()
-    assert np.max(np.abs(_t(out32).astype(np.float64) - ref)) <= 2e-4
+    assert np.max(np.abs(_t(out32).astype(np.float64) - ref)) <= 2e-4 * max(1.0, np.abs(ref).max())
     assert np.allclose(_t(lin), 10.0 ** ref, rtol=1e-12)
+
+
+def test_eval_of_a_fitted_field(ctx):
+    """The fitted circle field evaluates to the oracle's own fitted field."""
+    g = synth.circle64()
+    S = api.partition(ctx, g)
+    D = api.init_lattice(ctx, g, [16, 16], m_cap=256)
+    beta, _ = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64"))
+    xq = synth.uniform_queries(2, 5000, seed=78, dtype=np.float64)
+    out = api.evaluate(ctx, g, D, beta, torch.as_tensor(xq, device="cuda"))
+    torch.cuda.synchronize()
+    od = O.init_dictionary(g, [16, 16], 256)
+    bo, sto, _ = O.fit_batch(O.partition(g), od, L1, L2, cd_sweeps=8)
+    ref, _ = O.evaluate(O.grid_axis_coords(g), od, bo.ravel(), xq)
+    assert np.max(np.abs(_t(out) - ref)) <= 1e-9 * np.abs(ref).max()
 
 
 def test_eval_multifield_and_outside(ctx):
     grids = [synth.disc_field(5000 + f, n=32 * (2 + f)) for f in range(3)]
-    parts = [api.partition(ctx, g) for g in grids]
     Ds = [api.init_lattice(ctx, g, [8, 8], m_cap=64) for g in grids]
-    betas = [api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64"))[0] for S, D in zip(parts, Ds)]
+    ods = [O.init_dictionary(g, [8, 8], 64) for g in grids]
+    bs = [_coefficients(od, 60 + f) for f, od in enumerate(ods)]
     Dall = api.Dictionary(sum(D.n_sub for D in Ds), 2, 64, torch.cat([D.m for D in Ds]),
                           torch.cat([D.c for D in Ds]), torch.cat([D.sigma for D in Ds]),
                           torch.cat([D.level for D in Ds]))
-    ball = torch.cat(betas)
+    ball = torch.cat([b[1] for b in bs])
     counts = [3000, 1, 2500]
     xs = [synth.uniform_queries(2, n, seed=90 + f, dtype=np.float64) for f, n in enumerate(counts)]
     xs[2][:2] = [[-0.1, 0.5], [0.5, 1.5]]            # outside the domain
@@ -261,7 +268,7 @@ def test_eval_multifield_and_outside(ctx):
     assert int(nout.item()) == 2
     q0 = 0
     for f, g in enumerate(grids):
-        ref, n_o = O.evaluate(O.grid_axis_coords(g), _oracle_dict(Ds[f]), _t(betas[f]).ravel(), xs[f])
+        ref, n_o = O.evaluate(O.grid_axis_coords(g), ods[f], bs[f][0].ravel(), xs[f])
         got = o[q0:q0 + counts[f]]
         assert np.array_equal(np.isnan(got), np.isnan(ref))
         ok = ~np.isnan(ref)
