@@ -163,9 +163,19 @@ typedef struct {
     int32_t cd_sweeps;  /* CD sweeps done                                     */
     int32_t iters;      /* active-set iterations                              */
     int32_t support;    /* number of nonzero coefficients                     */
-    double kkt;         /* KKT residual of the returned beta (FP64)           */
+    double kkt;         /* KKT residual of the returned beta: max over m of
+                           |g_m - lambda1 sign(beta_m)| (active) or
+                           (|g_m| - lambda1)+ (inactive), g the FP64 gradient
+                           of the smooth part (FP32/BF16 modes: from the FP64
+                           design, not the rounded Gram)                     */
     double stream_bytes; /* bytes of Gram rows and active-block inverse the
                             solve had to stream (algorithmic traffic)        */
+    int32_t polish;     /* FP32/BF16 Gram: FP64 conjugate-gradient steps of the
+                           polish on the final support (negative: stopped
+                           early on a sign change or lost curvature, the kkt
+                           field then shows how far from the FP64 minimizer);
+                           0 for FP64                                         */
+    int32_t reserved;
 } pam_fit_stats;
 
 /* a3-a6. For every subdomain: Gaussian RBF design at the samples (Eq.

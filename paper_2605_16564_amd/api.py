@@ -205,7 +205,8 @@ class EnetOpts:
 
 STATS_DTYPE = np.dtype([("status", np.int32), ("cd_sweeps", np.int32), ("iters", np.int32),
                         ("support", np.int32), ("kkt", np.float64),
-                        ("stream_bytes", np.float64)])
+                        ("stream_bytes", np.float64), ("polish", np.int32),
+                        ("reserved", np.int32)])
 
 
 def new_stats(n_sub, device):

@@ -34,10 +34,16 @@ static constexpr int kTile = 128;  // rows staged in LDS per bordering tile
 static constexpr int kFz = 8;      // coordinates frozen before one batched downdate
 static constexpr int kQ = 16;      // rows of the low-rank update scratch (>= kB, kFz)
 static constexpr int kPass = kR * kT;
+static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the polish
 
 __host__ __device__ size_t solve_ldh(int m_cap) { return (size_t)round_up(m_cap, kPass); }
 __host__ __device__ size_t solve_h_elems(int m_cap) { return (size_t)(m_cap + 1) * solve_ldh(m_cap); }
-__host__ __device__ size_t solve_scratch_elems(int m_cap) { return (size_t)3 * kQ * m_cap; }
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad) {
+    // blocked-bordering rows [3][kQ][m_cap], then for the FP64 phase of the
+    // low-precision modes: -1/(2 sigma^2) [m_cap], three CG vectors [3][m_cap]
+    // and two per-sample vectors [2][npad]
+    return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad;
+}
 size_t solve_lds_bytes(int m_cap) { return (size_t)49 * round_up(m_cap, 8) + 64; }
 
 // ---------------------------------------------------------------- reductions
@@ -615,6 +621,131 @@ __device__ bool activate(Sv<TG> &v, int *list, int n, Red &red, double *cinv, in
     return any;
 }
 
+// ---------------------------------------------------------------- FP64 phase
+// Low-precision Gram modes: the first pass of the iteration solves the
+// problem whose design and Gram are rounded to FP32 (or BF16). A second pass
+// of the same iteration then finishes the FP64 problem from that point:
+// gradients come from the Shepard-normalized FP64 design W64, recomputed
+// from (x, c, sigma) for every product (nothing of it is stored), and the
+// active solve (G64_SS + lambda2 I) z = b64_S - lambda1 theta_S is done by
+// conjugate gradients preconditioned with H, which keeps being the inverse of
+// the low-precision active block. The returned KKT residual certifies the
+// FP64 problem.
+struct Pol {
+    const double *x, *y, *c, *sg;
+    int N, dim;
+    double *w;            // [M] -1 / (2 sigma_m^2)
+    double *p, *q, *t;    // [m_cap] CG vectors by active position
+    double *u;            // [N] per-sample vector
+    double *is;           // [N] 1 / s_j
+};
+
+__device__ __forceinline__ double phi64(const Pol &P, int j, int m) {
+    double d2 = 0.0;
+    for (int a = 0; a < P.dim; ++a) {
+        const double d = P.x[(size_t)j * P.dim + a] - P.c[(size_t)m * P.dim + a];
+        d2 += d * d;
+    }
+    return exp(d2 * P.w[m]);
+}
+
+// s_j over all centers, the residual e_j = y_j - (W64 beta)_j and
+// u_j = e_j / s_j; then g_m = (W64' e)_m - lambda2 beta_m for every m < M.
+template <typename TG>
+__device__ __noinline__ void grad64(Sv<TG> &v, const Pol &P) {
+    const int M = v.M;
+    for (int j = threadIdx.x; j < P.N; j += kT) {
+        double sj = 0.0, num = 0.0;
+        for (int m = 0; m < M; ++m) {
+            const double f = phi64(P, j, m);
+            sj += f;
+            num += f * v.beta[m];
+        }
+        const double is = 1.0 / sj;
+        P.is[j] = is;
+        P.u[j] = (P.y[j] - num * is) * is;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < M; m += kT) {
+        double acc = 0.0;
+        for (int j = 0; j < P.N; ++j) acc += phi64(P, j, m) * P.u[j];
+        v.g[m] = acc - v.l2 * v.beta[m];
+    }
+    __syncthreads();
+}
+
+// q = (W64_S' W64_S + lambda2 I) p over active positions (1 / s_j from the
+// last grad64, which does not depend on beta).
+template <typename TG>
+__device__ void apply64(Sv<TG> &v, const Pol &P, const double *p, double *q) {
+    const int s = v.s;
+    for (int j = threadIdx.x; j < P.N; j += kT) {
+        double t = 0.0;
+        for (int i = 0; i < s; ++i) t += phi64(P, j, v.S[i]) * p[i];
+        const double is = P.is[j];
+        P.u[j] = t * is * is;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < s; i += kT) {
+        const int m = v.S[i];
+        double acc = 0.0;
+        for (int j = 0; j < P.N; ++j) acc += phi64(P, j, m) * P.u[j];
+        q[i] = acc + v.l2 * p[i];
+    }
+    __syncthreads();
+}
+
+// z (by position) solves the FP64 reduced system on the signed active set,
+// by CG from beta_S whose residual g_S - lambda1 theta_S needs the FP64
+// gradient at beta in v.g. No frozen positions may be pending. Returns the
+// number of products with the FP64 block.
+template <typename TG>
+__device__ __noinline__ int cg64(Sv<TG> &v, const Pol &P, Red &red, double tol, double *z) {
+    const int s = v.s;
+    double *r = v.rhs;
+    double rm = 0.0;
+    for (int i = threadIdx.x; i < s; i += kT) {
+        const int k = v.S[i];
+        z[i] = v.beta[k];
+        r[i] = v.g[k] - v.l1 * (double)v.th[k];
+        rm = fmax(rm, fabs(r[i]));
+    }
+    if (bmax(rm, red) <= tol) return 0;
+    solve_active(v, r, P.t, red);
+    double rz = 0.0;
+    for (int i = threadIdx.x; i < s; i += kT) {
+        P.p[i] = P.t[i];
+        rz += r[i] * P.t[i];
+    }
+    rz = bsum(rz, red);
+    int it = 0;
+    while (it < kPolishMax) {
+        apply64(v, P, P.p, P.q);
+        ++it;
+        double pq = 0.0;
+        for (int i = threadIdx.x; i < s; i += kT) pq += P.p[i] * P.q[i];
+        pq = bsum(pq, red);
+        if (!(pq > 0.0) || !(rz > 0.0)) break;
+        const double al = rz / pq;
+        double rmx = 0.0;
+        for (int i = threadIdx.x; i < s; i += kT) {
+            z[i] += al * P.p[i];
+            r[i] -= al * P.q[i];
+            rmx = fmax(rmx, fabs(r[i]));
+        }
+        if (bmax(rmx, red) <= tol) break;
+        solve_active(v, r, P.t, red);
+        double rzn = 0.0;
+        for (int i = threadIdx.x; i < s; i += kT) rzn += r[i] * P.t[i];
+        rzn = bsum(rzn, red);
+        const double bt = rzn / rz;
+        rz = rzn;
+        for (int i = threadIdx.x; i < s; i += kT) P.p[i] = P.t[i] + bt * P.p[i];
+        __syncthreads();
+    }
+    return it;
+}
+
 template <typename TG>
 __global__ void __launch_bounds__(kT)
 k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
@@ -639,7 +770,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.l1 = a.lambda1_sub ? a.lambda1_sub[s_id] : a.lambda1;
     v.l2 = a.lambda2_sub ? a.lambda2_sub[s_id] : a.lambda2;
     v.H = Hall + (size_t)loc * solve_h_elems(a.m_cap);
-    double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap);
+    double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap, a.npad);
     v.Ag = sc;
     v.U = sc + (size_t)kQ * a.m_cap;
     v.V = sc + (size_t)2 * kQ * a.m_cap;
@@ -672,7 +803,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         if (st && threadIdx.x == 0) {
             st->status = (flags[s_id] & 1) ? PAM_ST_UNDERFLOW : PAM_ST_EMPTY;
             st->cd_sweeps = 0; st->iters = 0; st->support = 0; st->kkt = 0.0;
-            st->stream_bytes = 0.0;
+            st->stream_bytes = 0.0; st->polish = 0; st->reserved = 0;
         }
         return;
     }
@@ -786,19 +917,62 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         for (int m = threadIdx.x; m < M; m += kT) t = fmax(t, fabs(Gat(v, m, M)));
         return t;
     }(), red);
-    const double viol_tol = v.l1 * (1.0 + 1e-12) + 1e-14 * bnorm;
-    int it = 0, status = PAM_ST_NOCONV, refines = 0;
-    bool skip_solve = false;
-    while (it < a.max_iter) {
+    int it = 0, status = PAM_ST_NOCONV, refines = 0, n_cg = 0;
+    bool skip_solve = false, ran_ex = false;
+    constexpr bool kLow = sizeof(TG) < sizeof(double);
+    Pol P{};
+    if (kLow) {
+        const int64_t j0 = a.off[s_id];
+        P.x = a.x + (size_t)j0 * a.dim;
+        P.y = a.y + j0;
+        P.c = a.c + (size_t)s_id * a.m_cap * a.dim;
+        P.sg = a.sigma + (size_t)s_id * a.m_cap;
+        P.N = (int)(a.off[s_id + 1] - j0);
+        P.dim = a.dim;
+        P.w = sc + (size_t)3 * kQ * a.m_cap;
+        P.p = P.w + a.m_cap;
+        P.q = P.p + a.m_cap;
+        P.t = P.q + a.m_cap;
+        P.u = P.t + a.m_cap;
+        P.is = P.u + a.npad;
+        for (int m = threadIdx.x; m < M; m += kT) P.w[m] = -0.5 / (P.sg[m] * P.sg[m]);
+        __syncthreads();
+    }
+    // pass 0 solves the problem of the stored Gram; low-precision modes then
+    // finish the FP64 problem from its end point (pass 1)
+    for (int phase = 0; phase < (kLow ? 2 : 1); ++phase) {
+    const bool ex = phase == 1;
+    if (ex) {
+        if (status != PAM_ST_OK) break;
+        __syncthreads();
+        compact(v, tile);
+        grad64(v, P);
+        status = PAM_ST_NOCONV;
+        refines = 0;
+        skip_solve = false;
+        ran_ex = true;
+    }
+    // the FP64 gradient is a recomputed sum of N terms: its tolerances
+    const double gtol = (ex ? 1e-12 : 1e-15) * fmax(1.0, bnorm);
+    const double viol_tol = v.l1 * (1.0 + 1e-12) + (ex ? 1e-12 : 1e-14) * bnorm;
+    // the FP64 pass starts next to the minimizer; a bound on its length
+    // guards against cycling on margins at the FP64 rounding level
+    const int it_end = ex ? min(a.max_iter, it + 2 * M + 100) : a.max_iter;
+    while (it < it_end) {
         ++it;
         if (v.s > 0 && !skip_solve) {
+            if (ex) compact(v, tile);   // the CG solve runs on live positions only
             const int s = v.s;
-            for (int i = threadIdx.x; i < s; i += kT) {
-                const int k = v.S[i];
-                v.rhs[i] = Gat(v, k, M) - v.l1 * (double)v.th[k];
+            if (ex) {
+                n_cg += cg64(v, P, red, gtol, v.z);
+            } else {
+                for (int i = threadIdx.x; i < s; i += kT) {
+                    const int k = v.S[i];
+                    v.rhs[i] = Gat(v, k, M) - v.l1 * (double)v.th[k];
+                }
+                __syncthreads();
+                solve_active(v, v.rhs, v.z, red);
             }
-            __syncthreads();
-            solve_active(v, v.rhs, v.z, red);
             PHASE_MARK(3);
             bool mine = true;
             for (int i = threadIdx.x; i < s; i += kT)
@@ -909,7 +1083,8 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
             compact(v, tile);
         }
         skip_solve = false;
-        full_gradient(v);
+        if (ex) grad64(v, P);
+        else full_gradient(v);
         PHASE_MARK(6);
 #ifdef PAM_PHASE_PROFILE
         ++n_cons;
@@ -954,11 +1129,12 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
             rp = fmax(rp, fabs(v.rhs[i]));
         }
         const double rmax = bmax(rp, red);
-        if (s == 0 || rmax <= 1e-15 * fmax(1.0, bnorm) || refines >= 3) {
+        if (s == 0 || rmax <= gtol || refines >= 3) {
             status = PAM_ST_OK;
             break;
         }
         ++refines;
+        if (ex) continue;   // the next CG solve starts from beta: a refinement step
         solve_active(v, v.rhs, v.z, red);   // correction H r
         bool keep_mine = true;
         for (int i = threadIdx.x; i < s; i += kT) {
@@ -971,9 +1147,15 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
             skip_solve = true;
         }
     }
+    }   // phase
     // ---- outputs and KKT residual
     __syncthreads();
-    full_gradient(v);
+    if constexpr (kLow) {
+        if (!ran_ex) full_gradient(v);
+        else if (status != PAM_ST_OK) grad64(v, P);
+    } else {
+        full_gradient(v);
+    }
     double kk = 0.0, nz = 0.0;
     for (int m = threadIdx.x; m < M; m += kT) {
         const double b = v.beta[m];
@@ -997,6 +1179,8 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         st->support = (int)nzs;
         st->kkt = kkt;
         st->stream_bytes = v.bytes;
+        st->polish = n_cg;
+        st->reserved = 0;
     }
 }
 

@@ -133,7 +133,7 @@ pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_gram(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a);
 __host__ __device__ size_t solve_h_elems(int m_cap);
-__host__ __device__ size_t solve_scratch_elems(int m_cap);
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad);
 
 struct RefineArgs {
     int32_t n_sub, dim, m_cap, n_max;

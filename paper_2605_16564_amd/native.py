@@ -55,7 +55,8 @@ class PamEnetOpts(C.Structure):
 
 class PamFitStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("cd_sweeps", C.c_int32), ("iters", C.c_int32),
-                ("support", C.c_int32), ("kkt", C.c_double), ("stream_bytes", C.c_double)]
+                ("support", C.c_int32), ("kkt", C.c_double), ("stream_bytes", C.c_double),
+                ("polish", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PamRefineOpts(C.Structure):
