@@ -157,7 +157,7 @@ __device__ __forceinline__ double Gat(const Sv<TG> &v, int i, int j) {
 // out_i = sum_j H[j][i] in_j, i < s (H symmetric; rows streamed coalesced,
 // four rows in flight per thread).
 template <int R, typename TG>
-__device__ void hgemv_r(Sv<TG> &v, const double *in, double *out) {
+__device__ __forceinline__ void hgemv_r(Sv<TG> &v, const double *in, double *out) {
     constexpr int kRows = 8;   // rows loaded before use
     const int s = v.s;
     for (int base = 0; base < s; base += R * kT) {
@@ -196,7 +196,7 @@ __device__ void hgemv_r(Sv<TG> &v, const double *in, double *out) {
 // out_i = sum_j H[j][i] in_j, i < s (H symmetric; rows streamed coalesced,
 // up to four outputs per thread so that more rows are in flight).
 template <typename TG>
-__device__ void hgemv(Sv<TG> &v, const double *in, double *out) {
+__device__ __forceinline__ void hgemv(Sv<TG> &v, const double *in, double *out) {
     v.bytes += 8.0 * (double)v.s * (double)v.s;
     if (v.s <= kT) hgemv_r<1>(v, in, out);
     else if (v.s <= 2 * kT) hgemv_r<2>(v, in, out);
@@ -207,7 +207,7 @@ __device__ void hgemv(Sv<TG> &v, const double *in, double *out) {
 // thread-owned columns j keep Ur[.][j] in registers, rows i stream in
 // batches of eight with Vr[.][i] staged in LDS tiles.
 template <int NQ, typename TG>
-__device__ void hupdate(Sv<TG> &v, int s, int nq, const double *Vr, const double *Ur, double *tile) {
+__device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *Vr, const double *Ur, double *tile) {
     for (int jb = 0; jb < s; jb += kT) {
         const int j = jb + threadIdx.x;
         const bool live = j < s;
@@ -258,7 +258,7 @@ __device__ void hupdate(Sv<TG> &v, int s, int nq, const double *Vr, const double
 // Rows of A_SB and of V = U C^-1 are staged through LDS in tiles so that
 // the streaming passes over H read them as broadcasts.
 template <typename TG>
-__device__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile) {
+__device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile) {
     const int s = v.s;
     v.bytes += 24.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
     for (int q = 0; q < nb; ++q)
@@ -385,7 +385,7 @@ __device__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *ci
 
 // Drop active position p (no update of H): the last position moves into p.
 template <typename TG>
-__device__ void drop_position(Sv<TG> &v, int p) {
+__device__ __forceinline__ void drop_position(Sv<TG> &v, int p) {
     const int last = v.s - 1;
     const int kp = v.S[p];
     if (p != last) {
@@ -412,7 +412,7 @@ __device__ void drop_position(Sv<TG> &v, int p) {
 // H. With W = H[:, R] (rows of H, by symmetry) and C = H[R, R], the inverse of
 // the remaining block is H - W C^-1 W'; C^-1 grows by bordering.
 template <typename TG>
-__device__ void freeze(Sv<TG> &v, int p) {
+__device__ __forceinline__ void freeze(Sv<TG> &v, int p) {
     const int s = v.s, r = v.r;
     v.bytes += 8.0 * s;
     for (int i = threadIdx.x; i < s; i += kT) v.U[(size_t)r * v.m_cap + i] = v.H[(size_t)p * v.ldh + i];
@@ -443,7 +443,7 @@ __device__ void freeze(Sv<TG> &v, int p) {
 // Apply the frozen set to H (one rank-r pass: H <- H - W' C^-1 W) and drop
 // the frozen positions from the active list.
 template <typename TG>
-__device__ void compact(Sv<TG> &v, double *tile) {
+__device__ __forceinline__ void compact(Sv<TG> &v, double *tile) {
     const int r = v.r;
     if (r == 0) return;
     const int s = v.s;
@@ -480,7 +480,7 @@ __device__ void compact(Sv<TG> &v, double *tile) {
 // z = (inverse of the active block without the frozen positions) * in,
 // with in and z zero at frozen positions.
 template <typename TG>
-__device__ void solve_active(Sv<TG> &v, double *in, double *out, Red &red) {
+__device__ __forceinline__ void solve_active(Sv<TG> &v, double *in, double *out, Red &red) {
     const int s = v.s, r = v.r;
     if (r > 0) {
         if ((int)threadIdx.x < r) in[v.Rp[threadIdx.x]] = 0.0;
@@ -521,7 +521,7 @@ __device__ void solve_active(Sv<TG> &v, double *in, double *out, Red &red) {
 // Remove active position p: H <- H_{-p,-p} - h h' / H_pp (h = H[-p, p]),
 // then the last position moves into p.
 template <typename TG>
-__device__ void remove_at(Sv<TG> &v, int p) {
+__device__ __forceinline__ void remove_at(Sv<TG> &v, int p) {
     const int s = v.s;
     v.bytes += 16.0 * (double)s * (double)s;
     const double hp = v.H[(size_t)p * v.ldh + p];
@@ -568,25 +568,59 @@ __device__ void remove_at(Sv<TG> &v, int p) {
 }
 
 // g = b - G beta - lambda2 beta over all coordinates (rows of the active
-// set), one coordinate per thread and pass, sixteen Gram rows in flight.
+// set). Each thread owns one 16-byte group of adjacent coordinates (four
+// FP32 or two FP64 Gram entries per load) and keeps sixteen Gram rows in
+// flight: the pass is bound by bytes in flight per CU.
+template <typename TG> struct Vec16;
+template <> struct Vec16<float> { using type = float4; };
+template <> struct Vec16<double> { using type = double2; };
+
 template <typename TG>
-__device__ void full_gradient(Sv<TG> &v) {
+__device__ __forceinline__ void full_gradient(Sv<TG> &v) {
     constexpr int kRows = 16;
-    const int s = v.s;
-    v.bytes += (double)s * v.M * sizeof(TG);
-    for (int m = threadIdx.x; m < v.M; m += kT) {
-        double acc = Gat(v, m, v.M) - v.l2 * v.beta[m];
-        const TG *col = v.G + m;
+    constexpr int VW = 16 / (int)sizeof(TG);
+    using V = typename Vec16<TG>::type;
+    const int s = v.s, M = v.M;
+    v.bytes += (double)s * M * sizeof(TG);
+    const int ncol = (M + VW - 1) / VW;
+    const size_t ldv = (size_t)v.mpad / VW;   // mpad is a multiple of 64
+    for (int cb = threadIdx.x; cb < ncol; cb += kT) {
+        const int m0 = cb * VW;
+        double acc[VW];
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+            const int m = m0 + c;
+            acc[c] = m < M ? Gat(v, m, M) - v.l2 * v.beta[m] : 0.0;
+        }
+        const V *col = reinterpret_cast<const V *>(v.G + m0);
         int i = 0;
         for (; i + kRows <= s; i += kRows) {
-            double gv[kRows];
+            V gv[kRows];
+            double bb[kRows];
 #pragma unroll
-            for (int e = 0; e < kRows; ++e) gv[e] = (double)col[(size_t)v.S[i + e] * v.mpad];
+            for (int e = 0; e < kRows; ++e) {
+                const int k = v.S[i + e];
+                gv[e] = col[(size_t)k * ldv];
+                bb[e] = v.beta[k];
+            }
 #pragma unroll
-            for (int e = 0; e < kRows; ++e) acc -= gv[e] * v.beta[v.S[i + e]];
+            for (int e = 0; e < kRows; ++e) {
+                const TG *g = reinterpret_cast<const TG *>(&gv[e]);
+#pragma unroll
+                for (int c = 0; c < VW; ++c) acc[c] -= (double)g[c] * bb[e];
+            }
         }
-        for (; i < s; ++i) acc -= (double)col[(size_t)v.S[i] * v.mpad] * v.beta[v.S[i]];
-        v.g[m] = acc;
+        for (; i < s; ++i) {
+            const int k = v.S[i];
+            const V gv = col[(size_t)k * ldv];
+            const TG *g = reinterpret_cast<const TG *>(&gv);
+            const double bk = v.beta[k];
+#pragma unroll
+            for (int c = 0; c < VW; ++c) acc[c] -= (double)g[c] * bk;
+        }
+#pragma unroll
+        for (int c = 0; c < VW; ++c)
+            if (m0 + c < M) v.g[m0 + c] = acc[c];
     }
     __syncthreads();
 }
@@ -595,7 +629,7 @@ __device__ void full_gradient(Sv<TG> &v) {
 // Coordinates that cannot enter are deactivated. Returns false if none of a
 // requested set could enter.
 template <typename TG>
-__device__ bool activate(Sv<TG> &v, int *list, int n, Red &red, double *cinv, int *blk, double *tile) {
+__device__ __forceinline__ bool activate(Sv<TG> &v, int *list, int n, Red &red, double *cinv, int *blk, double *tile) {
     bool any = false;
     for (int b0 = 0; b0 < n; b0 += kB) {
         const int nb = min(kB, n - b0);
@@ -640,59 +674,99 @@ struct Pol {
     double *is;           // [N] 1 / s_j
 };
 
-__device__ __forceinline__ double phi64(const Pol &P, int j, int m) {
-    double d2 = 0.0;
-    for (int a = 0; a < P.dim; ++a) {
-        const double d = P.x[(size_t)j * P.dim + a] - P.c[(size_t)m * P.dim + a];
-        d2 += d * d;
+// Per-sample pass: for samples j (two per thread at a time, for independent
+// exponentials in flight) over the centers k(i), i < n:
+// sum_i phi_{j,k(i)} and sum_i phi_{j,k(i)} p_i.
+template <typename K, typename F>
+__device__ __forceinline__ void sample_pass(const Pol &P, int n, K key, const double *p, F out) {
+    for (int j0 = threadIdx.x; j0 < P.N; j0 += 2 * kT) {
+        const int j1 = min(j0 + kT, P.N - 1);
+        double x0[3], x1[3];   // unused dimensions are zero on both sides
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            x0[a] = a < P.dim ? P.x[(size_t)j0 * P.dim + a] : 0.0;
+            x1[a] = a < P.dim ? P.x[(size_t)j1 * P.dim + a] : 0.0;
+        }
+        double s0 = 0.0, n0 = 0.0, s1 = 0.0, n1 = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const int m = key(i);
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double ca = a < P.dim ? P.c[(size_t)m * P.dim + a] : 0.0;
+                d0 += (x0[a] - ca) * (x0[a] - ca);
+                d1 += (x1[a] - ca) * (x1[a] - ca);
+            }
+            const double w = P.w[m], pv = p[i];
+            const double f0 = exp(d0 * w), f1 = exp(d1 * w);
+            s0 += f0;
+            n0 += f0 * pv;
+            s1 += f1;
+            n1 += f1 * pv;
+        }
+        out(j0, s0, n0);
+        if (j0 + kT < P.N) out(j0 + kT, s1, n1);
     }
-    return exp(d2 * P.w[m]);
+    __syncthreads();
+}
+
+// Per-center pass: for items i < n (center k(i)), four per thread at a time,
+// over all samples: sum_j phi_{j,k(i)} u_j.
+template <typename K, typename F>
+__device__ __forceinline__ void center_pass(const Pol &P, int n, K key, F out) {
+    constexpr int R = 4;
+    for (int i0 = threadIdx.x; i0 < n; i0 += R * kT) {
+        double c[R][3], w[R], acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int m = key(min(i0 + r * kT, n - 1));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) c[r][a] = a < P.dim ? P.c[(size_t)m * P.dim + a] : 0.0;
+            w[r] = P.w[m];
+            acc[r] = 0.0;
+        }
+        for (int j = 0; j < P.N; ++j) {
+            double xj[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xj[a] = a < P.dim ? P.x[(size_t)j * P.dim + a] : 0.0;
+            const double uj = P.u[j];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double d = 0.0;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) d += (xj[a] - c[r][a]) * (xj[a] - c[r][a]);
+                acc[r] += exp(d * w[r]) * uj;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (i0 + r * kT < n) out(i0 + r * kT, acc[r]);
+    }
+    __syncthreads();
 }
 
 // s_j over all centers, the residual e_j = y_j - (W64 beta)_j and
 // u_j = e_j / s_j; then g_m = (W64' e)_m - lambda2 beta_m for every m < M.
 template <typename TG>
-__device__ __noinline__ void grad64(Sv<TG> &v, const Pol &P) {
-    const int M = v.M;
-    for (int j = threadIdx.x; j < P.N; j += kT) {
-        double sj = 0.0, num = 0.0;
-        for (int m = 0; m < M; ++m) {
-            const double f = phi64(P, j, m);
-            sj += f;
-            num += f * v.beta[m];
-        }
+__device__ __forceinline__ void grad64(Sv<TG> &v, const Pol &P) {
+    sample_pass(P, v.M, [](int i) { return i; }, v.beta, [&](int j, double sj, double num) {
         const double is = 1.0 / sj;
         P.is[j] = is;
         P.u[j] = (P.y[j] - num * is) * is;
-    }
-    __syncthreads();
-    for (int m = threadIdx.x; m < M; m += kT) {
-        double acc = 0.0;
-        for (int j = 0; j < P.N; ++j) acc += phi64(P, j, m) * P.u[j];
-        v.g[m] = acc - v.l2 * v.beta[m];
-    }
-    __syncthreads();
+    });
+    center_pass(P, v.M, [](int i) { return i; }, [&](int m, double acc) { v.g[m] = acc - v.l2 * v.beta[m]; });
 }
 
 // q = (W64_S' W64_S + lambda2 I) p over active positions (1 / s_j from the
 // last grad64, which does not depend on beta).
 template <typename TG>
-__device__ void apply64(Sv<TG> &v, const Pol &P, const double *p, double *q) {
-    const int s = v.s;
-    for (int j = threadIdx.x; j < P.N; j += kT) {
-        double t = 0.0;
-        for (int i = 0; i < s; ++i) t += phi64(P, j, v.S[i]) * p[i];
+__device__ __forceinline__ void apply64(Sv<TG> &v, const Pol &P, const double *p, double *q) {
+    const int *S = v.S;
+    sample_pass(P, v.s, [S](int i) { return S[i]; }, p, [&](int j, double, double t) {
         const double is = P.is[j];
         P.u[j] = t * is * is;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < s; i += kT) {
-        const int m = v.S[i];
-        double acc = 0.0;
-        for (int j = 0; j < P.N; ++j) acc += phi64(P, j, m) * P.u[j];
-        q[i] = acc + v.l2 * p[i];
-    }
-    __syncthreads();
+    });
+    center_pass(P, v.s, [S](int i) { return S[i]; }, [&](int i, double acc) { q[i] = acc + v.l2 * p[i]; });
 }
 
 // z (by position) solves the FP64 reduced system on the signed active set,
@@ -700,7 +774,7 @@ __device__ void apply64(Sv<TG> &v, const Pol &P, const double *p, double *q) {
 // gradient at beta in v.g. No frozen positions may be pending. Returns the
 // number of products with the FP64 block.
 template <typename TG>
-__device__ __noinline__ int cg64(Sv<TG> &v, const Pol &P, Red &red, double tol, double *z) {
+__device__ __forceinline__ int cg64(Sv<TG> &v, const Pol &P, Red &red, double tol, double *z) {
     const int s = v.s;
     double *r = v.rhs;
     double rm = 0.0;
@@ -793,7 +867,8 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
 #ifdef PAM_PHASE_PROFILE
     long long ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     long long ph_last = wall_clock64();
-    int n_rm = 0, n_add = 0, n_ls = 0, n_cons = 0;
+    int n_rm = 0, n_add = 0, n_ls = 0, n_cons = 0, it_ex0 = 0;
+    long long t_ex0 = 0;
 #endif
     double *beta_out = a.beta + (size_t)s_id * a.m_cap;
     pam_fit_stats *st = a.stats ? a.stats + s_id : nullptr;
@@ -951,6 +1026,10 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         refines = 0;
         skip_solve = false;
         ran_ex = true;
+#ifdef PAM_PHASE_PROFILE
+        it_ex0 = it;
+        t_ex0 = wall_clock64();
+#endif
     }
     // the FP64 gradient is a recomputed sum of N terms: its tolerances
     const double gtol = (ex ? 1e-12 : 1e-15) * fmax(1.0, bnorm);
@@ -1168,9 +1247,10 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     for (int m = threadIdx.x; m < a.m_cap; m += kT) beta_out[m] = m < M ? v.beta[m] : 0.0;
 #ifdef PAM_PHASE_PROFILE
     if (threadIdx.x == 0)
-        printf("PH sub=%d M=%d s_init=%d s=%d it=%d cons=%d ls=%d rm=%d add=%d sweeps=%d us: grad0=%.0f cd=%.0f init=%.0f solve=%.0f ls=%.0f rm=%.0f fullg=%.0f act=%.0f\n",
-               s_id, M, s_init, v.s, it, n_cons, n_ls, n_rm, n_add, sweeps, ph[0] * 0.01, ph[1] * 0.01,
-               ph[2] * 0.01, ph[3] * 0.01, ph[4] * 0.01, ph[5] * 0.01, ph[6] * 0.01, ph[7] * 0.01);
+        printf("PH sub=%d M=%d s_init=%d s=%d it=%d cons=%d ls=%d rm=%d add=%d sweeps=%d it_ex=%d cg=%d us: grad0=%.0f cd=%.0f init=%.0f solve=%.0f ls=%.0f rm=%.0f fullg=%.0f act=%.0f ex=%.0f\n",
+               s_id, M, s_init, v.s, it, n_cons, n_ls, n_rm, n_add, sweeps, ran_ex ? it - it_ex0 : 0, n_cg,
+               ph[0] * 0.01, ph[1] * 0.01, ph[2] * 0.01, ph[3] * 0.01, ph[4] * 0.01, ph[5] * 0.01, ph[6] * 0.01,
+               ph[7] * 0.01, ran_ex ? (wall_clock64() - t_ex0) * 0.01 : 0.0);
 #endif
     if (st && threadIdx.x == 0) {
         st->status = status;
