@@ -8,9 +8,18 @@ subdomain and round (a3-a9), then evaluation of the fitted field at the
 4x4 Gauss points of every cell (a10, mesh transfer to a finer quadrature).
 
 Default workload `facies256`: 256x256 three-facies field, 8x8 subdomains,
-12x12 initial centers, up to 3 enrichment rounds (K_top = 204). The metric is
-subdomain fits per second (one fit = one subdomain-round); evaluation
-throughput and the field's L1 error are reported beside it.
+12x12 initial centers, up to 3 enrichment rounds (K_top = 204), FP32 design
+and Gram with the FP64 pass. The metric is subdomain fits per second (one fit
+= one subdomain-round); evaluation throughput and the field's L1 error are
+reported beside it.
+
+The learned warm start (on by default) is trained before the timed region on
+fields of other seeds; inside the step the network's forward pass and the
+hint map run before the first fit. Beside the timed step the record holds:
+the comparator (the plain GPU fit: one launch per subdomain and kernel, every
+refit from zero, no hint), the learned part's training throughput and gain,
+the error of the GPU coefficients and field against the FP64 oracle on the
+CPU sample, and the oracle's own throughput on that sample.
 
 Prints one JSON line. `--gpus N` with N > 1 is refused: this build runs on
 one GPU.
@@ -45,8 +54,10 @@ def parse():
     ap.add_argument("--precision", default=None, help="Gram precision override (f64|f32|bf16)")
     ap.add_argument("--cd-sweeps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-subdomains", type=int, default=4)
+    ap.add_argument("--cpu-sample-subdomains", type=int, default=8)
     ap.add_argument("--cpu-sample-rounds", type=int, default=1)
+    ap.add_argument("--no-learned", action="store_true", help="no learned warm start")
+    ap.add_argument("--no-comparator", action="store_true")
     return ap.parse_args()
 
 
@@ -54,7 +65,8 @@ def cpu_baseline(grid, wl, n_sub_sample: int, rounds: int):
     """Time the FP64 CPU oracle on a bounded sample of the same workload:
     Alg. 1 with `rounds` enrichment rounds on `n_sub_sample` interior
     subdomains, one OpenMP thread per subdomain (the full three rounds take
-    about 290 s per subdomain on one core). Returns the JSON record."""
+    about 290 s per subdomain on one core). Returns the JSON record and the
+    oracle's results (first subdomain, dictionary, coefficients)."""
     from oracle import oracle as O
     S = O.partition(grid)
     n = min(n_sub_sample, len(S["off"]) - 1)
@@ -72,16 +84,123 @@ def cpu_baseline(grid, wl, n_sub_sample: int, rounds: int):
     eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    _, _, _, info = O.refine_batch(sub, Ds, wl.lambda1, wl.lambda2, k_top=wl.k_top,
-                                   max_rounds=rounds, m_max=1 << 30, eps_tol=eps)
+    Do, bo, _, info = O.refine_batch(sub, Ds, wl.lambda1, wl.lambda2, k_top=wl.k_top,
+                                     max_rounds=rounds, m_max=1 << 30, eps_tol=eps)
     dt = time.perf_counter() - t0
     fits = int(info["rounds"].sum())
-    return {"value": fits / dt, "unit": "subdomain fits/s", "cores": min(threads, n),
-            "kind": "oracle",
-            "sample": f"Alg. 1 with {rounds} of the {wl.max_rounds} enrichment rounds on {n} of "
-                      f"{len(S['off']) - 1} subdomains ({fits} fits up to "
-                      f"M={wl.m0 + rounds * wl.k_top * (2 ** grid.dim - 1)}, {dt:.1f} s, FP64, "
-                      f"one OpenMP thread per subdomain); later rounds are slower per fit"}
+    rec = {"value": fits / dt, "unit": "subdomain fits/s", "cores": min(threads, n),
+           "kind": "oracle",
+           "sample": f"Alg. 1 with {rounds} of the {wl.max_rounds} enrichment rounds on {n} of "
+                     f"{len(S['off']) - 1} subdomains ({fits} fits up to "
+                     f"M={wl.m0 + rounds * wl.k_top * (2 ** grid.dim - 1)}, {dt:.1f} s, FP64, "
+                     f"one OpenMP thread per subdomain); later rounds are slower per fit"}
+    return rec, (first, n, sub, Do, bo, rounds)
+
+
+def local_field(c, sigma, beta, x):
+    """Normalized expansion sum_m beta_m phi_m(x) / sum_m phi_m(x) (FP64)."""
+    d2 = ((x[:, None, :] - c[None, :, :]) ** 2).sum(-1)
+    phi = np.exp(-d2 / (2.0 * sigma[None, :] ** 2))
+    return (phi @ beta) / phi.sum(1)
+
+
+def oracle_check(ctx, api, grid, wl, prec, opts, sample):
+    """Same rounds on the GPU: dictionaries, coefficients and the field's L1
+    error on the sample's owned cells against the oracle's."""
+    import torch
+    first, n, sub, Do, bo, rounds = sample
+    S = api.partition(ctx, grid)
+    D = api.init_lattice(ctx, grid, wl.g, Do.m_cap, wl.sigma_factor)
+    eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
+    beta, _, _, _, _ = api.refine(ctx, S, D, opts, api.RefineOpts(k_top=wl.k_top, max_rounds=rounds,
+                                                                  eps_tol=eps, eta=wl.eta))
+    torch.cuda.synchronize()
+    m = D.m.cpu().numpy()[first:first + n]
+    c = D.c.cpu().numpy()[first:first + n]
+    sg = D.sigma.cpu().numpy()[first:first + n]
+    b = beta.cpu().numpy()[first:first + n]
+    same_dict = bool(np.array_equal(m, Do.m))
+    err, l1g, l1o = 0.0, 0.0, 0.0
+    cell = float(np.prod(grid.cell_size))
+    for s in range(n):
+        M = int(Do.m[s])
+        ref = bo[s * Do.m_cap:s * Do.m_cap + M]
+        co = Do.c[s * Do.m_cap * grid.dim:(s * Do.m_cap + M) * grid.dim].reshape(M, grid.dim)
+        so = Do.sigma[s * Do.m_cap:s * Do.m_cap + M]
+        same_dict &= bool(np.array_equal(c[s, :M], co) and np.array_equal(sg[s, :M], so))
+        err = max(err, float(np.abs(b[s, :M] - ref).max() / np.abs(ref).max()))
+        xs = sub["x"][sub["off"][s]:sub["off"][s + 1]]
+        ys = sub["y"][sub["off"][s]:sub["off"][s + 1]]
+        l1g += float(np.abs(local_field(c[s, :M], sg[s, :M], b[s, :M], xs) - ys).sum()) * cell
+        l1o += float(np.abs(local_field(co, so, ref, xs) - ys).sum()) * cell
+    return {"coef_rel_err_max": err, "gate_coef": 1e-5 if prec == "f32" else None,
+            "field_l1_gpu": l1g, "field_l1_oracle": l1o, "gate_l1": 1e-3,
+            "dictionaries_equal": same_dict,
+            "sample": f"{n} subdomains from {first}, {rounds} enrichment round(s), "
+                      "L1 over their samples' cells"}
+
+
+def train_learned(ctx, api, wl, prec):
+    """Train the warm-start network on eight fields of other seeds (outside
+    the timed region); returns (params, record)."""
+    import torch
+    from paper_2605_16564_amd import learned, synth
+    opts = api.EnetOpts(wl.lambda1, wl.lambda2, prec)
+    grids = [synth.facies256(seed=2100 + i) for i in range(8)]
+    t0 = time.perf_counter()
+    x, t, m = learned.training_set(ctx, grids, wl.g, wl.k_top, opts, wl.eps_tol_rel)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    params = api.cnn_init(7, x.device)
+    epochs, batch = 12, 128
+    ctx.timing(True)
+    ctx.timing_read(reset=True)
+    losses, _ = api.cnn_train(ctx, params, x, t, m, epochs=epochs, batch=batch, lr=2e-3, seed=1)
+    tk = ctx.timing_read(reset=True)
+    ctx.timing(False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    n = int(x.shape[0])
+    # fwd 27.4 MFLOP per patch (2 * 256 pixels * sum of cin*cout*25); fwd+bwd ~3x
+    f_fwd = 2.0 * 256 * 25 * (1 * 32 + 32 * 32 + 32 * 32 + 32 * 2)
+    flops = 3.0 * f_fwd * n * epochs
+    cnn_ms = tk["cnn"][0]
+    peak = 256 * 64 * 2 * 2.4e9 / 1e12          # FP32 FMA on the vector ALUs, non-packed
+    ach = flops / (cnn_ms / 1e3) / 1e12
+    rec = {"train_patches": n, "epochs": epochs, "batch": batch, "loss_first": losses[0],
+           "loss_last": losses[-1], "labels_s": t1 - t0, "train_s": t2 - t1,
+           "train_patches_per_s": n * epochs / (t2 - t1),
+           "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                        "frac": ach / peak, "traffic": None, "kernel": "k_conv/k_wgrad"}}
+    return params, rec
+
+
+def learned_gain(ctx, api, grid, wl, prec, params):
+    """Cold first-round fits of the bench field with and without the hint."""
+    import torch
+    from paper_2605_16564_amd import learned
+    S = api.partition(ctx, grid)
+    D = api.init_lattice(ctx, grid, wl.g, wl.m0, wl.sigma_factor)
+    out = {}
+    for name, hinted in (("cd_warmup", False), ("hinted", True)):
+        ctx.timing(True)
+        ctx.timing_read(reset=True)
+        hint = learned.hint(ctx, params, grid, D) if hinted else None
+        beta, st = api.fit(ctx, S, D, api.EnetOpts(wl.lambda1, wl.lambda2, prec, support_hint=hint))
+        tk = ctx.timing_read(reset=True)
+        ctx.timing(False)
+        s = api.stats_to_numpy(st)
+        out[name] = {"solve_ms": tk["solve"][0], "cnn_ms": tk["cnn"][0],
+                     "iters": int(s["iters"].sum()), "cd_sweeps": int(s["cd_sweeps"].sum()),
+                     "beta": beta}
+    b0, b1 = out["cd_warmup"].pop("beta"), out["hinted"].pop("beta")
+    out["coef_rel_diff"] = float((b0 - b1).abs().max().item() / b0.abs().max().item())
+    x, t, m = learned.training_set(ctx, [grid], wl.g, wl.k_top, api.EnetOpts(wl.lambda1, wl.lambda2, prec),
+                                   wl.eps_tol_rel)
+    acc = learned.head_accuracy(api.cnn_forward(ctx, params, x), t, m)
+    out["held_out_accuracy"] = {"refine": acc[0][0], "refine_majority": acc[0][1],
+                                "support": acc[1][0], "support_majority": acc[1][1]}
+    return out
 
 
 def main():
@@ -107,13 +226,21 @@ def main():
     ycell = cell_y[torch.as_tensor(cell_of, device=dev)]
     Q = xq.shape[0]
     eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
-    opts = api.EnetOpts(wl.lambda1, wl.lambda2, prec, cd_sweeps=args.cd_sweeps)
-    ropts = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta)
+    use_learned = not args.no_learned and grid.dim == 2
+    params, learned_rec = None, None
+    if use_learned:
+        from paper_2605_16564_amd import learned
+        params, learned_rec = train_learned(ctx, api, wl, prec)
 
-    def step():
+    def step(batched=True, cold=False, hinted=use_learned):
         S = api.partition(ctx, grid, cell_y)
         D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
-        beta, lvl, rounds, rs, stats = api.refine(ctx, S, D, opts, ropts)
+        hint = learned.hint(ctx, params, grid, D) if hinted else None
+        o = api.EnetOpts(wl.lambda1, wl.lambda2, prec, cd_sweeps=args.cd_sweeps, batched=batched,
+                         support_hint=hint)
+        ro = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta,
+                            cold_rounds=cold)
+        beta, lvl, rounds, rs, stats = api.refine(ctx, S, D, o, ro)
         out = api.evaluate(ctx, grid, D, beta, xq)
         return S, D, beta, rounds, rs, stats, out
 
@@ -244,9 +371,30 @@ def main():
         "dominant_kernel": dominant,
         "roofline": roof,
     }
+    rec["config"]["learned_warm_start"] = bool(use_learned)
+    if use_learned:
+        learned_rec["gain_first_fit"] = learned_gain(ctx, api, grid, wl, prec, params)
+        rec["learned"] = learned_rec
+    if not args.no_comparator:
+        # plain GPU fit: one launch per subdomain and kernel, every refit from
+        # zero, no hint; same path otherwise (one step, kernels already loaded)
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        resc = step(batched=False, cold=True, hinted=False)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - tc0
+        fits_c = int(resc[3].sum().item())
+        oc = resc[6]
+        l1c = float((w_d * (oc.double() - ycell).abs()).sum().item()) / area
+        rec["comparator"] = {"kind": "plain GPU fit (per-subdomain launches, cold refits, no hint)",
+                             "value": fits_c / tc, "unit": "fits/s", "field_l1_log10": l1c,
+                             "speedup": value / (fits_c / tc)}
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(grid, wl, args.cpu_sample_subdomains,
-                                           min(args.cpu_sample_rounds, wl.max_rounds))
+        base, sample = cpu_baseline(grid, wl, args.cpu_sample_subdomains,
+                                    min(args.cpu_sample_rounds, wl.max_rounds))
+        rec["cpu_baseline"] = base
+        rec["oracle_check"] = oracle_check(ctx, api, grid, wl, prec,
+                                           api.EnetOpts(wl.lambda1, wl.lambda2, prec), sample)
     print(json.dumps(rec))
     ctx.close()
 

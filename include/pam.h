@@ -204,6 +204,10 @@ typedef struct {
     double *round_stats;        /* [n_sub*(max_rounds+1)*6] per round
                                    {M, support, max R_T, marked, sum R_T,
                                    solve stream bytes}, or NULL                */
+    int32_t cold_rounds;        /* 0: each refit starts from the previous beta
+                                   extended by zeros (Alg. 1); 1: each refit
+                                   starts from zero (comparator; same result,
+                                   more work)                                  */
 } pam_refine_opts;
 
 /* a3-a9 (Alg. 1): fit, residual indicator R_T (Sec. 2 Step 3, 2-point

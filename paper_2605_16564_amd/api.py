@@ -242,6 +242,7 @@ class RefineOpts:
     eta: float = 0.5
     eps_tol: float = 0.0
     space: int = 0
+    cold_rounds: bool = False
 
 
 def refine(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, ropts: RefineOpts,
@@ -266,6 +267,7 @@ def refine(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, ropts: Refin
     r.max_rounds, r.m_max = int(ropts.max_rounds), int(min(ropts.m_max, 2 ** 31 - 1))
     r.eta, r.eps_tol, r.space = float(ropts.eta), float(ropts.eps_tol), int(ropts.space)
     r.elem_level, r.rounds, r.round_stats = _p(elem_level), _p(rounds), _p(rstats)
+    r.cold_rounds = 1 if ropts.cold_rounds else 0
     ss, ds, os_ = S.struct(), D.struct(), opts.struct(warm)
     ctx.use_current_stream()
     N.check(N.lib().pam_refine(ctx.h, C.byref(ss), C.byref(ds), _p(beta), C.byref(os_),

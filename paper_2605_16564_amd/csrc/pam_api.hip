@@ -437,7 +437,7 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     ra.round_stats = r->round_stats;
     ra.stats = stats;
     for (int round = 0; round <= r->max_rounds; ++round) {
-        const int warm = round == 0 ? opts->warm_start : 1;
+        const int warm = round == 0 ? opts->warm_start : (r->cold_rounds ? 0 : 1);
         if ((st = run_fit(ctx, samples, dict, opts, beta, stats, active, warm)) != PAM_OK) return st;
         ra.round = round;
         {

@@ -63,7 +63,7 @@ class PamRefineOpts(C.Structure):
     _fields_ = [("k_top", C.c_int32), ("k_top_sub", C.c_void_p), ("max_rounds", C.c_int32),
                 ("m_max", C.c_int32), ("eta", C.c_double), ("eps_tol", C.c_double),
                 ("space", C.c_int32), ("elem_level", C.c_void_p), ("rounds", C.c_void_p),
-                ("round_stats", C.c_void_p)]
+                ("round_stats", C.c_void_p), ("cold_rounds", C.c_int32)]
 
 
 class PamField(C.Structure):
