@@ -35,6 +35,7 @@ static constexpr int kFz = 8;      // coordinates frozen before one batched down
 static constexpr int kQ = 16;      // rows of the low-rank update scratch (>= kB, kFz)
 static constexpr int kPass = kR * kT;
 static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the polish
+static constexpr int kIncMax = 48;     // incremental solution updates between full solves
 
 __host__ __device__ size_t solve_ldh(int m_cap) { return (size_t)round_up(m_cap, kPass); }
 __host__ __device__ size_t solve_h_elems(int m_cap) { return (size_t)(m_cap + 1) * solve_ldh(m_cap); }
@@ -257,8 +258,12 @@ __device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *
 // Returns false (set unchanged) if C is not numerically positive definite.
 // Rows of A_SB and of V = U C^-1 are staged through LDS in tiles so that
 // the streaming passes over H read them as broadcasts.
+// With upd_z, v.z holds H r_S for the current block (r = b - lambda1 theta)
+// on entry and the solution for the enlarged block on return:
+//   z_S <- z_S + V (U' r_S - r_B),  z_B = C^-1 (r_B - U' r_S).
 template <typename TG>
-__device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile) {
+__device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile,
+                                          bool upd_z = false) {
     const int s = v.s;
     v.bytes += 24.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
     for (int q = 0; q < nb; ++q)
@@ -362,6 +367,34 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         }
     }
     __syncthreads();
+    if (upd_z) {
+        double ur[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) ur[q] = 0.0;
+        for (int i = threadIdx.x; i < s; i += kT) {
+            const int k = v.S[i];
+            const double ri = Gat(v, k, v.M) - v.l1 * (double)v.th[k];
+#pragma unroll
+            for (int q = 0; q < kB; ++q) ur[q] += q < nb ? v.U[(size_t)q * v.m_cap + i] * ri : 0.0;
+        }
+        bsum_vec<kB>(ur, red);
+        double w[kB];   // U' r_S - r_B
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+            w[q] = q < nb ? ur[q] - (Gat(v, ks[q], v.M) - v.l1 * (double)v.th[ks[q]]) : 0.0;
+        for (int i = threadIdx.x; i < s; i += kT) {
+            double acc = v.z[i];
+#pragma unroll
+            for (int q = 0; q < kB; ++q) acc += q < nb ? v.V[(size_t)q * v.m_cap + i] * w[q] : 0.0;
+            v.z[i] = acc;
+        }
+        if ((int)threadIdx.x < nb) {
+            double acc = 0.0;
+            for (int q = 0; q < nb; ++q) acc -= cinv[threadIdx.x * kB + q] * w[q];
+            v.z[s + threadIdx.x] = acc;
+        }
+        __syncthreads();
+    }
     // H[i][j] += sum_q V[q][i] U[q][j] over the old block
     hupdate<kB>(v, s, nb, v.V, v.U, tile);
     for (int j = threadIdx.x; j < s; j += kT)
@@ -401,6 +434,7 @@ __device__ __forceinline__ void drop_position(Sv<TG> &v, int p) {
             const int kl = v.S[last];
             v.S[p] = kl;
             v.pos[kl] = p;
+            v.z[p] = v.z[last];   // the maintained solution follows its position
         }
     }
     if (threadIdx.x == 0) v.pos[kp] = -1;
@@ -411,8 +445,12 @@ __device__ __forceinline__ void drop_position(Sv<TG> &v, int p) {
 // Freeze active position p: its coordinate is held at zero without touching
 // H. With W = H[:, R] (rows of H, by symmetry) and C = H[R, R], the inverse of
 // the remaining block is H - W C^-1 W'; C^-1 grows by bordering.
+//
+// With upd_z, v.z holds the solution on the current live positions and is
+// carried to the block without p: z <- z - h z_p / h_pp, h the column p of
+// the effective inverse H - W C^-1 W' (before p joins the frozen set).
 template <typename TG>
-__device__ __forceinline__ void freeze(Sv<TG> &v, int p) {
+__device__ __forceinline__ void freeze(Sv<TG> &v, int p, bool upd_z = false) {
     const int s = v.s, r = v.r;
     v.bytes += 8.0 * s;
     for (int i = threadIdx.x; i < s; i += kT) v.U[(size_t)r * v.m_cap + i] = v.H[(size_t)p * v.ldh + i];
@@ -428,6 +466,7 @@ __device__ __forceinline__ void freeze(Sv<TG> &v, int p) {
             delta -= c[q] * t;
         }
         const double id = 1.0 / delta;
+        u[kFz] = delta;   // for the update of z below
         for (int q = 0; q < r; ++q) {
             for (int k = 0; k < r; ++k) v.Cri[q * kFz + k] += u[q] * u[k] * id;
             v.Cri[q * kFz + r] = -u[q] * id;
@@ -437,7 +476,45 @@ __device__ __forceinline__ void freeze(Sv<TG> &v, int p) {
         v.Rp[r] = p;
     }
     __syncthreads();
+    if (upd_z) {
+        const double *u = v.Cri + kFz * kFz + kFz;
+        const double f = v.z[p] / u[kFz];
+        __syncthreads();   // every thread holds z_p before any position is written
+        for (int i = threadIdx.x; i < s; i += kT) {
+            double h = v.U[(size_t)r * v.m_cap + i];
+            for (int q = 0; q < r; ++q) h -= v.U[(size_t)q * v.m_cap + i] * u[q];
+            v.z[i] -= h * f;
+        }
+        __syncthreads();
+        // frozen positions (the earlier ones and p) stay exactly zero
+        if ((int)threadIdx.x <= r) v.z[v.Rp[threadIdx.x]] = 0.0;
+        __syncthreads();
+    }
     v.r = r + 1;
+}
+
+// z += d * (column p of the effective inverse H - W C^-1 W'): the solution
+// after the right-hand side of position p changed by d.
+template <typename TG>
+__device__ __forceinline__ void heff_axpy(Sv<TG> &v, int p, double d) {
+    const int s = v.s, r = v.r;
+    double *t = v.Cri + kFz * kFz + 2 * kFz + 1;   // [kFz] scratch after delta
+    if (threadIdx.x == 0)
+        for (int q = 0; q < r; ++q) {
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc += v.Cri[q * kFz + k] * v.U[(size_t)k * v.m_cap + p];
+            t[q] = acc;
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < s; i += kT) {
+        double h = v.H[(size_t)p * v.ldh + i];
+        for (int q = 0; q < r; ++q) h -= v.U[(size_t)q * v.m_cap + i] * t[q];
+        v.z[i] += d * h;
+    }
+    __syncthreads();
+    // frozen positions stay exactly zero
+    if ((int)threadIdx.x < r) v.z[v.Rp[threadIdx.x]] = 0.0;
+    __syncthreads();
 }
 
 // Apply the frozen set to H (one rank-r pass: H <- H - W' C^-1 W) and drop
@@ -518,55 +595,6 @@ __device__ __forceinline__ void solve_active(Sv<TG> &v, double *in, double *out,
     __syncthreads();
 }
 
-// Remove active position p: H <- H_{-p,-p} - h h' / H_pp (h = H[-p, p]),
-// then the last position moves into p.
-template <typename TG>
-__device__ __forceinline__ void remove_at(Sv<TG> &v, int p) {
-    const int s = v.s;
-    v.bytes += 16.0 * (double)s * (double)s;
-    const double hp = v.H[(size_t)p * v.ldh + p];
-    for (int i = threadIdx.x; i < s; i += kT) v.u[i] = v.H[(size_t)i * v.ldh + p];
-    __syncthreads();
-    const double ih = 1.0 / hp;
-    // row p and column p are left stale: they are overwritten by the move
-    // below or fall outside the shrunken block.
-    for (int j = threadIdx.x; j < s; j += kT) {
-        const double uj = v.u[j] * ih;
-        double *Hc = v.H + j;
-        int i = 0;
-        for (; i + 16 <= s; i += 16) {
-            double *h = Hc + (size_t)i * v.ldh;
-            double hv[16];
-#pragma unroll
-            for (int e = 0; e < 16; ++e) hv[e] = h[(size_t)e * v.ldh];
-#pragma unroll
-            for (int e = 0; e < 16; ++e) h[(size_t)e * v.ldh] = hv[e] - v.u[i + e] * uj;
-        }
-        for (; i < s; ++i) Hc[(size_t)i * v.ldh] -= v.u[i] * uj;
-    }
-    __syncthreads();
-    const int last = s - 1;
-    const int kp = v.S[p];
-    if (p != last) {
-        for (int j = threadIdx.x; j < last; j += kT) {
-            if (j == p) continue;
-            const double val = v.H[(size_t)last * v.ldh + j];
-            v.H[(size_t)p * v.ldh + j] = val;
-            v.H[(size_t)j * v.ldh + p] = val;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            v.H[(size_t)p * v.ldh + p] = v.H[(size_t)last * v.ldh + last];
-            const int kl = v.S[last];
-            v.S[p] = kl;
-            v.pos[kl] = p;
-        }
-    }
-    if (threadIdx.x == 0) v.pos[kp] = -1;
-    __syncthreads();
-    v.s = s - 1;
-}
-
 // g = b - G beta - lambda2 beta over all coordinates (rows of the active
 // set). Each thread owns one 16-byte group of adjacent coordinates (four
 // FP32 or two FP64 Gram entries per load) and keeps sixteen Gram rows in
@@ -629,13 +657,14 @@ __device__ __forceinline__ void full_gradient(Sv<TG> &v) {
 // Coordinates that cannot enter are deactivated. Returns false if none of a
 // requested set could enter.
 template <typename TG>
-__device__ __forceinline__ bool activate(Sv<TG> &v, int *list, int n, Red &red, double *cinv, int *blk, double *tile) {
+__device__ __forceinline__ bool activate(Sv<TG> &v, int *list, int n, Red &red, double *cinv, int *blk, double *tile,
+                                         bool upd_z = false) {
     bool any = false;
     for (int b0 = 0; b0 < n; b0 += kB) {
         const int nb = min(kB, n - b0);
         if (threadIdx.x < nb) blk[threadIdx.x] = list[b0 + threadIdx.x];
         __syncthreads();
-        if (add_block(v, blk, nb, red, cinv, tile)) {
+        if (add_block(v, blk, nb, red, cinv, tile, upd_z)) {
             any = true;
             continue;
         }
@@ -643,7 +672,7 @@ __device__ __forceinline__ bool activate(Sv<TG> &v, int *list, int n, Red &red, 
             const int k = list[b0 + q];
             if (threadIdx.x == 0) blk[0] = k;
             __syncthreads();
-            if (add_block(v, blk, 1, red, cinv, tile)) {
+            if (add_block(v, blk, 1, red, cinv, tile, upd_z)) {
                 any = true;
             } else if (threadIdx.x == 0) {
                 v.th[k] = 0;
@@ -831,7 +860,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __shared__ int list[kB];
     __shared__ double tile[kQ * kTile];
     __shared__ int frz[kFz];
-    __shared__ double cri[kFz * kFz + 2 * kFz];
+    __shared__ double cri[kFz * kFz + 3 * kFz + 1];
     const int s_id = a.sub_begin + blockIdx.x;
     if (a.active && !a.active[s_id]) return;
     const int loc = s_id - a.sub_begin;
@@ -994,6 +1023,14 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     }(), red);
     int it = 0, status = PAM_ST_NOCONV, refines = 0, n_cg = 0;
     bool skip_solve = false, ran_ex = false;
+    // v.z holds the solution of the current signed block (zv): line searches
+    // and activations then carry it by rank-one and bordering identities
+    // instead of a pass over H; a full solve at least every kIncMax updates
+    bool zv = false;
+    int n_inc = 0;
+#ifdef PAM_INC_CHECK
+    int dbg_op = 0, dbg_n = 0;
+#endif
     constexpr bool kLow = sizeof(TG) < sizeof(double);
     Pol P{};
     if (kLow) {
@@ -1042,20 +1079,65 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         if (v.s > 0 && !skip_solve) {
             if (ex) compact(v, tile);   // the CG solve runs on live positions only
             const int s = v.s;
-            if (ex) {
-                n_cg += cg64(v, P, red, gtol, v.z);
-            } else {
+            // full solve of the signed block into v.z
+            auto solve_full = [&]() {
                 for (int i = threadIdx.x; i < s; i += kT) {
                     const int k = v.S[i];
                     v.rhs[i] = Gat(v, k, M) - v.l1 * (double)v.th[k];
                 }
                 __syncthreads();
                 solve_active(v, v.rhs, v.z, red);
+                zv = true;
+                n_inc = 0;
+            };
+            bool fresh = true;
+            if (ex) {
+                n_cg += cg64(v, P, red, gtol, v.z);
+            } else if (zv && n_inc < kIncMax) {
+                fresh = n_inc == 0;   // carried by the identities
+#ifdef PAM_INC_CHECK
+                {
+                    for (int i = threadIdx.x; i < s; i += kT) {
+                        const int k = v.S[i];
+                        v.rhs[i] = Gat(v, k, M) - v.l1 * (double)v.th[k];
+                    }
+                    __syncthreads();
+                    double *zf = v.Ag;
+                    solve_active(v, v.rhs, zf, red);
+                    double dm = 0.0, zm = 0.0;
+                    int im = -1;
+                    for (int i = threadIdx.x; i < s; i += kT) {
+                        const double dd = fabs(zf[i] - v.z[i]);
+                        if (dd > dm) { dm = dd; im = i; }
+                        zm = fmax(zm, fabs(zf[i]));
+                    }
+                    VI xx; xx.v = dm; xx.i = im;
+                    xx = bargmax(xx, red);
+                    zm = bmax(zm, red);
+                    if (threadIdx.x == 0 && xx.v > 1e-11 * zm && dbg_n < 8) {
+                        printf("INC sub=%d it=%d s=%d r=%d n_inc=%d last_op=%d diff=%.3e at %d (zf %.3e z %.3e th %d) zmax=%.3e\n",
+                               s_id, it, s, v.r, n_inc, dbg_op, xx.v, xx.i, zf[xx.i], v.z[xx.i], (int)v.th[v.S[xx.i]], zm);
+                    }
+                    if (xx.v > 1e-11 * zm) ++dbg_n;
+                    __syncthreads();
+                }
+#endif
+            } else {
+                solve_full();
             }
             PHASE_MARK(3);
             bool mine = true;
             for (int i = threadIdx.x; i < s; i += kT)
                 if ((int)sgn(v.z[i]) != v.th[v.S[i]]) mine = false;
+            // the carried solution steers line searches; a step is accepted
+            // as consistent only on a solve of its own (the identities lose
+            // about eps * cond(G) per update)
+            if (!fresh && ball(mine, red)) {
+                solve_full();
+                mine = true;
+                for (int i = threadIdx.x; i < s; i += kT)
+                    if ((int)sgn(v.z[i]) != v.th[v.S[i]]) mine = false;
+            }
             if (!ball(mine, red)) {
                 // discrete line search from beta_S to z over the zero crossings
                 double p1 = 0.0, p2 = 0.0, p3 = 0.0;
@@ -1124,11 +1206,37 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
                     const double b0 = v.beta[k], zi = v.z[i];
                     double nb = b0 + tstar * (zi - b0);
                     if (tstar < 1.0 && b0 != 0.0 && sgn(zi) != sgn(b0) && b0 / (b0 - zi) == tstar) nb = 0.0;
-                    v.g[k] -= tstar * (v.g[k] - v.l1 * (double)v.th[k]);
+                    const int t0 = v.th[k];
+                    if (t0 == 0) nb = 0.0;   // a frozen position awaiting the downdate
+                    v.g[k] -= tstar * (v.g[k] - v.l1 * (double)t0);
                     v.beta[k] = nb;
-                    v.th[k] = (signed char)sgn(nb);
+                    const int t1 = (int)sgn(nb);
+                    // a coordinate that entered at zero may leave the line search
+                    // with the other sign: its right-hand side moves by 2 lambda1 theta
+                    v.u[i] = (t1 != 0 && t1 != t0) ? 2.0 * v.l1 * (double)t0 : 0.0;
+                    v.th[k] = (signed char)t1;
                 }
                 __syncthreads();
+                const bool inc = zv && !ex;
+                if (inc) {
+                    for (;;) {
+                        VI x; x.v = -1.0; x.i = -1;
+                        for (int i = threadIdx.x; i < s; i += kT)
+                            if (v.u[i] != 0.0) { VI c; c.v = (double)i; c.i = i; x = vmax(x, c); }
+                        x = bargmax(x, red);
+                        if (x.i < 0) break;
+                        const double d = v.u[x.i];
+                        __syncthreads();
+                        if (threadIdx.x == 0) v.u[x.i] = 0.0;
+                        heff_axpy(v, x.i, d);
+                        ++n_inc;
+#ifdef PAM_INC_CHECK
+                        dbg_op = (dbg_op % 1000) * 10 + 1;
+#endif
+                    }
+                } else {
+                    zv = false;
+                }
                 // freeze the coordinates that reached zero (batched downdate)
                 for (;;) {
                     VI x; x.v = -1.0; x.i = -1;
@@ -1146,7 +1254,11 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
                         compact(v, tile);
                         continue;   // positions moved: search again
                     }
-                    freeze(v, x.i);
+                    freeze(v, x.i, inc);
+                    n_inc += inc ? 1 : 0;
+#ifdef PAM_INC_CHECK
+                    dbg_op = (dbg_op % 1000) * 10 + 2;
+#endif
 #ifdef PAM_PHASE_PROFILE
                     ++n_rm;
 #endif
@@ -1155,6 +1267,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
 #ifdef PAM_PHASE_PROFILE
                 ++n_ls;
 #endif
+                refines = 0;   // the refinement budget counts consecutive attempts only
                 continue;
             }
             for (int i = threadIdx.x; i < s; i += kT) v.beta[v.S[i]] = v.z[i];
@@ -1195,7 +1308,12 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
 #ifdef PAM_PHASE_PROFILE
             n_add += nadd;
 #endif
-            if (!activate(v, list, nadd, red, cinv, blk, tile)) break;
+            if (!activate(v, list, nadd, red, cinv, blk, tile, zv && !ex)) break;
+            n_inc += 1;
+            refines = 0;
+#ifdef PAM_INC_CHECK
+            dbg_op = 3;
+#endif
             PHASE_MARK(7);
             continue;
         }
@@ -1213,6 +1331,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
             break;
         }
         ++refines;
+        zv = false;
         if (ex) continue;   // the next CG solve starts from beta: a refinement step
         solve_active(v, v.rhs, v.z, red);   // correction H r
         bool keep_mine = true;
@@ -1243,6 +1362,16 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         nz += b != 0.0 ? 1.0 : 0.0;
     }
     const double kkt = bmax(kk, red);
+#ifdef PAM_INC_CHECK
+    if (kkt > 1e-8)
+        for (int m = threadIdx.x; m < M; m += kT) {
+            const double b = v.beta[m];
+            const double e = b != 0.0 ? fabs(v.g[m] - v.l1 * sgn(b)) : fmax(fabs(v.g[m]) - v.l1, 0.0);
+            if (e > 1e-8)
+                printf("KKT sub=%d m=%d beta=%.3e g=%.3e th=%d pos=%d status=%d it=%d refines=%d\n", s_id, m, b, v.g[m],
+                       (int)v.th[m], v.pos[m], status, it, refines);
+        }
+#endif
     const double nzs = bsum(nz, red);
     for (int m = threadIdx.x; m < a.m_cap; m += kT) beta_out[m] = m < M ? v.beta[m] : 0.0;
 #ifdef PAM_PHASE_PROFILE
