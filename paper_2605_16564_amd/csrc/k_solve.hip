@@ -29,6 +29,7 @@ namespace pam {
 static constexpr int kT = 512;
 static constexpr int kW = kT / 64;
 static constexpr int kB = 8;       // coordinates activated per blocked bordering step
+static constexpr int kAdd = 16;    // violators activated per consistent iteration
 static constexpr int kR = 1;       // GEMV outputs per thread per pass
 static constexpr int kTile = 128;  // rows staged in LDS per bordering tile
 static constexpr int kFz = 8;      // coordinates frozen before one batched downdate
@@ -45,7 +46,7 @@ __host__ __device__ size_t solve_scratch_elems(int m_cap, int npad) {
     // and two per-sample vectors [2][npad]
     return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad;
 }
-size_t solve_lds_bytes(int m_cap) { return (size_t)49 * round_up(m_cap, 8) + 64; }
+size_t solve_lds_bytes(int m_cap) { return (size_t)57 * round_up(m_cap, 8) + 64; }
 
 // ---------------------------------------------------------------- reductions
 struct Red {
@@ -140,6 +141,7 @@ struct Sv {
     double *H;             // [m_cap+1][ldh] inverse of the active block
     double *Ag, *U, *V;    // [kB][m_cap] scratch for blocked bordering
     double *g, *beta;      // LDS, by coordinate
+    double *b;             // LDS, by coordinate: b = W'y (column M of the Gram)
     double *z, *rhs, *u;   // LDS, by active position
     int *S, *pos;          // LDS
     signed char *th;       // LDS
@@ -373,7 +375,7 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         for (int q = 0; q < kB; ++q) ur[q] = 0.0;
         for (int i = threadIdx.x; i < s; i += kT) {
             const int k = v.S[i];
-            const double ri = Gat(v, k, v.M) - v.l1 * (double)v.th[k];
+            const double ri = v.b[k] - v.l1 * (double)v.th[k];
 #pragma unroll
             for (int q = 0; q < kB; ++q) ur[q] += q < nb ? v.U[(size_t)q * v.m_cap + i] * ri : 0.0;
         }
@@ -381,7 +383,7 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         double w[kB];   // U' r_S - r_B
 #pragma unroll
         for (int q = 0; q < kB; ++q)
-            w[q] = q < nb ? ur[q] - (Gat(v, ks[q], v.M) - v.l1 * (double)v.th[ks[q]]) : 0.0;
+            w[q] = q < nb ? ur[q] - (v.b[ks[q]] - v.l1 * (double)v.th[ks[q]]) : 0.0;
         for (int i = threadIdx.x; i < s; i += kT) {
             double acc = v.z[i];
 #pragma unroll
@@ -618,7 +620,7 @@ __device__ __forceinline__ void full_gradient(Sv<TG> &v) {
 #pragma unroll
         for (int c = 0; c < VW; ++c) {
             const int m = m0 + c;
-            acc[c] = m < M ? Gat(v, m, M) - v.l2 * v.beta[m] : 0.0;
+            acc[c] = m < M ? v.b[m] - v.l2 * v.beta[m] : 0.0;
         }
         const V *col = reinterpret_cast<const V *>(v.G + m0);
         int i = 0;
@@ -857,7 +859,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __shared__ Red red;
     __shared__ double cinv[kB * kB];
     __shared__ int blk[kB];
-    __shared__ int list[kB];
+    __shared__ int list[kAdd];
     __shared__ double tile[kQ * kTile];
     __shared__ int frz[kFz];
     __shared__ double cri[kFz * kFz + 3 * kFz + 1];
@@ -884,7 +886,8 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.z = ld + 2 * Mc;
     v.rhs = ld + 3 * Mc;
     v.u = ld + 4 * Mc;
-    v.S = reinterpret_cast<int *>(ld + 5 * Mc);
+    v.b = ld + 5 * Mc;
+    v.S = reinterpret_cast<int *>(ld + 6 * Mc);
     v.pos = v.S + Mc;
     v.th = reinterpret_cast<signed char *>(v.pos + Mc);
     v.s = 0;
@@ -915,7 +918,8 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     for (int m = threadIdx.x; m < M; m += kT) {
         v.beta[m] = a.warm_start ? beta_out[m] : 0.0;
         v.pos[m] = -1;
-        v.g[m] = Gat(v, m, M);
+        v.b[m] = Gat(v, m, M);
+        v.g[m] = v.b[m];
     }
     __syncthreads();
     for (int m = threadIdx.x; m < M; m += kT) v.g[m] -= v.l2 * v.beta[m];
@@ -1000,7 +1004,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         // signs of the hinted set from the ridge solution on it (lambda1
         // dropped): near the minimizer's support these are its signs, which
         // the gradient at zero often is not
-        for (int i = threadIdx.x; i < v.s; i += kT) v.rhs[i] = Gat(v, v.S[i], M);
+        for (int i = threadIdx.x; i < v.s; i += kT) v.rhs[i] = v.b[v.S[i]];
         __syncthreads();
         solve_active(v, v.rhs, v.z, red);
         for (int i = threadIdx.x; i < v.s; i += kT) {
@@ -1018,7 +1022,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     // ---- exact sign-consistent active-set iteration
     const double bnorm = bmax([&] {
         double t = 0.0;
-        for (int m = threadIdx.x; m < M; m += kT) t = fmax(t, fabs(Gat(v, m, M)));
+        for (int m = threadIdx.x; m < M; m += kT) t = fmax(t, fabs(v.b[m]));
         return t;
     }(), red);
     int it = 0, status = PAM_ST_NOCONV, refines = 0, n_cg = 0;
@@ -1083,7 +1087,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
             auto solve_full = [&]() {
                 for (int i = threadIdx.x; i < s; i += kT) {
                     const int k = v.S[i];
-                    v.rhs[i] = Gat(v, k, M) - v.l1 * (double)v.th[k];
+                    v.rhs[i] = v.b[k] - v.l1 * (double)v.th[k];
                 }
                 __syncthreads();
                 solve_active(v, v.rhs, v.z, red);
@@ -1099,7 +1103,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
                 {
                     for (int i = threadIdx.x; i < s; i += kT) {
                         const int k = v.S[i];
-                        v.rhs[i] = Gat(v, k, M) - v.l1 * (double)v.th[k];
+                        v.rhs[i] = v.b[k] - v.l1 * (double)v.th[k];
                     }
                     __syncthreads();
                     double *zf = v.Ag;
@@ -1281,9 +1285,10 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
 #ifdef PAM_PHASE_PROFILE
         ++n_cons;
 #endif
-        // worst inactive violations (up to kB, by |g| then index)
+        // worst inactive violations (up to kAdd, by |g| then index), bordered
+        // kB at a time
         int nadd = 0;
-        for (int q = 0; q < kB; ++q) {
+        for (int q = 0; q < kAdd; ++q) {
             VI x; x.v = -1.0; x.i = -1;
             for (int m = threadIdx.x; m < M; m += kT) {
                 if (v.pos[m] >= 0) continue;
@@ -1396,7 +1401,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     const size_t lds = solve_lds_bytes(a.m_cap);
     if (lds > 150 * 1024) {
-        set_error("m_cap too large for the LDS-resident solve (max 3100)");
+        set_error("m_cap too large for the LDS-resident solve (max 2690)");
         return PAM_ERR_CAPACITY;
     }
     double *H = wsp<double>(ctx, BUF_H);
