@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--cpu-sample-rounds", type=int, default=1)
     ap.add_argument("--no-learned", action="store_true", help="no learned warm start")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="skip the one-pattern-off runs (batching, precision, learned)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three device copies of 1 GiB (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -261,11 +263,11 @@ def main():
         from paper_2605_16564_amd import learned
         params, learned_rec = train_learned(ctx, api, wl, prec)
 
-    def step(batched=True, cold=False, hinted=use_learned):
+    def step(batched=True, cold=False, hinted=use_learned, precision=prec):
         S = api.partition(ctx, grid, cell_y)
         D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
         hint = learned.hint(ctx, params, grid, D) if hinted else None
-        o = api.EnetOpts(wl.lambda1, wl.lambda2, prec, cd_sweeps=args.cd_sweeps, batched=batched,
+        o = api.EnetOpts(wl.lambda1, wl.lambda2, precision, cd_sweeps=args.cd_sweeps, batched=batched,
                          support_hint=hint)
         ro = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta,
                             cold_rounds=cold)
@@ -408,6 +410,24 @@ def main():
     if use_learned:
         learned_rec["gain_first_fit"] = learned_gain(ctx, api, grid, wl, prec, params)
         rec["learned"] = learned_rec
+    if not args.no_ablations:
+        # each pattern switched off alone (one untimed and one timed step; the
+        # unbatched run is one timed step): fits/s and the ratio it costs
+        abl = {}
+        variants = [("no_learned", dict(hinted=False), 1), ("fp64", dict(precision="f64"), 1),
+                    ("unbatched", dict(batched=False), 0)]
+        for name, kw, warm in variants:
+            if name == "no_learned" and not use_learned:
+                continue
+            for _ in range(warm):
+                step(**kw)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            ra = step(**kw)
+            torch.cuda.synchronize()
+            va = int(ra[3].sum().item()) / (time.perf_counter() - ta)
+            abl[name] = {"value": va, "unit": "fits/s", "speedup_of_pattern": value / va}
+        rec["ablations"] = abl
     if not args.no_comparator:
         # plain GPU fit: one launch per subdomain and kernel, every refit from
         # zero, no hint; same path otherwise (one step, kernels already loaded)
