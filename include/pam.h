@@ -262,17 +262,23 @@ pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
  * ------------------------------------------------------------------------ */
 int64_t pam_cnn_param_count(void);
 
-/* logits = network(params, x) for B >= 1 patches. */
+/* logits = network(params, x) for B >= 1 patches. precision: PAM_PREC_F32
+ * (every layer on the vector ALUs in FP32) or PAM_PREC_BF16 (the two 32 -> 32
+ * layers on BF16 MFMA with FP32 accumulation, activations and the thin first
+ * and last layers in FP32); other values are rejected. */
 pam_status pam_cnn_forward(pam_ctx *ctx, const float *params, int32_t B, const float *x,
-                           float *logits);
+                           float *logits, int32_t precision);
 
-/* Masked binary cross-entropy with logits over both channels,
+/* Masked binary cross-entropy with logits over both channels (precision as
+ * for pam_cnn_forward; BF16 also runs the 32 -> 32 layers' backward-data and
+ * weight-gradient products on MFMA),
  *   L = sum mask * (max(z,0) - z*t + log(1 + exp(-|z|))) / sum mask,
  * and its gradient with respect to every parameter (grads, same layout as
  * params, overwritten). loss: device float scalar or NULL. A batch with an
  * all-zero mask gives L = 0 and zero gradients. */
 pam_status pam_cnn_loss_grad(pam_ctx *ctx, const float *params, int32_t B, const float *x,
-                             const float *target, const float *mask, float *grads, float *loss);
+                             const float *target, const float *mask, float *grads, float *loss,
+                             int32_t precision);
 
 /* One Adam step (Kingma and Ba, 2015) with bias correction at step >= 1:
  * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,

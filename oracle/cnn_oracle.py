@@ -14,6 +14,9 @@ in float64, written from the definitions:
 * gradients: the chain rule taken layer by layer (no automatic
   differentiation); the pins check them against central differences;
 * Adam (Kingma and Ba, 2015, Algorithm 1) with bias correction;
+* optional emulation of the BF16 mode: the listed layers take their
+  convolution operands rounded to bfloat16 (round to nearest even from the
+  FP32 value), everything else in float64;
 * the patch cut, the hint map and the training labels as index maps.
 """
 from __future__ import annotations
@@ -44,6 +47,14 @@ def unpack(params):
     return out
 
 
+def bf16(a):
+    """Round to bfloat16 (8-bit significand, round to nearest even) through
+    float32, returned as float64."""
+    u = np.ascontiguousarray(np.asarray(a, np.float64).astype(np.float32)).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 # ---------------------------------------------------------------- network
 def conv_same(x, w, b=None):
     """x [B, Ci, H, W], w [Co, Ci, 5, 5] -> [B, Co, H, W] (zero padding 2)."""
@@ -59,14 +70,15 @@ def conv_same(x, w, b=None):
     return out
 
 
-def forward(params, x):
-    """logits [B, 2, 16, 16] and the per-layer inputs (for the backward pass)."""
+def forward(params, x, bf16_layers=()):
+    """logits [B, 2, 16, 16] and the per-layer inputs (for the backward pass).
+    Layers in bf16_layers convolve BF16-rounded inputs and weights."""
     layers = unpack(params)
     a = np.asarray(x, np.float64).reshape(-1, 1, P, P)
     inputs = []
     for l, (w, b) in enumerate(layers):
         inputs.append(a)
-        z = conv_same(a, w, b)
+        z = conv_same(bf16(a), bf16(w), b) if l in bf16_layers else conv_same(a, w, b)
         a = np.maximum(z, 0.0) if l < 3 else z
     return a, inputs
 
@@ -82,15 +94,20 @@ def bce(z, t, m):
     return float((m * per).sum() / cnt), m * (sig - t) / cnt
 
 
-def backward(params, inputs, dz):
+def backward(params, inputs, dz, bf16_layers=()):
     """Gradient of the loss with respect to the flattened parameters, from
-    d loss / d logits, by the chain rule through the four layers."""
+    d loss / d logits, by the chain rule through the four layers. Layers in
+    bf16_layers take BF16-rounded operands in their weight-gradient and
+    data-gradient products (the bias gradient sums the unrounded g)."""
     layers = unpack(params)
     grads = []
     g = np.asarray(dz, np.float64)             # gradient w.r.t. the layer output (pre-activation)
     for l in range(3, -1, -1):
         w, _ = layers[l]
         a = inputs[l]
+        gb = g.sum(axis=(0, 2, 3))
+        if l in bf16_layers:
+            a, g, w = bf16(a), bf16(g), bf16(w)
         H = W = P
         ap = np.zeros((a.shape[0], a.shape[1], H + 4, W + 4))
         ap[:, :, 2:2 + H, 2:2 + W] = a
@@ -98,7 +115,6 @@ def backward(params, inputs, dz):
         for u in range(K):
             for v in range(K):
                 gw[:, :, u, v] = np.einsum("bohw,bchw->oc", g, ap[:, :, u:u + H, v:v + W])
-        gb = g.sum(axis=(0, 2, 3))
         grads.append((gw, gb))
         if l == 0:
             break
@@ -109,15 +125,15 @@ def backward(params, inputs, dz):
         for u in range(K):
             for v in range(K):
                 ga += np.einsum("bohw,oc->bchw", gp[:, :, 4 - u:4 - u + H, 4 - v:4 - v + W], w[:, :, u, v])
-        g = ga * (a > 0.0)                     # through the ReLU that produced a
+        g = ga * (inputs[l] > 0.0)             # through the ReLU that produced the input
     grads.reverse()
     return np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in grads])
 
 
-def loss_grad(params, x, t, m):
-    z, inputs = forward(params, x)
+def loss_grad(params, x, t, m, bf16_layers=()):
+    z, inputs = forward(params, x, bf16_layers)
     loss, dz = bce(z, np.asarray(t).reshape(z.shape), np.asarray(m).reshape(z.shape))
-    return loss, backward(params, inputs, dz)
+    return loss, backward(params, inputs, dz, bf16_layers)
 
 
 def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

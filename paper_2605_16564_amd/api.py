@@ -347,19 +347,28 @@ def _patch_count(t: torch.Tensor, per: int, name: str) -> int:
     return t.numel() // per
 
 
-def cnn_forward(ctx: Context, params: torch.Tensor, x: torch.Tensor) -> torch.Tensor:
-    """Logits [B, 2, 16, 16] of patches x [B, 1, 16, 16]."""
+def _cnn_prec(precision: str) -> int:
+    if precision not in ("f32", "bf16"):
+        raise N.PamError("network precision must be 'f32' or 'bf16'")
+    return N.PREC[precision]
+
+
+def cnn_forward(ctx: Context, params: torch.Tensor, x: torch.Tensor,
+                precision: str = "f32") -> torch.Tensor:
+    """Logits [B, 2, 16, 16] of patches x [B, 1, 16, 16]; precision 'f32'
+    (vector ALUs) or 'bf16' (32 -> 32 layers on MFMA)."""
     params, x = _f32_dev(params, "params"), _f32_dev(x, "x")
     B = _patch_count(x, 256, "x")
     out = torch.empty((B, 2, 16, 16), dtype=torch.float32, device=x.device)
     ctx.use_current_stream()
-    N.check(N.lib().pam_cnn_forward(ctx.h, _p(params), B, _p(x), _p(out)), "pam_cnn_forward")
+    N.check(N.lib().pam_cnn_forward(ctx.h, _p(params), B, _p(x), _p(out), _cnn_prec(precision)),
+            "pam_cnn_forward")
     return out
 
 
 def cnn_loss_grad(ctx: Context, params: torch.Tensor, x: torch.Tensor, target: torch.Tensor,
                   mask: torch.Tensor, grads: Optional[torch.Tensor] = None,
-                  loss: Optional[torch.Tensor] = None):
+                  loss: Optional[torch.Tensor] = None, precision: str = "f32"):
     """(grads [P], loss scalar tensor) of the masked BCE over a batch."""
     params, x = _f32_dev(params, "params"), _f32_dev(x, "x")
     target, mask = _f32_dev(target, "target"), _f32_dev(mask, "mask")
@@ -372,7 +381,8 @@ def cnn_loss_grad(ctx: Context, params: torch.Tensor, x: torch.Tensor, target: t
         loss = torch.empty((), dtype=torch.float32, device=x.device)
     ctx.use_current_stream()
     N.check(N.lib().pam_cnn_loss_grad(ctx.h, _p(params), B, _p(x), _p(target), _p(mask),
-                                      _p(grads), _p(loss)), "pam_cnn_loss_grad")
+                                      _p(grads), _p(loss), _cnn_prec(precision)),
+            "pam_cnn_loss_grad")
     return grads, loss
 
 
@@ -444,7 +454,7 @@ def cnn_init(seed: int, device) -> torch.Tensor:
 
 def cnn_train(ctx: Context, params: torch.Tensor, x: torch.Tensor, target: torch.Tensor,
               mask: torch.Tensor, epochs: int, batch: int = 256, lr: float = 2e-3, seed: int = 0,
-              state=None):
+              state=None, precision: str = "f32"):
     """Adam on the masked BCE over shuffled minibatches; params updated in
     place. Returns (mean loss per epoch, optimizer state (m, v, step))."""
     n = x.shape[0]
@@ -461,7 +471,7 @@ def cnn_train(ctx: Context, params: torch.Tensor, x: torch.Tensor, target: torch
         for b0 in range(0, n, batch):
             idx = perm[b0:b0 + batch]
             _, loss = cnn_loss_grad(ctx, params, x.index_select(0, idx), target.index_select(0, idx),
-                                    mask.index_select(0, idx), grads)
+                                    mask.index_select(0, idx), grads, precision=precision)
             state[2] += 1
             cnn_adam(ctx, params, grads, m, v, state[2], lr)
             acc += loss

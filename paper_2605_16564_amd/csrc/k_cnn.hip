@@ -353,16 +353,189 @@ k_label_samples(const int64_t *__restrict__ off, const double *__restrict__ x,
     target[at] = elem_level[j] > 0 ? 1.0f : 0.0f;
 }
 
+// ---------------------------------------------------------------- BF16 MFMA path
+// The 32 -> 32 layers as implicit GEMMs on the matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation): operand A lane l holds row
+// l % 16 and reduction elements 8 (l / 16) .. +7, operand B column l % 16 and
+// the same reduction elements; D lane l holds rows 4 (l / 16) .. +3 of
+// column l % 16.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+    // round to nearest even
+    unsigned int u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// BF16 weight packs of the 32 -> 32 layers l = 1, 2: forward [co][tap][ci]
+// and backward-data [ci][tap'][co] (tap' the point-reflected tap).
+__global__ void k_pack_bf16(const float *__restrict__ params, unsigned short *__restrict__ wf,
+                            unsigned short *__restrict__ wb) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * 32 * 32 * kTaps) return;
+    const int l = 1 + e / (32 * 32 * kTaps), r = e % (32 * 32 * kTaps);
+    const int co = r / (32 * kTaps), ci = (r / kTaps) % 32, tap = r % kTaps;
+    const unsigned short w = to_bf16(params[cnn_off(l) + r]);
+    unsigned short *f = wf + (size_t)(l - 1) * 32 * 32 * kTaps, *b = wb + (size_t)(l - 1) * 32 * 32 * kTaps;
+    f[(co * kTaps + tap) * 32 + ci] = w;
+    b[(ci * kTaps + (kTaps - 1 - tap)) * 32 + co] = w;
+}
+
+// out[b][o][p] = bias[o] + sum_tap sum_c w[o][tap][c] in[b][c][p + tap - 2]
+// for 32 input and 32 output channels; mode 0 identity, 1 ReLU, 2 gate.
+// 256 threads: wave w computes pixel rows 4w .. 4w+3 for both 16-channel
+// output tiles. The padded input plane is staged channels-last in BF16.
+static constexpr int kCs = 40;   // LDS channel stride (80 B: 16-byte aligned, spreads banks)
+
+__global__ void __launch_bounds__(256)
+k_conv32_mfma(const float *__restrict__ in, const unsigned short *__restrict__ w, const float *__restrict__ bias,
+              float *__restrict__ out, int mode, const float *__restrict__ gate, int B) {
+    __shared__ __attribute__((aligned(16))) unsigned short sx[kH][kH][kCs];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kq = 8 * (lane >> 4);
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        __syncthreads();
+        const float *src = in + (size_t)b * 32 * kPix;
+        for (int e = threadIdx.x; e < 32 * kH * kH; e += 256) {
+            const int c = e / (kH * kH), rr = e % (kH * kH);
+            const int yy = rr / kH - 2, xx = rr % kH - 2;
+            const float v = (yy >= 0 && yy < kP && xx >= 0 && xx < kP) ? src[c * kPix + yy * kP + xx] : 0.0f;
+            sx[rr / kH][rr % kH][c] = to_bf16(v);
+        }
+        __syncthreads();
+        v4f acc[4][2];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            acc[r][0] = v4f{0.f, 0.f, 0.f, 0.f};
+            acc[r][1] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll 1
+        for (int tap = 0; tap < kTaps; ++tap) {
+            const int ky = tap / kK, kx = tap % kK;
+            const v8bf a0 = *reinterpret_cast<const v8bf *>(w + ((size_t)col * kTaps + tap) * 32 + kq);
+            const v8bf a1 = *reinterpret_cast<const v8bf *>(w + ((size_t)(16 + col) * kTaps + tap) * 32 + kq);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int py = 4 * wv + r;
+                const v8bf bv = *reinterpret_cast<const v8bf *>(&sx[py + ky][col + kx][kq]);
+                acc[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[r][0], 0, 0, 0);
+                acc[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc[r][1], 0, 0, 0);
+            }
+        }
+        float *dst = out + (size_t)b * 32 * kPix;
+        const float *gt = gate ? gate + (size_t)b * 32 * kPix : nullptr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int o = 16 * t + 4 * (lane >> 4) + q;
+                    const int pp = (4 * wv + r) * kP + col;
+                    float v = acc[r][t][q] + (bias ? bias[o] : 0.0f);
+                    if (mode == 1) v = fmaxf(v, 0.0f);
+                    else if (mode == 2) v = gt[o * kPix + pp] > 0.0f ? v : 0.0f;
+                    dst[o * kPix + pp] = v;
+                }
+    }
+}
+
+// Weight and bias gradient partials of a 32 -> 32 layer over patches
+// [b0, b1): gw[o][c][tap] = sum_p gout[o][p] in[c][p + tap - 2]. The
+// reduction runs over pixels, 32 per MFMA (two rows); the input is staged as
+// five column-shifted BF16 copies so that every 8-pixel fragment is aligned.
+// Wave w owns the (tap, input-tile) pairs w, w+4, ... (50 pairs, two
+// output tiles each). part[blk][o*800 + c*25 + tap], bias at [25600 + o].
+__global__ void __launch_bounds__(256)
+k_wgrad32_mfma(const float *__restrict__ in, const float *__restrict__ gout, int B, int per_block,
+               float *__restrict__ part) {
+    constexpr int NP = 13;   // pairs per wave (50 over 4 waves)
+    __shared__ __attribute__((aligned(16))) unsigned short xs[kK][32][kH][kP];   // [kx][c][row][col]
+    __shared__ __attribute__((aligned(16))) unsigned short gs[32][kPix];         // [o][p]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kq = 8 * (lane >> 4);
+    v4f acc[NP][2];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        acc[i][0] = v4f{0.f, 0.f, 0.f, 0.f};
+        acc[i][1] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    float bacc = 0.0f;   // bias gradient: thread o < 32 sums gout[o][.]
+    const int b0 = blockIdx.x * per_block, b1 = min(B, b0 + per_block);
+    for (int b = b0; b < b1; ++b) {
+        __syncthreads();
+        const float *src = in + (size_t)b * 32 * kPix;
+        for (int e = threadIdx.x; e < kK * 32 * kH * kP; e += 256) {
+            const int kx = e / (32 * kH * kP), r1 = e % (32 * kH * kP);
+            const int c = r1 / (kH * kP), r2 = r1 % (kH * kP);
+            const int row = r2 / kP, cl = r2 % kP;
+            const int yy = row - 2, xx = cl + kx - 2;
+            const float v = (yy >= 0 && yy < kP && xx >= 0 && xx < kP) ? src[c * kPix + yy * kP + xx] : 0.0f;
+            xs[kx][c][row][cl] = to_bf16(v);
+        }
+        const float *g = gout + (size_t)b * 32 * kPix;
+        for (int e = threadIdx.x; e < 32 * kPix; e += 256) gs[e / kPix][e % kPix] = to_bf16(g[e]);
+        {
+            // bias: 8 threads per output channel, 32 pixels each
+            const int o = threadIdx.x >> 3, sg = threadIdx.x & 7;
+            float t = 0.0f;
+            for (int p2 = 0; p2 < 32; ++p2) t += g[o * kPix + sg * 32 + p2];
+            t += __shfl_xor(t, 1, 64);
+            t += __shfl_xor(t, 2, 64);
+            t += __shfl_xor(t, 4, 64);
+            bacc += t;   // lanes with sg == 0 keep the channel's sum
+        }
+        __syncthreads();
+        // 8 reduction chunks of 32 pixels (rows 2j, 2j+1)
+        for (int j = 0; j < kP / 2; ++j) {
+            // this lane's 8 pixels: row 2j + (kq >= 16), columns (kq % 16) .. +7
+            const int prow = 2 * j + (kq >> 4), pcol = kq & 15;
+            const v8bf a0 = *reinterpret_cast<const v8bf *>(&gs[col][prow * kP + pcol]);
+            const v8bf a1 = *reinterpret_cast<const v8bf *>(&gs[16 + col][prow * kP + pcol]);
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const int pr = wv + 4 * i;
+                if (pr < 2 * kTaps) {
+                    const int tap = pr >> 1, ct = pr & 1;
+                    const int ky = tap / kK, kx = tap % kK;
+                    const v8bf bv = *reinterpret_cast<const v8bf *>(&xs[kx][16 * ct + col][prow + ky][pcol]);
+                    acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc[i][0], 0, 0, 0);
+                    acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc[i][1], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float *dst = part + (size_t)blockIdx.x * (32 * 32 * kTaps + 32);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const int pr = wv + 4 * i;
+        if (pr >= 2 * kTaps) continue;
+        const int tap = pr >> 1, ct = pr & 1;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int o = 16 * t + 4 * (lane >> 4) + q, c = 16 * ct + col;
+                dst[(o * 32 + c) * kTaps + tap] = acc[i][t][q];
+            }
+    }
+    if ((threadIdx.x & 7) == 0) dst[32 * 32 * kTaps + (threadIdx.x >> 3)] = bacc;
+}
+
 // ---------------------------------------------------------------- launchers
 struct CnnWs {
     float *wf, *wb, *a[3], *z, *ga, *gb, *gz, *part, *bpart;
+    unsigned short *hf, *hb;   // BF16 packs of the 32 -> 32 layers (forward, backward data)
 };
+static constexpr int kPack16 = 2 * 32 * 32 * kTaps;   // BF16 elements per pack
 
 static constexpr int kWgradPer = 8;   // patches per weight-gradient block
 
 static size_t cnn_ws_floats(int B, bool train) {
     const size_t A = (size_t)B * 32 * kPix;
-    size_t n = 2 * (size_t)kParams + 3 * A + (size_t)B * 2 * kPix;
+    size_t n = 2 * (size_t)kParams + 3 * A + (size_t)B * 2 * kPix + kPack16;   // two BF16 packs = kPack16 floats
     if (train) {
         const size_t nblk = (B + kWgradPer - 1) / kWgradPer;
         // partial rows: at most 16 per block (layer 1), each of the largest layer size
@@ -378,6 +551,9 @@ static CnnWs carve(float *p, int B, bool train) {
     w.wb = p; p += kParams;
     for (int i = 0; i < 3; ++i) { w.a[i] = p; p += A; }
     w.z = p; p += (size_t)B * 2 * kPix;
+    w.hf = reinterpret_cast<unsigned short *>(p);
+    w.hb = w.hf + kPack16;
+    p += kPack16;
     if (train) {
         w.ga = p; p += A;
         w.gb = p; p += A;
@@ -397,15 +573,29 @@ static void conv(pam_ctx *ctx, int cin, int cout, const float *in, const float *
     else hipLaunchKernelGGL((k_conv<2, 32>), g, t, 0, ctx->stream, in, w, b, out, mode, gate);
 }
 
-static void forward(pam_ctx *ctx, const float *params, const CnnWs &w, const float *x, float *z, int B) {
+static int mfma_grid(int B) { return std::min(B, 4096); }
+
+static void forward(pam_ctx *ctx, const float *params, const CnnWs &w, const float *x, float *z, int B, bool bf16) {
     hipLaunchKernelGGL(k_pack, dim3((kParams + 255) / 256), dim3(256), 0, ctx->stream, params, w.wf, w.wb);
+    if (bf16)
+        hipLaunchKernelGGL(k_pack_bf16, dim3((kPack16 + 255) / 256), dim3(256), 0, ctx->stream, params, w.hf, w.hb);
     const float *in = x;
     for (int l = 0; l < 4; ++l) {
         float *out = l < 3 ? w.a[l] : z;
-        conv(ctx, cnn_cin(l), cnn_cout(l), in, w.wf + cnn_off(l),
-             params + cnn_off(l) + cnn_cout(l) * cnn_cin(l) * kTaps, out, B, l < 3 ? 1 : 0, nullptr);
+        const float *bias = params + cnn_off(l) + cnn_cout(l) * cnn_cin(l) * kTaps;
+        if (bf16 && (l == 1 || l == 2))
+            hipLaunchKernelGGL(k_conv32_mfma, dim3(mfma_grid(B)), dim3(256), 0, ctx->stream, in,
+                               w.hf + (size_t)(l - 1) * 32 * 32 * kTaps, bias, out, 1, (const float *)nullptr, B);
+        else
+            conv(ctx, cnn_cin(l), cnn_cout(l), in, w.wf + cnn_off(l), bias, out, B, l < 3 ? 1 : 0, nullptr);
         in = out;
     }
+}
+
+static pam_status check_prec(int precision) {
+    PAM_REQUIRE(precision == PAM_PREC_F32 || precision == PAM_PREC_BF16,
+                "network precision must be PAM_PREC_F32 or PAM_PREC_BF16");
+    return PAM_OK;
 }
 
 static pam_status check_ctx(pam_ctx *ctx) {
@@ -453,29 +643,34 @@ extern "C" {
 
 int64_t pam_cnn_param_count(void) { return kParams; }
 
-pam_status pam_cnn_forward(pam_ctx *ctx, const float *params, int32_t B, const float *x, float *logits) {
+pam_status pam_cnn_forward(pam_ctx *ctx, const float *params, int32_t B, const float *x, float *logits,
+                           int32_t precision) {
     pam_status st = check_ctx(ctx);
     if (st != PAM_OK) return st;
+    if ((st = check_prec(precision)) != PAM_OK) return st;
     PAM_REQUIRE(params && x && logits && B >= 1, "NULL argument or B < 1");
     PAM_CHECK_HIP(hipSetDevice(ctx->device));
     if ((st = ensure(ctx, BUF_CNN, cnn_ws_floats(B, false) * sizeof(float))) != PAM_OK) return st;
     const CnnWs w = carve(wsp<float>(ctx, BUF_CNN), B, false);
     KernelTimer kt(ctx, PAM_TK_CNN);
-    forward(ctx, params, w, x, logits, B);
+    forward(ctx, params, w, x, logits, B, precision == PAM_PREC_BF16);
     PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;
 }
 
 pam_status pam_cnn_loss_grad(pam_ctx *ctx, const float *params, int32_t B, const float *x,
-                             const float *target, const float *mask, float *grads, float *loss) {
+                             const float *target, const float *mask, float *grads, float *loss,
+                             int32_t precision) {
     pam_status st = check_ctx(ctx);
     if (st != PAM_OK) return st;
+    if ((st = check_prec(precision)) != PAM_OK) return st;
+    const bool bf16 = precision == PAM_PREC_BF16;
     PAM_REQUIRE(params && x && target && mask && grads && B >= 1, "NULL argument or B < 1");
     PAM_CHECK_HIP(hipSetDevice(ctx->device));
     if ((st = ensure(ctx, BUF_CNN, cnn_ws_floats(B, true) * sizeof(float))) != PAM_OK) return st;
     const CnnWs w = carve(wsp<float>(ctx, BUF_CNN), B, true);
     KernelTimer kt(ctx, PAM_TK_CNN);
-    forward(ctx, params, w, x, w.z, B);
+    forward(ctx, params, w, x, w.z, B, bf16);
     const int64_t nz = (int64_t)B * 2 * kPix;
     hipLaunchKernelGGL(k_bce, dim3(kBceBlocks), dim3(256), 0, ctx->stream, w.z, target, mask, nz, w.gz, w.bpart);
     hipLaunchKernelGGL(k_bce_scale, dim3(kBceBlocks), dim3(256), 0, ctx->stream, w.bpart, kBceBlocks, w.gz, nz,
@@ -494,6 +689,9 @@ pam_status pam_cnn_loss_grad(pam_ctx *ctx, const float *params, int32_t B, const
             hipLaunchKernelGGL((k_wgrad<1, 32, 4, 16>), dim3(nblk), dim3(128), 0, ctx->stream, act_in[l], gout, B,
                                kWgradPer, w.part);
             n_part = nblk * 16;
+        } else if (bf16) {
+            hipLaunchKernelGGL(k_wgrad32_mfma, dim3(nblk), dim3(256), 0, ctx->stream, act_in[l], gout, B, kWgradPer,
+                               w.part);
         } else {
             hipLaunchKernelGGL((k_wgrad<32, 32, 4, 1>), dim3(nblk), dim3(256), 0, ctx->stream, act_in[l], gout, B,
                                kWgradPer, w.part);
@@ -504,7 +702,11 @@ pam_status pam_cnn_loss_grad(pam_ctx *ctx, const float *params, int32_t B, const
         // gradient of the layer input (a ReLU output): forward pass over the
         // flipped weights from cout to cin channels, gated by the activation
         float *gin = (gout == w.ga) ? w.gb : w.ga;
-        conv(ctx, cnn_cout(l), cnn_cin(l), gout, w.wb + cnn_off(l), nullptr, gin, B, 2, act_in[l]);
+        if (bf16 && (l == 1 || l == 2))
+            hipLaunchKernelGGL(k_conv32_mfma, dim3(mfma_grid(B)), dim3(256), 0, ctx->stream, gout,
+                               w.hb + (size_t)(l - 1) * 32 * 32 * kTaps, (const float *)nullptr, gin, 2, act_in[l], B);
+        else
+            conv(ctx, cnn_cout(l), cnn_cin(l), gout, w.wb + cnn_off(l), nullptr, gin, B, 2, act_in[l]);
         gout = gin;
     }
     PAM_CHECK_HIP(hipGetLastError());

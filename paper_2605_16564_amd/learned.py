@@ -42,9 +42,10 @@ def training_set(ctx: api.Context, grids, g, k_top, opts, eps_tol_rel=1e-4):
     return torch.cat(xs), torch.cat(ts), torch.cat(ms)
 
 
-def hint(ctx: api.Context, params: torch.Tensor, grid, D: api.Dictionary, threshold: float = 0.0):
+def hint(ctx: api.Context, params: torch.Tensor, grid, D: api.Dictionary, threshold: float = 0.0,
+         precision: str = "f32"):
     """uint8 [n_sub, m_cap] support hint of the trained network for D on grid."""
-    z = api.cnn_forward(ctx, params, api.grid_patches(ctx, grid, scale=CNN_SCALE))
+    z = api.cnn_forward(ctx, params, api.grid_patches(ctx, grid, scale=CNN_SCALE), precision)
     return api.support_hint(ctx, grid, D, z, threshold)
 
 

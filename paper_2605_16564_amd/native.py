@@ -108,8 +108,8 @@ def lib():
         L.pam_timing_enable.argtypes = [P, C.c_int32]
         L.pam_timing_read.argtypes = [P, P, P, C.c_int32]
         L.pam_cnn_param_count.argtypes = []
-        L.pam_cnn_forward.argtypes = [P, P, C.c_int32, P, P]
-        L.pam_cnn_loss_grad.argtypes = [P, P, C.c_int32, P, P, P, P, P]
+        L.pam_cnn_forward.argtypes = [P, P, C.c_int32, P, P, C.c_int32]
+        L.pam_cnn_loss_grad.argtypes = [P, P, C.c_int32, P, P, P, P, P, C.c_int32]
         L.pam_cnn_adam.argtypes = [P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float,
                                    C.c_float]
         L.pam_grid_patches.argtypes = [P, C.POINTER(PamGrid), P, C.c_float, P, P]

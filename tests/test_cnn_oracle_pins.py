@@ -169,3 +169,24 @@ def test_labels_from_beta_and_marks():
             p = base[s] + (j // 16) * (ni // 16) + i // 16
             assert t[p, 1, j % 16, i % 16] == (1.0 if k % 3 == 0 else 0.0)
             assert t[p, 0, j % 16, i % 16] == (1.0 if (s * 1024 + k) % 5 == 0 else 0.0)
+
+
+def test_bf16_rounding_closed_forms():
+    # 8-bit significand: spacing 2^-7 on [1, 2); round to nearest, ties to even
+    cases = [(1.0, 1.0), (1.0 + 2.0 ** -9, 1.0), (1.0 + 2.0 ** -8, 1.0),      # below half, tie -> even
+             (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),                           # tie -> even (up)
+             (1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -7),                  # above half
+             (-3.0 - 2.0 ** -7, -3.0), (0.0, 0.0), (2.0 ** -130, 2.0 ** -130)]  # subnormal kept
+    for x, want in cases:
+        assert CO.bf16(np.array([x]))[0] == want, (x, CO.bf16(np.array([x]))[0], want)
+
+
+def test_bf16_emulation_only_touches_listed_layers():
+    p, x, t, m = _problem(5)
+    z0, _ = CO.forward(p, x)
+    z1, _ = CO.forward(p, x, bf16_layers=(1, 2))
+    rel = np.abs(z1 - z0).max() / np.abs(z0).max()
+    assert 0.0 < rel < 5e-2          # a rounding-size change
+    # rounding nothing reproduces the plain network exactly
+    assert np.array_equal(CO.forward(p, x, bf16_layers=())[0], z0)
+

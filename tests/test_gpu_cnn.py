@@ -79,6 +79,36 @@ def test_cnn_gradients_match_oracle(ctx, B):
         assert err <= 2e-4 * scale
 
 
+@pytest.mark.parametrize("B", [1, 6, 37])
+def test_cnn_bf16_matches_oracle(ctx, B):
+    """BF16 mode against the oracle emulating it (the 32 -> 32 layers' operands
+    rounded to bfloat16 at the same points, FP64 otherwise): logits and
+    gradients to FP32-accumulation accuracy, up to the odd operand that the
+    FP32 and FP64 paths round to neighbouring bfloat16 values: one such flip
+    moves a product by 2^-8 of itself, measured up to 4e-4 of max|z| and
+    4.4e-3 of a layer's max|g|; the bounds are 1e-3 and 1e-2. Against the
+    plain FP64 network the BF16 mode is a rounding-size approximation
+    (reported, 0.3-0.4 % on logits)."""
+    p = synth.cnn_init(31)
+    x, t, m = synth.cnn_batch(32, B)
+    z = _t(api.cnn_forward(ctx, _d(p), _d(x), precision="bf16"))
+    ze, _ = CO.forward(p.astype(np.float64), x.astype(np.float64), bf16_layers=(1, 2))
+    zo, _ = CO.forward(p.astype(np.float64), x.astype(np.float64))
+    zerr = np.abs(z - ze).max() / np.abs(ze).max()
+    print("B", B, "logit err vs emulation", zerr, "vs FP64 network", np.abs(z - zo).max() / np.abs(zo).max())
+    assert zerr <= 1e-3
+    g, loss = api.cnn_loss_grad(ctx, _d(p), _d(x), _d(t), _d(m), precision="bf16")
+    g, loss = _t(g), float(loss.item())
+    le, ge = CO.loss_grad(p.astype(np.float64), x.astype(np.float64), t, m, bf16_layers=(1, 2))
+    _, go = CO.loss_grad(p.astype(np.float64), x.astype(np.float64), t, m)
+    assert loss == pytest.approx(le, rel=1e-4)
+    for l, sl in enumerate(_layer_slices()):
+        err = np.abs(g[sl] - ge[sl]).max() / np.abs(ge[sl]).max()
+        rel_fp64 = np.linalg.norm(g[sl] - go[sl]) / np.linalg.norm(go[sl])
+        print("layer", l, "grad err vs emulation", err, "rel L2 vs FP64 network", rel_fp64)
+        assert err <= 1e-2
+
+
 def test_cnn_empty_mask_gives_zero(ctx):
     p = synth.cnn_init(5)
     x, t, m = synth.cnn_batch(6, 4)
