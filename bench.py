@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--cpu-sample-subdomains", type=int, default=8)
     ap.add_argument("--cpu-sample-rounds", type=int, default=1)
     ap.add_argument("--no-learned", action="store_true", help="no learned warm start")
+    ap.add_argument("--train-mosaics", type=int, default=12,
+                    help="training fields: mosaics of 8x8 facies256 fields (16384 patches each)")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-ablations", action="store_true",
                     help="skip the one-pattern-off runs (batching, precision, learned)")
@@ -161,22 +163,24 @@ def oracle_check(ctx, api, grid, wl, prec, opts, sample):
                       "L1 over their samples' cells"}
 
 
-def train_learned(ctx, api, wl, prec):
-    """Train the warm-start network on eight fields of other seeds (outside
-    the timed region); returns (params, record)."""
+def train_learned(ctx, api, wl, prec, n_mosaics):
+    """Train the warm-start network (BF16 MFMA path) on the method's own fits
+    of fields of other seeds, outside the timed region: n_mosaics mosaics of
+    8 x 8 facies256 fields, 16384 patches each; returns (params, record)."""
     import torch
     from paper_2605_16564_amd import learned, synth
     opts = api.EnetOpts(wl.lambda1, wl.lambda2, prec)
-    grids = [synth.facies256(seed=2100 + i) for i in range(8)]
+    grids = [synth.facies_mosaic(seed=10000 + 64 * i) for i in range(n_mosaics)]
     t0 = time.perf_counter()
     x, t, m = learned.training_set(ctx, grids, wl.g, wl.k_top, opts, wl.eps_tol_rel)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     params = api.cnn_init(7, x.device)
-    epochs, batch = 12, 128
+    epochs, batch = 4, 1024
     ctx.timing(True)
     ctx.timing_read(reset=True)
-    losses, _ = api.cnn_train(ctx, params, x, t, m, epochs=epochs, batch=batch, lr=2e-3, seed=1)
+    losses, _ = api.cnn_train(ctx, params, x, t, m, epochs=epochs, batch=batch, lr=2e-3, seed=1,
+                              precision="bf16")
     tk = ctx.timing_read(reset=True)
     ctx.timing(False)
     torch.cuda.synchronize()
@@ -186,13 +190,14 @@ def train_learned(ctx, api, wl, prec):
     f_fwd = 2.0 * 256 * 25 * (1 * 32 + 32 * 32 + 32 * 32 + 32 * 2)
     flops = 3.0 * f_fwd * n * epochs
     cnn_ms = tk["cnn"][0]
-    peak = 256 * 64 * 2 * 2.4e9 / 1e12          # FP32 FMA on the vector ALUs, non-packed
+    peak = 2500.0          # dense BF16 MFMA, TFLOP/s (the thin layers run on FP32 vector ALUs)
     ach = flops / (cnn_ms / 1e3) / 1e12
-    rec = {"train_patches": n, "epochs": epochs, "batch": batch, "loss_first": losses[0],
-           "loss_last": losses[-1], "labels_s": t1 - t0, "train_s": t2 - t1,
+    rec = {"train_patches": n, "epochs": epochs, "batch": batch, "precision": "bf16",
+           "loss_first": losses[0], "loss_last": losses[-1], "labels_s": t1 - t0, "train_s": t2 - t1,
            "train_patches_per_s": n * epochs / (t2 - t1),
-           "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                        "frac": ach / peak, "traffic": None, "kernel": "k_conv/k_wgrad"}}
+           "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                        "frac": ach / peak, "traffic": None,
+                        "kernel": "network training (k_conv32_mfma, k_wgrad32_mfma, thin layers)"}}
     return params, rec
 
 
@@ -206,7 +211,7 @@ def learned_gain(ctx, api, grid, wl, prec, params):
     for name, hinted in (("cd_warmup", False), ("hinted", True)):
         ctx.timing(True)
         ctx.timing_read(reset=True)
-        hint = learned.hint(ctx, params, grid, D) if hinted else None
+        hint = learned.hint(ctx, params, grid, D, precision="bf16") if hinted else None
         beta, st = api.fit(ctx, S, D, api.EnetOpts(wl.lambda1, wl.lambda2, prec, support_hint=hint))
         tk = ctx.timing_read(reset=True)
         ctx.timing(False)
@@ -218,7 +223,7 @@ def learned_gain(ctx, api, grid, wl, prec, params):
     out["coef_rel_diff"] = float((b0 - b1).abs().max().item() / b0.abs().max().item())
     x, t, m = learned.training_set(ctx, [grid], wl.g, wl.k_top, api.EnetOpts(wl.lambda1, wl.lambda2, prec),
                                    wl.eps_tol_rel)
-    acc = learned.head_accuracy(api.cnn_forward(ctx, params, x), t, m)
+    acc = learned.head_accuracy(api.cnn_forward(ctx, params, x, "bf16"), t, m)
     out["held_out_accuracy"] = {"refine": acc[0][0], "refine_majority": acc[0][1],
                                 "support": acc[1][0], "support_majority": acc[1][1]}
     return out
@@ -261,12 +266,12 @@ def main():
     params, learned_rec = None, None
     if use_learned:
         from paper_2605_16564_amd import learned
-        params, learned_rec = train_learned(ctx, api, wl, prec)
+        params, learned_rec = train_learned(ctx, api, wl, prec, args.train_mosaics)
 
     def step(batched=True, cold=False, hinted=use_learned, precision=prec):
         S = api.partition(ctx, grid, cell_y)
         D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
-        hint = learned.hint(ctx, params, grid, D) if hinted else None
+        hint = learned.hint(ctx, params, grid, D, precision="bf16") if hinted else None
         o = api.EnetOpts(wl.lambda1, wl.lambda2, precision, cd_sweeps=args.cd_sweeps, batched=batched,
                          support_hint=hint)
         ro = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta,

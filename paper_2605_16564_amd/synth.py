@@ -111,6 +111,20 @@ def facies256(seed: int = 2000, n: int = 256, n_sub: int = 8) -> Grid:
                 0.0, y.ravel().astype(np.float64))
 
 
+def facies_mosaic(seed: int, tiles: int = 8) -> Grid:
+    """tiles x tiles independent facies256 fields (seeds seed, seed+1, ...)
+    side by side: the same cells (1/256), subdomains (32 x 32 cells) and
+    facies statistics as facies256, on [0, tiles]^2."""
+    n = 256 * tiles
+    Y = np.zeros((n, n))
+    for tj in range(tiles):
+        for ti in range(tiles):
+            f = facies256(seed=seed + tj * tiles + ti)
+            Y[tj * 256:(tj + 1) * 256, ti * 256:(ti + 1) * 256] = f.y.reshape(256, 256)
+    return Grid(2, [n, n, 1], [0.0, 0.0, 0.0], [float(tiles), float(tiles), 1.0], [8 * tiles, 8 * tiles, 1],
+                [even_breaks(n, 8 * tiles), even_breaks(n, 8 * tiles), even_breaks(1, 1)], 0.0, Y.ravel())
+
+
 def layered3d(nx: int = 60, ny: int = 220, nz: int = 85, sub=(6, 22, 9), seed: int = 3000) -> Grid:
     """Layered 3-D field: even layers 1 + 1.5 z with z a unit-variance GRF
     (correlation length 10 cells); odd layers a constant background in
