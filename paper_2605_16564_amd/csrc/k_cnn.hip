@@ -176,13 +176,28 @@ k_wgrad(const float *__restrict__ in, const float *__restrict__ gout, int B, int
     }
 }
 
-// sum of n_part partial gradient rows into the layer's gradient slice
-__global__ void k_wgrad_reduce(const float *__restrict__ part, int n_part, int nw, float *__restrict__ grad) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw) return;
-    float s = 0.0f;
-    for (int p = 0; p < n_part; ++p) s += part[(size_t)p * nw + i];
-    grad[i] = s;
+// sum of n_part partial gradient rows into the layer's gradient slice:
+// 64 outputs per block, four slices of the partial rows per output (eight
+// rows in flight per thread), combined in LDS in a fixed order.
+__global__ void __launch_bounds__(256)
+k_wgrad_reduce(const float *__restrict__ part, int n_part, int nw, float *__restrict__ grad) {
+    const int o = blockIdx.x * 64 + (threadIdx.x & 63), sl = threadIdx.x >> 6;
+    float acc = 0.0f;
+    if (o < nw) {
+        int p = sl;
+        for (; p + 28 < n_part; p += 32) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = part[(size_t)(p + 4 * e) * nw + o];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc += v[e];
+        }
+        for (; p < n_part; p += 4) acc += part[(size_t)p * nw + o];
+    }
+    __shared__ float red[4][64];
+    red[sl][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (sl == 0 && o < nw) grad[o] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 // ---------------------------------------------------------------- loss
@@ -467,16 +482,23 @@ k_wgrad32_mfma(const float *__restrict__ in, const float *__restrict__ gout, int
     for (int b = b0; b < b1; ++b) {
         __syncthreads();
         const float *src = in + (size_t)b * 32 * kPix;
-        for (int e = threadIdx.x; e < kK * 32 * kH * kP; e += 256) {
-            const int kx = e / (32 * kH * kP), r1 = e % (32 * kH * kP);
-            const int c = r1 / (kH * kP), r2 = r1 % (kH * kP);
-            const int row = r2 / kP, cl = r2 % kP;
-            const int yy = row - 2, xx = cl + kx - 2;
-            const float v = (yy >= 0 && yy < kP && xx >= 0 && xx < kP) ? src[c * kPix + yy * kP + xx] : 0.0f;
-            xs[kx][c][row][cl] = to_bf16(v);
+        // two adjacent columns per thread and 32-bit store
+        for (int e = threadIdx.x; e < kK * 32 * kH * (kP / 2); e += 256) {
+            const int kx = e / (32 * kH * (kP / 2)), r1 = e % (32 * kH * (kP / 2));
+            const int c = r1 / (kH * (kP / 2)), r2 = r1 % (kH * (kP / 2));
+            const int row = r2 / (kP / 2), cl = 2 * (r2 % (kP / 2));
+            const int yy = row - 2, x0 = cl + kx - 2;
+            const bool ry = yy >= 0 && yy < kP;
+            const float v0 = (ry && x0 >= 0 && x0 < kP) ? src[c * kPix + yy * kP + x0] : 0.0f;
+            const float v1 = (ry && x0 + 1 >= 0 && x0 + 1 < kP) ? src[c * kPix + yy * kP + x0 + 1] : 0.0f;
+            *reinterpret_cast<unsigned int *>(&xs[kx][c][row][cl]) =
+                (unsigned int)to_bf16(v0) | ((unsigned int)to_bf16(v1) << 16);
         }
         const float *g = gout + (size_t)b * 32 * kPix;
-        for (int e = threadIdx.x; e < 32 * kPix; e += 256) gs[e / kPix][e % kPix] = to_bf16(g[e]);
+        for (int e = threadIdx.x; e < 32 * kPix / 2; e += 256) {
+            const float2 gv = reinterpret_cast<const float2 *>(g)[e];
+            reinterpret_cast<unsigned int *>(&gs[0][0])[e] = (unsigned int)to_bf16(gv.x) | ((unsigned int)to_bf16(gv.y) << 16);
+        }
         {
             // bias: 8 threads per output channel, 32 pixels each
             const int o = threadIdx.x >> 3, sg = threadIdx.x & 7;
@@ -531,7 +553,8 @@ struct CnnWs {
 };
 static constexpr int kPack16 = 2 * 32 * 32 * kTaps;   // BF16 elements per pack
 
-static constexpr int kWgradPer = 8;   // patches per weight-gradient block
+static constexpr int kWgradPer = 8;     // patches per weight-gradient block (vector ALU kernels)
+static constexpr int kWgradPer16 = 4;   // patches per block of the MFMA weight gradient
 
 static size_t cnn_ws_floats(int B, bool train) {
     const size_t A = (size_t)B * 32 * kPix;
@@ -539,7 +562,9 @@ static size_t cnn_ws_floats(int B, bool train) {
     if (train) {
         const size_t nblk = (B + kWgradPer - 1) / kWgradPer;
         // partial rows: at most 16 per block (layer 1), each of the largest layer size
-        n += 2 * A + (size_t)B * 2 * kPix + 2 * kBceBlocks + nblk * 16 * (size_t)layer_size(1);
+        const size_t nblk16 = (B + kWgradPer16 - 1) / kWgradPer16;
+        n += 2 * A + (size_t)B * 2 * kPix + 2 * kBceBlocks +
+             std::max(nblk * 16, nblk16) * (size_t)layer_size(1);
     }
     return n;
 }
@@ -690,13 +715,14 @@ pam_status pam_cnn_loss_grad(pam_ctx *ctx, const float *params, int32_t B, const
                                kWgradPer, w.part);
             n_part = nblk * 16;
         } else if (bf16) {
-            hipLaunchKernelGGL(k_wgrad32_mfma, dim3(nblk), dim3(256), 0, ctx->stream, act_in[l], gout, B, kWgradPer,
-                               w.part);
+            n_part = (B + kWgradPer16 - 1) / kWgradPer16;
+            hipLaunchKernelGGL(k_wgrad32_mfma, dim3(n_part), dim3(256), 0, ctx->stream, act_in[l], gout, B,
+                               kWgradPer16, w.part);
         } else {
             hipLaunchKernelGGL((k_wgrad<32, 32, 4, 1>), dim3(nblk), dim3(256), 0, ctx->stream, act_in[l], gout, B,
                                kWgradPer, w.part);
         }
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3((nw + 255) / 256), dim3(256), 0, ctx->stream, w.part, n_part, nw,
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((nw + 63) / 64), dim3(256), 0, ctx->stream, w.part, n_part, nw,
                            grads + cnn_off(l));
         if (l == 0) break;
         // gradient of the layer input (a ReLU output): forward pass over the
