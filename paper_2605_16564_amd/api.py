@@ -103,6 +103,21 @@ class Samples:
         return s
 
 
+def concat_samples(parts: Sequence[Samples]) -> Samples:
+    """Samples of several grids as one batch (subdomains in order)."""
+    off = [np.zeros(1, np.int64)]
+    base = 0
+    for S in parts:
+        off.append(S.off_host[1:] + base)
+        base += int(S.off_host[-1])
+    off_h = np.concatenate(off)
+    dev = parts[0].x.device
+    return Samples(parts[0].dim, int(sum(S.n_sub for S in parts)), int(max(S.n_max for S in parts)),
+                   torch.as_tensor(off_h, device=dev), off_h, torch.cat([S.x for S in parts]),
+                   torch.cat([S.y for S in parts]), torch.cat([S.h for S in parts]),
+                   torch.cat([S.cell for S in parts]) if all(S.cell is not None for S in parts) else None)
+
+
 def partition_count(grid):
     g, brk = _grid_struct(grid)
     n = int(np.prod(grid.n_sub[: grid.dim]))
@@ -164,6 +179,16 @@ class Dictionary:
         s.n_sub, s.dim, s.m_cap = self.n_sub, self.dim, self.m_cap
         s.m, s.c, s.sigma, s.level = _p(self.m), _p(self.c), _p(self.sigma), _p(self.level)
         return s
+
+
+def concat_dicts(parts: Sequence["Dictionary"]) -> "Dictionary":
+    """Dictionaries of several grids (same dim and m_cap) as one batch."""
+    d0 = parts[0]
+    if any(D.m_cap != d0.m_cap or D.dim != d0.dim for D in parts):
+        raise N.PamError("dictionaries to concatenate need the same dim and m_cap")
+    return Dictionary(int(sum(D.n_sub for D in parts)), d0.dim, d0.m_cap, torch.cat([D.m for D in parts]),
+                      torch.cat([D.c for D in parts]), torch.cat([D.sigma for D in parts]),
+                      torch.cat([D.level for D in parts]))
 
 
 def init_lattice(ctx: Context, grid, g: Sequence[int], m_cap: int, sigma_factor: float = 1.0):

@@ -1,0 +1,150 @@
+"""Parity at the configurations' full sizes, in the batched launch the
+benchmark times, on sampled outputs the FP64 oracle computes one by one, and
+on properties that hold at any size (status, FP64 KKT certificate, no query
+outside the domain).
+
+C2: the facies256 field, 8x8 subdomains, FP32 + FP64 pass, the first
+enrichment round: sampled subdomains' dictionaries, element levels and
+coefficients against the oracle. C3: the 60x220x85 layered field, 1188
+subdomains of 8^3 centers, BF16 + FP64 pass: every fit certified, sampled
+coefficients against the oracle. C5: 64 fields in one
+fit (5820 subdomains) and 6.4e7 queries in one evaluation: every fit certified, sampled
+subdomains and sampled queries of the smallest fields against the oracle.
+Tolerances as in the other GPU tests: coefficients 1e-5 of max|beta|
+(FP32/BF16 gate), FP32 evaluation 2e-4."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2605_16564_amd import api, synth  # noqa: E402
+
+L1, L2 = synth.LAMBDA1, synth.LAMBDA2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def _t(x):
+    return x.detach().cpu().numpy()
+
+
+def _sub_problem(Sn, od, subs):
+    """Oracle samples and dictionary restricted to the listed subdomains."""
+    offs = [0]
+    xs, ys, hs = [], [], []
+    for s in subs:
+        a, b = Sn["off"][s], Sn["off"][s + 1]
+        xs.append(Sn["x"][a:b]); ys.append(Sn["y"][a:b]); hs.append(Sn["h"][a:b])
+        offs.append(offs[-1] + b - a)
+    sub = dict(off=np.array(offs, np.int64), x=np.concatenate(xs), y=np.concatenate(ys), h=np.concatenate(hs))
+    D = O.Dictionary(len(subs), od.m_cap, od.dim)
+    for i, s in enumerate(subs):
+        D.m[i] = od.m[s]
+        D.c[i * od.m_cap * od.dim:(i + 1) * od.m_cap * od.dim] = od.c[s * od.m_cap * od.dim:(s + 1) * od.m_cap * od.dim]
+        D.sigma[i * od.m_cap:(i + 1) * od.m_cap] = od.sigma[s * od.m_cap:(s + 1) * od.m_cap]
+        D.level[i * od.m_cap:(i + 1) * od.m_cap] = od.level[s * od.m_cap:(s + 1) * od.m_cap]
+    return sub, D
+
+
+def _coef_err(b_gpu_rows, bo, m, m_cap):
+    worst = 0.0
+    for i, row in enumerate(b_gpu_rows):
+        M = int(m[i])
+        ref = bo[i * m_cap:i * m_cap + M]
+        worst = max(worst, float(np.abs(row[:M] - ref).max() / np.abs(ref).max()))
+    return worst
+
+
+def test_c2_facies256_first_round(ctx):
+    g = synth.facies256()
+    m_cap = 144 + 3 * 204
+    tol = 1e-4 / 256 ** 2
+    S = api.partition(ctx, g)
+    D = api.init_lattice(ctx, g, [12, 12], m_cap)
+    beta, lvl, rounds, rs, st = api.refine(ctx, S, D, api.EnetOpts(L1, L2, "f32"),
+                                           api.RefineOpts(k_top=204, max_rounds=1, eps_tol=tol))
+    torch.cuda.synchronize()
+    stn = api.stats_to_numpy(st)
+    assert np.all(stn["status"] == 0) and stn["kkt"].max() < 1e-9, stn["kkt"].max()
+    subs = [9, 36]
+    Sn = O.partition(g)
+    sub, Ds = _sub_problem(Sn, O.init_dictionary(g, [12, 12], m_cap), subs)
+    Do, bo, lvo, info = O.refine_batch(sub, Ds, L1, L2, k_top=204, max_rounds=1, m_max=1 << 30, eps_tol=tol)
+    Dm, Dc, Dsg, Dlv = _t(D.m), _t(D.c), _t(D.sigma), _t(D.level)
+    lv = _t(lvl)
+    for i, s in enumerate(subs):
+        M = int(Do.m[i])
+        assert Dm[s] == M
+        assert np.array_equal(Dc[s, :M].ravel(), Do.c[i * m_cap * 2:(i * m_cap + M) * 2])
+        assert np.array_equal(Dsg[s, :M], Do.sigma[i * m_cap:i * m_cap + M])
+        assert np.array_equal(Dlv[s, :M], Do.level[i * m_cap:i * m_cap + M])
+        a, b = Sn["off"][s], Sn["off"][s + 1]
+        assert np.array_equal(lv[a:b], lvo[sub["off"][i]:sub["off"][i + 1]])
+    err = _coef_err([_t(beta)[s] for s in subs], bo, Do.m, m_cap)
+    print("C2 sampled coefficient error", err)
+    assert err <= 1e-5
+
+
+def test_c3_layered3d_first_fit(ctx):
+    g = synth.layered3d()
+    assert g.n_subdomains == 1188
+    S = api.partition(ctx, g)
+    D = api.init_lattice(ctx, g, [8, 8, 8], 512)
+    beta, st = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "bf16"))
+    torch.cuda.synchronize()
+    stn = api.stats_to_numpy(st)
+    print("C3 kkt max", stn["kkt"].max(), "support mean", stn["support"].mean(), "CG products", stn["polish"].sum())
+    assert np.all(stn["status"] == 0) and stn["kkt"].max() < 1e-9
+    subs = [100, 777]
+    sub, Ds = _sub_problem(O.partition(g), O.init_dictionary(g, [8, 8, 8], 512), subs)
+    bo, sto, _ = O.fit_batch(sub, Ds, L1, L2)
+    err = _coef_err([_t(beta)[s] for s in subs], bo, Ds.m, 512)
+    print("C3 sampled coefficient error", err)
+    assert err <= 1e-5
+
+
+def test_c5_multifield_fit_and_transfer(ctx):
+    grids = synth.multifield()
+    parts = [api.partition(ctx, g) for g in grids]
+    dicts = [api.init_lattice(ctx, g, [16, 16], 256) for g in grids]
+    S, D = api.concat_samples(parts), api.concat_dicts(dicts)
+    bases = np.cumsum([0] + [d.n_sub for d in dicts])
+    beta, st = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f32"))
+    Q = 1_000_000
+    xs = [synth.uniform_queries(2, Q, seed=7000 + f) for f in range(len(grids))]
+    xq = torch.as_tensor(np.concatenate(xs), device="cuda")
+    nout = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = api.evaluate(ctx, grids, D, beta, xq, q_counts=[Q] * len(grids), n_outside=nout)
+    torch.cuda.synchronize()
+    stn = api.stats_to_numpy(st)
+    print("C5 subdomains", D.n_sub, "kkt max", stn["kkt"].max())
+    assert D.n_sub == sum(g.n_subdomains for g in grids)
+    assert np.all(stn["status"] == 0) and stn["kkt"].max() < 1e-9
+    assert int(nout.item()) == 0
+    o = _t(out)
+    assert np.all(np.isfinite(o))
+    # the smallest fields: the oracle fits them whole and evaluates sampled queries
+    sizes = np.array([g.n_cells[0] for g in grids])
+    for f in np.argsort(sizes, kind="stable")[:2]:
+        g = grids[f]
+        od = O.init_dictionary(g, [16, 16], 256)
+        bo, sto, _ = O.fit_batch(O.partition(g), od, L1, L2)
+        rows = [_t(beta)[bases[f] + s] for s in range(od.n_sub)]
+        err = _coef_err(rows, bo, od.m, 256)
+        pick = np.random.default_rng(int(f)).choice(Q, 2000, replace=False)
+        ref, _ = O.evaluate(O.grid_axis_coords(g), od, bo, xs[f][pick].astype(np.float64))
+        got = o[f * Q + pick].astype(np.float64)
+        eerr = np.abs(got - ref).max()
+        print("C5 field", f, "side", g.n_cells[0], "coefficient error", err, "eval error", eerr)
+        assert err <= 1e-5
+        assert eerr <= 2e-4 * max(1.0, np.abs(ref).max())
