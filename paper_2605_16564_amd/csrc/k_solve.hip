@@ -46,7 +46,7 @@ __host__ __device__ size_t solve_scratch_elems(int m_cap, int npad) {
     // and two per-sample vectors [2][npad]
     return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad;
 }
-size_t solve_lds_bytes(int m_cap) { return (size_t)57 * round_up(m_cap, 8) + 64; }
+size_t solve_lds_bytes(int m_cap) { return (size_t)57 * round_up(m_cap, 8) + 64; }   // 57 B per center: see the carve-out in k_solve
 
 // ---------------------------------------------------------------- reductions
 struct Red {
@@ -908,7 +908,9 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     if ((flags[s_id] & 1) || M <= 0 || a.off[s_id + 1] <= a.off[s_id]) {
         for (int m = threadIdx.x; m < a.m_cap; m += kT) beta_out[m] = 0.0;
         if (st && threadIdx.x == 0) {
-            st->status = (flags[s_id] & 1) ? PAM_ST_UNDERFLOW : PAM_ST_EMPTY;
+            // no centers or no samples is EMPTY (the empty design also flags underflow)
+            const bool empty = M <= 0 || a.off[s_id + 1] <= a.off[s_id];
+            st->status = empty ? PAM_ST_EMPTY : PAM_ST_UNDERFLOW;
             st->cd_sweeps = 0; st->iters = 0; st->support = 0; st->kkt = 0.0;
             st->stream_bytes = 0.0; st->polish = 0; st->reserved = 0;
         }
@@ -1398,12 +1400,28 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     }
 }
 
-pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
-    const size_t lds = solve_lds_bytes(a.m_cap);
-    if (lds > 150 * 1024) {
-        set_error("m_cap too large for the LDS-resident solve (max 2690)");
+// LDS of one workgroup on gfx950 (static + dynamic)
+static constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+
+pam_status solve_check_capacity(int m_cap, int precision) {
+    hipFuncAttributes attr;
+    const void *fn = precision == PAM_PREC_F64 ? (const void *)k_solve<double> : (const void *)k_solve<float>;
+    PAM_CHECK_HIP(hipFuncGetAttributes(&attr, fn));
+    const size_t fixed = attr.sharedSizeBytes;
+    if (solve_lds_bytes(m_cap) + fixed > kLdsPerWorkgroup) {
+        const size_t max_m = ((kLdsPerWorkgroup - fixed - 64) / 57) / 8 * 8;
+        char msg[160];
+        snprintf(msg, sizeof msg, "m_cap too large for the LDS-resident solve (%d; max %zu)", m_cap, max_m);
+        set_error(msg);
         return PAM_ERR_CAPACITY;
     }
+    return PAM_OK;
+}
+
+pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
+    const size_t lds = solve_lds_bytes(a.m_cap);
+    pam_status st = solve_check_capacity(a.m_cap, a.precision);
+    if (st != PAM_OK) return st;
     double *H = wsp<double>(ctx, BUF_H);
     double *scr = wsp<double>(ctx, BUF_VEC);
     const int32_t *flags = wsp<int32_t>(ctx, BUF_FLAGS);

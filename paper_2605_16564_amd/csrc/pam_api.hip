@@ -211,7 +211,7 @@ static pam_status check_fit_args(const pam_samples *S, const pam_dict *D, const 
         nmax = std::max(nmax, n);
     }
     PAM_REQUIRE(nmax <= S->n_max, "n_max is smaller than the largest subdomain");
-    return PAM_OK;
+    return solve_check_capacity(D->m_cap, o->precision);
 }
 
 static pam_status check_ctx(pam_ctx *ctx) {
