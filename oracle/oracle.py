@@ -84,6 +84,12 @@ def lib():
         L.ora_eval.restype = C.c_long
         L.ora_eval.argtypes = [C.c_int, _ip, _dp, C.c_int, _ip, _dp, _dp, _dp, C.c_long, _dp,
                                C.c_int, _dp]
+        L.ora_eval_blend.restype = C.c_long
+        L.ora_eval_blend.argtypes = [C.c_int, _ip, _dp, C.c_double, C.c_int, _ip, _dp, _dp, _dp,
+                                     C.c_long, _dp, C.c_int, _dp]
+        L.ora_interface_jump.restype = C.c_long
+        L.ora_interface_jump.argtypes = [C.c_int, _ip, _dp, C.c_int, _ip, _dp, _dp, _dp, C.c_int,
+                                         _dp]
         _lib = L
     return _lib
 
@@ -303,3 +309,38 @@ def evaluate(axis_x, D: Dictionary, beta, xq, space=0):
     n_out = lib().ora_eval(d, ns, ax, D.m_cap, D.m, D.c, D.sigma, _f64(beta), Q, xq.ravel(),
                            space, out)
     return out, n_out
+
+
+def evaluate_blend(axis_x, D: Dictionary, beta, xq, blend, space=0):
+    """Continuous reconstruction: partition-of-unity average of neighbouring
+    local surrogates (Sec. 2 Step 4 and the remark after it); the weights are
+    defined in the C file. blend = 0 is the owner reconstruction."""
+    d = D.dim
+    xq = _f64(xq).reshape(-1, d)
+    Q = xq.shape[0]
+    out = np.zeros(Q)
+    ns = _i32([len(a) - 1 for a in axis_x])
+    ax = _f64(np.concatenate(axis_x))
+    n_out = lib().ora_eval_blend(d, ns, ax, float(blend), D.m_cap, D.m, D.c, D.sigma, _f64(beta),
+                                 Q, xq.ravel(), space, out)
+    return out, n_out
+
+
+def interface_count(n_sub):
+    """Interior interface pieces of a box partition with n_sub per axis."""
+    n_sub = list(n_sub)
+    tot = int(np.prod(n_sub))
+    return sum(tot // n_sub[a] * (n_sub[a] - 1) for a in range(len(n_sub)))
+
+
+def interface_jump(axis_x, D: Dictionary, beta, n):
+    """Per interior interface piece (axis, then the upper subdomain in linear
+    order): (max, mean) of |K*_A - K*_B| at n^(dim-1) face midpoints."""
+    d = D.dim
+    ns = _i32([len(a) - 1 for a in axis_x])
+    nf = interface_count(ns)
+    out = np.zeros(2 * max(nf, 1))
+    ax = _f64(np.concatenate(axis_x))
+    got = lib().ora_interface_jump(d, ns, ax, D.m_cap, D.m, D.c, D.sigma, _f64(beta), int(n), out)
+    assert got == nf
+    return out[:2 * nf].reshape(nf, 2)

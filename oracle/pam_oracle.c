@@ -23,6 +23,10 @@
  *   Sec. 3.4, Alg. 1 (4)-(5)             enrichment, dictionary update
  *   Sec. 2 Step 4                        global reconstruction / evaluation
  *   Eq. (L2error)                        relative L2 error metric
+ *   Sec. 2 Step 4, Remark after it       interface treatment: averaging of
+ *                                        neighbouring local surrogates and
+ *                                        the jump of the piecewise K* across
+ *                                        subdomain interfaces
  *
  * Readings where the paper is silent (all documented with the design notes):
  *   - the regression is on the Shepard-normalized matrix W, and the surrogate
@@ -738,4 +742,160 @@ long ora_eval(int dim, const int *n_sub, const double *axis_x, int m_cap,
         out[q] = space == 1 ? pow(10.0, v) : v;
     }
     return outside;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Interface treatment (Sec. 2 Step 4 and the remark after it: the piecewise  */
+/* K* is discontinuous across subdomain interfaces in general; a continuous  */
+/* reconstruction averages neighbouring local surrogates).                   */
+/*                                                                           */
+/* Reading (the paper names the idea, not the weights): a tensor-product     */
+/* partition of unity over the subdomain boxes. On each axis, interval j of  */
+/* the owned breakpoints b_0 < ... < b_n has the weight                      */
+/*   omega_j(t) = rho((t - b_j + h_j) / (2 h_j))                on the left  */
+/*                                                 band |t - b_j| < h_j,     */
+/*   omega_j(t) = 1 - rho((t - b_{j+1} + h_{j+1}) / (2 h_{j+1})) on the right */
+/*                                                 band |t - b_{j+1}| < h_{j+1},*/
+/*   1 between the bands and 0 outside [b_j - h_j, b_{j+1} + h_{j+1}],        */
+/* with band half-width h_i = blend * min(L_{i-1}, L_i) at an interior        */
+/* breakpoint (L = interval lengths), h = 0 at the domain ends, and the C1    */
+/* ramp rho(s) = s^2 (3 - 2 s) on [0, 1]. With h = 0 the weight is the        */
+/* half-open indicator of the owned interval (last one closed), so blend = 0  */
+/* gives the owner reconstruction. The blended field is                       */
+/*   K_blend(x) = sum_i w_i(x) K*_i(x),  w_i = prod_a omega_{i_a}(x_a),       */
+/* summed over every subdomain i (zero weights skipped), K*_i the local       */
+/* normalized expansion. Requires 0 <= blend <= 1/2 (bands of one interval    */
+/* do not overlap).                                                           */
+/* ------------------------------------------------------------------------- */
+static double ora_rho(double s)
+{
+    if (s <= 0.0) return 0.0;
+    if (s >= 1.0) return 1.0;
+    return s * s * (3.0 - 2.0 * s);
+}
+
+static double ora_band(const double *bx, int n, int i, double blend)
+{
+    if (i <= 0 || i >= n) return 0.0;
+    return blend * fmin(bx[i] - bx[i - 1], bx[i + 1] - bx[i]);
+}
+
+static double ora_interval_weight(const double *bx, int n, int j, double blend, double t)
+{
+    double w = 1.0;
+    double hl = ora_band(bx, n, j, blend), hr = ora_band(bx, n, j + 1, blend);
+    if (j > 0) {
+        if (hl > 0.0) {
+            if (t <= bx[j] - hl) return 0.0;
+            if (t < bx[j] + hl) w = ora_rho((t - (bx[j] - hl)) / (2.0 * hl));
+        } else if (t < bx[j]) {
+            return 0.0;
+        }
+    }
+    if (j < n - 1) {
+        if (hr > 0.0) {
+            if (t >= bx[j + 1] + hr) return 0.0;
+            if (t > bx[j + 1] - hr) w = 1.0 - ora_rho((t - (bx[j + 1] - hr)) / (2.0 * hr));
+        } else if (t >= bx[j + 1]) {
+            return 0.0;
+        }
+    }
+    return w;
+}
+
+long ora_eval_blend(int dim, const int *n_sub, const double *axis_x, double blend, int m_cap,
+                    const int *m, const double *c, const double *sigma, const double *beta,
+                    long Q, const double *xq, int space, double *out)
+{
+    long outside = 0;
+    int n_tot = 1, off[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+        n_tot *= n_sub[a];
+        if (a > 0) off[a] = off[a - 1] + n_sub[a - 1] + 1;
+    }
+#pragma omp parallel for schedule(static) reduction(+ : outside)
+    for (long q = 0; q < Q; ++q) {
+        const double *x = xq + q * dim;
+        int inside = 1;
+        for (int a = 0; a < dim; ++a) {
+            const double *bx = axis_x + off[a];
+            if (!(x[a] >= bx[0] && x[a] <= bx[n_sub[a]])) inside = 0;
+        }
+        if (!inside) {
+            out[q] = NAN;
+            ++outside;
+            continue;
+        }
+        double acc = 0.0;
+        for (int i = 0; i < n_tot; ++i) {
+            double w = 1.0;
+            int rest = i;
+            for (int a = 0; a < dim; ++a) {
+                int k = rest % n_sub[a];
+                rest /= n_sub[a];
+                w *= ora_interval_weight(axis_x + off[a], n_sub[a], k, blend, x[a]);
+            }
+            if (w == 0.0) continue;
+            acc += w * ora_surrogate(dim, m[i], c + (long)i * m_cap * dim, sigma + (long)i * m_cap,
+                                     beta + (long)i * m_cap, x);
+        }
+        out[q] = space == 1 ? pow(10.0, acc) : acc;
+    }
+    return outside;
+}
+
+/* Jump of the piecewise K* across every interior interface piece: for axis  */
+/* a and each subdomain B with index k_a >= 1 (linear order, axis 0 fastest), */
+/* the face shared with A = B - e_a, sampled at the n^(dim-1) midpoints of a  */
+/* regular n-per-axis subdivision of the face; out[2f] = max |K*_A - K*_B|,  */
+/* out[2f+1] = mean |K*_A - K*_B| over the samples. Faces ordered by axis,    */
+/* then B. Returns the number of faces.                                       */
+long ora_interface_jump(int dim, const int *n_sub, const double *axis_x, int m_cap, const int *m,
+                        const double *c, const double *sigma, const double *beta, int n,
+                        double *out)
+{
+    int ns[3] = {1, 1, 1}, off[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+        ns[a] = n_sub[a];
+        if (a > 0) off[a] = off[a - 1] + n_sub[a - 1] + 1;
+    }
+    int n_tot = ns[0] * ns[1] * ns[2];
+    long f = 0;
+    for (int a = 0; a < dim; ++a) {
+        for (int B = 0; B < n_tot; ++B) {
+            int kk[3] = {B % ns[0], (B / ns[0]) % ns[1], B / (ns[0] * ns[1])};
+            if (kk[a] == 0) continue;
+            int stride = a == 0 ? 1 : (a == 1 ? ns[0] : ns[0] * ns[1]);
+            int A = B - stride;
+            int n_pts = 1;
+            for (int b = 0; b < dim - 1; ++b) n_pts *= n;
+            double mx = 0.0, sum = 0.0;
+            for (int p = 0; p < n_pts; ++p) {
+                double x[3];
+                int rest = p;
+                for (int b = 0; b < dim; ++b) {
+                    const double *bx = axis_x + off[b];
+                    if (b == a) {
+                        x[b] = bx[kk[b]];
+                    } else {
+                        int j = rest % n;
+                        rest /= n;
+                        double lo = bx[kk[b]], hi = bx[kk[b] + 1];
+                        x[b] = lo + (j + 0.5) * (hi - lo) / n;
+                    }
+                }
+                double vA = ora_surrogate(dim, m[A], c + (long)A * m_cap * dim,
+                                          sigma + (long)A * m_cap, beta + (long)A * m_cap, x);
+                double vB = ora_surrogate(dim, m[B], c + (long)B * m_cap * dim,
+                                          sigma + (long)B * m_cap, beta + (long)B * m_cap, x);
+                double j = fabs(vA - vB);
+                if (j > mx) mx = j;
+                sum += j;
+            }
+            out[2 * f] = mx;
+            out[2 * f + 1] = sum / n_pts;
+            ++f;
+        }
+    }
+    return f;
 }
