@@ -47,7 +47,7 @@ CU, LANES, CLOCK = 256, 64, 2.4e9                          # non-packed VALU lan
 # HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB device copy), valid only for the
 # kernel source they were taken on (sha256 prefix of its source files).
-TRAFFIC = {("k_solve<float>", "facies256"): {"src": "eeaeb9f3670fd31c", "bytes_per_launch": 65.15e9}}
+TRAFFIC = {("k_solve<float>", "facies256"): {"src": "c0204f36dadb4d7c", "bytes_per_launch": 65.18e9}}
 TRAFFIC_SOURCES = ["paper_2605_16564_amd/csrc/k_solve.hip", "paper_2605_16564_amd/csrc/pam_internal.h"]
 
 
