@@ -19,7 +19,10 @@ hint map run before the first fit. Beside the timed step the record holds:
 the comparator (the plain GPU fit: one launch per subdomain and kernel, every
 refit from zero, no hint), the learned part's training throughput and gain,
 the error of the GPU coefficients and field against the FP64 oracle on the
-CPU sample, and the oracle's own throughput on that sample.
+CPU sample, the oracle's own throughput on that sample, and the interface
+treatment on the fitted field (continuous reconstruction across subdomain
+interfaces: its throughput and error beside the owner reconstruction's, and
+the interface jump it removes).
 
 Prints one JSON line. `--gpus N` with N > 1 is refused: this build runs on
 one GPU.
@@ -42,7 +45,12 @@ if str(ROOT) not in sys.path:
 # MI355X published peaks used for the roofline fractions.
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # TFLOP/s, dense
-CU, LANES, CLOCK = 256, 64, 2.4e9                          # non-packed VALU lanes per CU
+# Vector ALU issue slots per second from the published vector peaks (an FMA
+# is 2 flops in one slot): FP32 157.3 TFLOP/s, FP64 78.6 TFLOP/s. A FP32
+# transcendental (v_exp_f32) takes 4 FP32 slots (measured at 1/4.4 of the FP32
+# FMA slot rate on this chip).
+SLOTS_F32 = 157.3e12 / 2.0
+SLOTS_F64 = 78.6e12 / 2.0
 
 # HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB device copy), valid only for the
@@ -79,6 +87,10 @@ def parse():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-ablations", action="store_true",
                     help="skip the one-pattern-off runs (batching, precision, learned)")
+    ap.add_argument("--no-continuity", action="store_true",
+                    help="skip the interface-treatment measurements")
+    ap.add_argument("--blend", type=float, default=0.1,
+                    help="interface band half-width as a fraction of the shorter neighbour")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three device copies of 1 GiB (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -229,6 +241,108 @@ def learned_gain(ctx, api, grid, wl, prec, params):
     return out
 
 
+def blend_pairs(grid, m_sub, xq, blend):
+    """Query-center pairs of the continuous reconstruction: per query, each
+    subdomain with non-zero weight contributes its dictionary size."""
+    d = grid.dim
+    ax = []
+    for a in range(d):
+        hcell = (grid.hi[a] - grid.lo[a]) / grid.n_cells[a]
+        ax.append(np.array([grid.lo[a] + float(b) * hcell for b in grid.breaks[a]]))
+    ns = [len(b) - 1 for b in ax]
+    k, nb = [], []
+    for a in range(d):
+        b, t = ax[a], xq[:, a]
+        ka = np.clip(np.searchsorted(b, t, side="right") - 1, 0, ns[a] - 1)
+        h = np.zeros(ns[a] + 1)
+        for i in range(1, ns[a]):
+            h[i] = blend * min(b[i] - b[i - 1], b[i + 1] - b[i])
+        right = (ka + 1 < ns[a]) & (t > b[np.minimum(ka + 1, ns[a])] - h[np.minimum(ka + 1, ns[a])])
+        left = (ka > 0) & ~right & (t < b[ka] + h[ka])
+        k.append(ka)
+        nb.append(np.where(right, 1, np.where(left, -1, 0)))
+    stride = np.cumprod([1] + ns[:-1])
+    pairs = 0.0
+    for c in range(1 << d):
+        ok = np.ones(len(xq), bool)
+        sub = np.zeros(len(xq), np.int64)
+        for a in range(d):
+            if (c >> a) & 1:
+                ok &= nb[a] != 0
+                sub += (k[a] + nb[a]) * stride[a]
+            else:
+                sub += k[a] * stride[a]
+        pairs += float(m_sub[sub[ok]].sum())
+    return pairs
+
+
+def continuity(ctx, api, grid, D, beta, xq, w_d, ycell, area, blend, reps=3):
+    """Interface treatment on the fitted field: the continuous reconstruction
+    timed beside the owner one (HIP events on the library's stream), both
+    fields' L1 errors, and the jumps of each across the interfaces."""
+    import torch
+    Q = int(xq.shape[0])
+    ctx.timing(True)
+    res = {}
+    for name in ("owner", "blend"):
+        run = (lambda: api.evaluate(ctx, grid, D, beta, xq)) if name == "owner" else \
+            (lambda: api.evaluate_blend(ctx, grid, D, beta, xq, blend))
+        out = run()
+        torch.cuda.synchronize()
+        ctx.timing_read(reset=True)
+        for _ in range(reps):
+            out = run()
+        tk = ctx.timing_read(reset=True)
+        ms = (tk["eval_bin"][0] + tk["eval" if name == "owner" else "blend"][0]) / reps
+        l1 = float((w_d * (out.double() - ycell).abs()).sum().item()) / area
+        res[name] = {"ms": ms, "query_evals_per_s": Q / (ms / 1e3), "field_l1_log10": l1,
+                     "kernel_ms": (tk["eval" if name == "owner" else "blend"][0]) / reps}
+    ctx.timing(False)
+    # jumps: the owner field's interface jump at 64 midpoints per face, and
+    # both fields' one-sided differences across the same points
+    n = 64 if grid.dim == 2 else 8
+    J = api.interface_jump(ctx, grid, D, beta, n).cpu().numpy()
+    ax = api.axis_coords(grid)
+    pts, nrm = [], []
+    ns = [len(b) - 1 for b in ax]
+    for a in range(grid.dim):
+        for i in range(1, ns[a]):
+            others = [b for b in range(grid.dim) if b != a]
+            grids1 = [np.linspace(ax[b][0], ax[b][-1], 4 * n * ns[b] + 1)[1:-1] for b in others]
+            mesh = np.meshgrid(*grids1, indexing="ij")
+            P = np.zeros((mesh[0].size, grid.dim))
+            for j, b in enumerate(others):
+                P[:, b] = mesh[j].ravel()
+            P[:, a] = ax[a][i]
+            pts.append(P)
+            nrm.append(np.full(len(P), a))
+    P, A = np.concatenate(pts), np.concatenate(nrm)
+    eps = 1e-7 * float(np.min(grid.cell_size))
+    lo, hi = P.copy(), P.copy()
+    lo[np.arange(len(P)), A] -= eps
+    hi[np.arange(len(P)), A] += eps
+    X = torch.as_tensor(np.concatenate([lo, hi]), device=xq.device)
+    vo = api.evaluate(ctx, grid, D, beta, X).cpu().numpy()
+    vb = api.evaluate_blend(ctx, grid, D, beta, X, blend).cpu().numpy()
+    m = len(P)
+    pairs = blend_pairs(grid, D.m.cpu().numpy().astype(np.float64), xq.cpu().numpy().astype(np.float64),
+                        blend)
+    peak_pairs = SLOTS_F32 / 11.0
+    ach = pairs / (res["blend"]["kernel_ms"] / 1e3)
+    return {
+        "blend": blend, "queries": Q,
+        "owner": res["owner"], "continuous": res["blend"],
+        "interface_jump_owner": {"faces": int(len(J)), "samples_per_face": n ** (grid.dim - 1),
+                                 "max": float(J[:, 0].max()), "mean": float(J[:, 1].mean())},
+        "one_sided_difference": {"points": m, "eps": eps,
+                                 "owner_max": float(np.abs(vo[:m] - vo[m:]).max()),
+                                 "continuous_max": float(np.abs(vb[:m] - vb[m:]).max())},
+        "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
+                     "unit": "Tpair/s", "frac": ach / peak_pairs,
+                     "kernel": "k_eval_chunks<float, true>", "pairs_per_launch": pairs},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -346,8 +460,8 @@ def main():
             return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                     "frac": ach / peak, "traffic": None, "kernel": "k_gram_" + prec}
         if kind == "eval":
-            # FP32 pair = 7 VALU lane-ops + one quarter-rate exp (4 issue slots)
-            peak_pairs = CU * LANES * CLOCK / 11.0
+            # FP32 pair = 7 VALU slots + one exp (4 slots)
+            peak_pairs = SLOTS_F32 / 11.0
             per_launch = eval_pairs / launches
             ach = per_launch / avg_s
             return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
@@ -366,15 +480,15 @@ def main():
                     "traffic_unit": "GB per launch",
                     "algorithmic": per_launch / 1e9, "kernel": kname}
         if kind == "indicator":
-            # FP64 pair: software exp (about 20 FP64 lane-ops) + 12 others
-            peak_pairs = CU * LANES * CLOCK / 32.0
+            # FP64 pair: software exp (about 20 FP64 slots) + 12 others
+            peak_pairs = SLOTS_F64 / 32.0
             per_launch = pairs_ind / launches
             ach = per_launch / avg_s
             return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
                     "unit": "Tpair/s", "frac": ach / peak_pairs, "traffic": None,
                     "kernel": "k_indicator"}
         if kind == "assemble":
-            peak_pairs = CU * LANES * CLOCK / (32.0 if prec == "f64" else 11.0)
+            peak_pairs = SLOTS_F64 / 32.0 if prec == "f64" else SLOTS_F32 / 11.0
             per_launch = pairs_design / launches
             ach = per_launch / avg_s
             return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
@@ -412,6 +526,8 @@ def main():
         "roofline": roof,
     }
     rec["config"]["learned_warm_start"] = bool(use_learned)
+    if not args.no_continuity:
+        rec["continuity"] = continuity(ctx, api, grid, D, beta, xq, w_d, ycell, area, args.blend)
     if use_learned:
         learned_rec["gain_first_fit"] = learned_gain(ctx, api, grid, wl, prec, params)
         rec["learned"] = learned_rec

@@ -247,6 +247,56 @@ pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
                     int64_t Q, void *out, int32_t space, int64_t *n_outside);
 
 /* ------------------------------------------------------------------------
+ * Interface treatment (Sec. 2 Step 4 and the remark after it: the piecewise
+ * K* of independent local fits is discontinuous across subdomain interfaces
+ * in general; a continuous reconstruction averages neighbouring local
+ * surrogates).
+ *
+ * Weights: a tensor-product partition of unity over the owned boxes. At an
+ * interior breakpoint b_i of an axis, with neighbouring interval lengths
+ * L_{i-1}, L_i, the band |t - b_i| < h_i, h_i = blend * min(L_{i-1}, L_i),
+ * gives the interval on the left the weight 1 - rho(s) and the one on the
+ * right rho(s), s = (t - b_i + h_i) / (2 h_i), rho(s) = s^2 (3 - 2 s) (C1);
+ * outside the bands the owner interval has weight 1. The weight of a
+ * subdomain is the product over the axes, and
+ *   K_blend(x) = sum_i w_i(x) K*_i(x)
+ * over the (at most 2^dim) subdomains with w_i(x) > 0, K*_i the local
+ * normalized expansion over subdomain i's whole dictionary. The result is
+ * continuous (C1 in the weights), equals the owner reconstruction
+ * bit-for-bit outside the bands, and at an interface is the mean of the two
+ * one-sided local surrogates. blend = 0 gives pam_eval's result exactly.
+ * With a fit overlap delta > 0 (pam_grid.overlap), blend <= delta keeps every
+ * surrogate inside the region it was fitted on.
+ * ------------------------------------------------------------------------ */
+
+/* Continuous reconstruction at the query points. Arguments as pam_eval, plus
+ * blend in [0, 1/2] (PAM_ERR_ARG otherwise). Averaging is in log10 space;
+ * space 1 exponentiates the averaged value. The per-query sum runs in a fixed
+ * order, so results do not depend on the binning. Workspace: 2^dim slots of
+ * the query type plus 2^dim int64 positions per query, from the context. */
+pam_status pam_eval_blend(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
+                          const pam_dict *dict, const double *beta, double blend, int32_t dtype,
+                          const void *xq, int64_t Q, void *out, int32_t space,
+                          int64_t *n_outside);
+
+/* [host] Number of interior interface pieces of the fields' partitions:
+ * sum over fields and axes a of (n_a - 1) * prod_{b != a} n_b; -1 on bad
+ * arguments. No device work. */
+int64_t pam_interface_count(int32_t n_fields, const pam_field *fields);
+
+/* Jump of the piecewise reconstruction across every interior interface
+ * piece, in FP64. Pieces are ordered by field, then axis a, then the upper
+ * subdomain B (k_a >= 1) in linear order (axis 0 fastest); the lower one is
+ * A = B - e_a. Each piece is sampled at the n_per_axis^(dim-1) midpoints of
+ * a regular subdivision of B's face at b = B's lower breakpoint on axis a.
+ * out: device double [2 * pam_interface_count], per piece
+ * (max |K*_A - K*_B|, mean |K*_A - K*_B|). Query ranges of the fields are
+ * ignored. n_per_axis in [1, 4096] and at most 2^24 samples per piece. */
+pam_status pam_interface_jump(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
+                              const pam_dict *dict, const double *beta, int32_t n_per_axis,
+                              double *out);
+
+/* ------------------------------------------------------------------------
  * Learned warm start (not part of the paper's method: a support prior for
  * the cold elastic-net fits). A four-layer convolutional network, 5x5
  * "same" convolutions with zero padding, 1 -> 32 -> 32 -> 32 -> 2 channels,
@@ -321,11 +371,15 @@ pam_status pam_cnn_labels(pam_ctx *ctx, const pam_grid *grid, const pam_samples 
  * context is bracketed by HIP events on the context's stream.
  * pam_timing_read synchronizes the stream and returns, per kernel kind, the
  * summed device time in milliseconds and the number of launches since the
- * last reset; reset = 1 clears the totals afterwards.
+ * last reset; reset = 1 clears the totals afterwards. EVAL_BIN covers the
+ * query (or term) binning passes of both reconstructions and the weighted
+ * sum of the continuous one; EVAL and BLEND the evaluation of the binned
+ * queries and terms; JUMP the interface-jump kernel.
  * ------------------------------------------------------------------------ */
 enum {
     PAM_TK_GATHER = 0, PAM_TK_LATTICE, PAM_TK_ASSEMBLE, PAM_TK_GRAM, PAM_TK_SOLVE,
-    PAM_TK_INDICATOR, PAM_TK_MARK, PAM_TK_EVAL_BIN, PAM_TK_EVAL, PAM_TK_CNN, PAM_TK_COUNT
+    PAM_TK_INDICATOR, PAM_TK_MARK, PAM_TK_EVAL_BIN, PAM_TK_EVAL, PAM_TK_CNN,
+    PAM_TK_BLEND, PAM_TK_JUMP, PAM_TK_COUNT
 };
 pam_status pam_timing_enable(pam_ctx *ctx, int32_t on);
 pam_status pam_timing_read(pam_ctx *ctx, double *ms /*[host] PAM_TK_COUNT*/,

@@ -309,18 +309,9 @@ def axis_coords(grid) -> List[np.ndarray]:
     return out
 
 
-def evaluate(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.Tensor,
-             q_counts: Optional[Sequence[int]] = None, sub_bases: Optional[Sequence[int]] = None,
-             space: int = 0, n_outside: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """K*(x) of one or several fields (subdomains concatenated in D) at xq.
-    xq is float32 or float64 [Q, dim]; field f owns q_counts[f] consecutive rows."""
-    if not isinstance(grids, (list, tuple)):
-        grids = [grids]
-    _require_cuda(xq, "xq")
-    dtype = 0 if xq.dtype == torch.float32 else 1
-    if xq.dtype not in (torch.float32, torch.float64):
-        raise N.PamError("xq must be float32 or float64")
-    Q = int(xq.shape[0])
+def _field_table(grids, Q, q_counts, sub_bases):
+    """pam_field array (and the breakpoint arrays it points into) for one or
+    several fields whose subdomains are concatenated in one dictionary."""
     if q_counts is None:
         q_counts = [Q]
     if sub_bases is None:
@@ -342,6 +333,26 @@ def evaluate(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.T
         F.sub_base = int(sub_bases[f])
         F.q_begin, F.q_end = q0, q0 + int(q_counts[f])
         q0 += int(q_counts[f])
+    return fields, keep
+
+
+def _query_dtype(xq: torch.Tensor) -> int:
+    _require_cuda(xq, "xq")
+    if xq.dtype not in (torch.float32, torch.float64):
+        raise N.PamError("xq must be float32 or float64")
+    return 0 if xq.dtype == torch.float32 else 1
+
+
+def evaluate(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.Tensor,
+             q_counts: Optional[Sequence[int]] = None, sub_bases: Optional[Sequence[int]] = None,
+             space: int = 0, n_outside: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """K*(x) of one or several fields (subdomains concatenated in D) at xq.
+    xq is float32 or float64 [Q, dim]; field f owns q_counts[f] consecutive rows."""
+    if not isinstance(grids, (list, tuple)):
+        grids = [grids]
+    dtype = _query_dtype(xq)
+    Q = int(xq.shape[0])
+    fields, keep = _field_table(grids, Q, q_counts, sub_bases)
     out = torch.empty(Q, dtype=xq.dtype, device=xq.device)
     ds = D.struct()
     ctx.use_current_stream()
@@ -349,6 +360,53 @@ def evaluate(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.T
                              _p(xq.contiguous()), Q, _p(out), int(space), _p(n_outside)),
             "pam_eval")
     return out
+
+
+def evaluate_blend(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.Tensor,
+                   blend: float, q_counts: Optional[Sequence[int]] = None,
+                   sub_bases: Optional[Sequence[int]] = None, space: int = 0,
+                   n_outside: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Continuous reconstruction: neighbouring local surrogates averaged over
+    interface bands of half-width blend * (shorter neighbouring interval).
+    Arguments as evaluate; blend = 0 gives evaluate's result exactly."""
+    if not isinstance(grids, (list, tuple)):
+        grids = [grids]
+    dtype = _query_dtype(xq)
+    Q = int(xq.shape[0])
+    fields, keep = _field_table(grids, Q, q_counts, sub_bases)
+    out = torch.empty(Q, dtype=xq.dtype, device=xq.device)
+    ds = D.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_eval_blend(ctx.h, len(grids), fields, C.byref(ds), _p(beta), float(blend),
+                                   dtype, _p(xq.contiguous()), Q, _p(out), int(space),
+                                   _p(n_outside)),
+            "pam_eval_blend")
+    return out
+
+
+def interface_count(grids) -> int:
+    if not isinstance(grids, (list, tuple)):
+        grids = [grids]
+    fields, keep = _field_table(grids, 0, [0] * len(grids), None)
+    return int(N.lib().pam_interface_count(len(grids), fields))
+
+
+def interface_jump(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, n_per_axis: int,
+                   sub_bases: Optional[Sequence[int]] = None) -> torch.Tensor:
+    """float64 [n_interfaces, 2]: (max, mean) |K*_A - K*_B| on every interior
+    interface piece, ordered by field, axis, then upper subdomain."""
+    if not isinstance(grids, (list, tuple)):
+        grids = [grids]
+    fields, keep = _field_table(grids, 0, [0] * len(grids), sub_bases)
+    nf = int(N.lib().pam_interface_count(len(grids), fields))
+    if nf < 0:
+        raise N.PamError("bad field table")
+    out = torch.empty((max(nf, 1), 2), dtype=torch.float64, device=beta.device)
+    ds = D.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_interface_jump(ctx.h, len(grids), fields, C.byref(ds), _p(beta),
+                                       int(n_per_axis), _p(out)), "pam_interface_jump")
+    return out[:nf]
 
 
 # ---------------------------------------------------------------- learned warm start

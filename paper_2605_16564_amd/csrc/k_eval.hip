@@ -1,10 +1,20 @@
 // Global reconstruction kernels (gfx950): K*(x) = normalized expansion of
-// the subdomain that owns x (Sec. 2 Step 4), at arbitrary query points.
+// the subdomain that owns x (Sec. 2 Step 4), at arbitrary query points; the
+// continuous variant that averages neighbouring local surrogates across
+// interfaces (the remark after Step 4); and the interface jump of the
+// piecewise field.
 //
 // Queries are binned by owner (histogram, scan, scatter) so that a block
 // evaluates up to kQ queries of one subdomain against that subdomain's
 // centers, staged once in LDS and read as broadcasts. The per-query sums run
 // in a fixed center order, so results do not depend on the binning order.
+//
+// The continuous variant bins terms instead of queries: a query inside an
+// interface band of width 2h has, per axis, its owner interval and one
+// neighbour, so up to 2^dim (subdomain, weight) terms. Term c of query q
+// (bit a of c set = neighbour on axis a) is evaluated like a query of that
+// subdomain into slot q * 2^dim + c; a last pass sums the slots of each
+// query in c order with the tensor-product weights.
 #include <float.h>
 
 #include <string.h>
@@ -49,6 +59,90 @@ __device__ __forceinline__ int owner_of(const EvalTables &t, int f, const TQ *xq
         pos += n + 1;
     }
     return F.sub_base + sub;
+}
+
+// Interface weights. At interior breakpoint b_i the band half-width is
+// h_i = blend * min(L_{i-1}, L_i) (L = interval lengths); in the band the
+// interval on the left has weight 1 - rho(s) and the one on the right rho(s),
+// s = (t - b_i + h_i) / (2 h_i), with the C1 ramp rho(s) = s^2 (3 - 2 s).
+// blend <= 1/2 keeps the two bands of an interval apart, so a point sees its
+// owner interval and at most one neighbour per axis.
+struct AxisTerm {
+    int k;          // owner interval
+    int nb;         // neighbour offset: -1, +1, or 0 (none)
+    double w_own, w_nb;
+};
+
+__device__ __forceinline__ double ramp(double s) {
+    return s <= 0.0 ? 0.0 : (s >= 1.0 ? 1.0 : s * s * (3.0 - 2.0 * s));
+}
+
+// Per-axis terms of query q of field f; returns the owner subdomain (field
+// local) or -1 outside the closed domain.
+template <typename TQ>
+__device__ __forceinline__ int axis_terms(const EvalTables &t, int f, const TQ *xq, int64_t q,
+                                          double blend, AxisTerm *at, int *stride_out) {
+    const FieldDev F = t.fields[f];
+    int sub = 0, stride = 1, pos = F.axis_off;
+    for (int d = 0; d < F.dim; ++d) {
+        const double v = (double)xq[q * F.dim + d];
+        const int n = F.n_sub_axis[d];
+        const double *bx = t.axis + pos;
+        if (!(v >= bx[0] && v <= bx[n])) return -1;
+        int k = n - 1;
+        for (int i = 0; i < n; ++i)
+            if (v < bx[i + 1]) { k = i; break; }
+        AxisTerm a{k, 0, 1.0, 0.0};
+        if (k + 1 < n) {   // band at the right breakpoint
+            const double h = blend * fmin(bx[k + 1] - bx[k], bx[k + 2] - bx[k + 1]);
+            if (h > 0.0 && v > bx[k + 1] - h) {
+                const double r = ramp((v - (bx[k + 1] - h)) / (2.0 * h));
+                a.nb = 1;
+                a.w_own = 1.0 - r;
+                a.w_nb = r;
+            }
+        }
+        if (k > 0 && a.nb == 0) {   // band at the left breakpoint
+            const double h = blend * fmin(bx[k] - bx[k - 1], bx[k + 1] - bx[k]);
+            if (h > 0.0 && v < bx[k] + h) {
+                const double r = ramp((v - (bx[k] - h)) / (2.0 * h));
+                a.nb = -1;
+                a.w_own = r;
+                a.w_nb = 1.0 - r;
+            }
+        }
+        at[d] = a;
+        stride_out[d] = stride;
+        sub += k * stride;
+        stride *= n;
+        pos += n + 1;
+    }
+    return sub;
+}
+
+// Term c of a query with axis terms at: weight (0 if the term is absent) and
+// subdomain offset from the owner.
+__device__ __forceinline__ double term_weight(int dim, const AxisTerm *at, const int *stride, int c,
+                                              int *dsub) {
+    double w = 1.0;
+    int o = 0;
+    for (int d = 0; d < dim; ++d) {
+        if ((c >> d) & 1) {
+            if (at[d].nb == 0) return 0.0;
+            w *= at[d].w_nb;
+            o += at[d].nb * stride[d];
+        } else {
+            w *= at[d].w_own;
+        }
+    }
+    *dsub = o;
+    return w;
+}
+
+__device__ __forceinline__ int field_of(const EvalTables &t, int64_t q) {
+    int f = 0;
+    while (f + 1 < t.n_fields && q >= t.fields[f].q_end) ++f;
+    return f;
 }
 
 // Owner of every query and the per-subdomain query counts. Counts go to an
@@ -166,6 +260,132 @@ k_scatter(int64_t Q, int n_sub, const int32_t *__restrict__ owner, const int64_t
     }
 }
 
+// Continuous variant, pass 1: terms of every query and the per-subdomain
+// term counts (LDS histogram as in k_owner). Outside points get NaN.
+template <typename TQ>
+__global__ void __launch_bounds__(kE)
+k_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, double blend,
+        int32_t *__restrict__ hist, TQ *__restrict__ out, unsigned long long *__restrict__ n_out) {
+    __shared__ int32_t lh[kBinsLds];
+    const bool local = n_sub <= kBinsLds;
+    if (local)
+        for (int b = threadIdx.x; b < n_sub; b += kE) lh[b] = 0;
+    __syncthreads();
+    for (int64_t q = (int64_t)blockIdx.x * kE + threadIdx.x; q < Q; q += (int64_t)gridDim.x * kE) {
+        const int f = field_of(t, q);
+        const int dim = t.fields[f].dim;
+        AxisTerm at[3];
+        int stride[3];
+        int o = -1;
+        if (q >= t.fields[f].q_begin && q < t.fields[f].q_end)
+            o = axis_terms(t, f, xq, q, blend, at, stride);
+        if (o < 0) {
+            out[q] = (TQ)NAN;
+            if (n_out) atomicAdd(n_out, 1ull);
+            continue;
+        }
+        o += t.fields[f].sub_base;
+        for (int c = 0; c < (1 << dim); ++c) {
+            int ds = 0;
+            if (term_weight(dim, at, stride, c, &ds) > 0.0) {
+                if (local) atomicAdd(&lh[o + ds], 1);
+                else atomicAdd(&hist[o + ds], 1);
+            }
+        }
+    }
+    __syncthreads();
+    if (local)
+        for (int b = threadIdx.x; b < n_sub; b += kE)
+            if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
+// Continuous variant, pass 2: binned positions of the terms (term id
+// q * 2^dim + c), ranked in LDS per block like k_scatter. The terms are
+// recomputed from the query, bit-identically to pass 1.
+static constexpr int kTermPer = 2;                 // queries per thread
+static constexpr int kTermBlk = kE * kTermPer;     // queries per block
+
+template <typename TQ>
+__global__ void __launch_bounds__(kE)
+k_scatter_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, double blend,
+                const int64_t *__restrict__ base, int32_t *__restrict__ cursor,
+                int64_t *__restrict__ perm) {
+    __shared__ int32_t lcount[kBinsLds];
+    __shared__ int32_t lbase[kBinsLds];
+    const bool local = n_sub <= kBinsLds;
+    const int64_t q0 = (int64_t)blockIdx.x * kTermBlk;
+    if (local) {
+        for (int b = threadIdx.x; b < n_sub; b += kE) lcount[b] = 0;
+        __syncthreads();
+    }
+    int ow[kTermPer][8], rk[kTermPer][8];
+#pragma unroll
+    for (int e = 0; e < kTermPer; ++e) {
+        const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) { ow[e][c] = -1; rk[e][c] = 0; }
+        if (q >= Q) continue;
+        const int f = field_of(t, q);
+        if (q < t.fields[f].q_begin || q >= t.fields[f].q_end) continue;
+        const int dim = t.fields[f].dim;
+        AxisTerm at[3];
+        int stride[3];
+        const int o = axis_terms(t, f, xq, q, blend, at, stride);
+        if (o < 0) continue;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            int ds = 0;
+            if (c < (1 << dim) && term_weight(dim, at, stride, c, &ds) > 0.0) {
+                ow[e][c] = t.fields[f].sub_base + o + ds;
+                if (local) rk[e][c] = atomicAdd(&lcount[ow[e][c]], 1);
+                else perm[base[ow[e][c]] + atomicAdd(&cursor[ow[e][c]], 1)] = (q << dim) | c;
+            }
+        }
+    }
+    if (!local) return;
+    __syncthreads();
+    for (int b = threadIdx.x; b < n_sub; b += kE)
+        if (lcount[b]) lbase[b] = atomicAdd(&cursor[b], lcount[b]);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kTermPer; ++e) {
+        const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
+        if (q >= Q) continue;
+        const int dim = t.fields[field_of(t, q)].dim;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (ow[e][c] >= 0) perm[base[ow[e][c]] + lbase[ow[e][c]] + rk[e][c]] = (q << dim) | c;
+    }
+}
+
+// Continuous variant, pass 4: out[q] = sum_c w_c K*_{sub(c)}(x_q) over the
+// present terms in c order (FP64 weights and sum), then 10^ if asked.
+template <typename TQ>
+__global__ void __launch_bounds__(kE)
+k_combine(EvalTables t, const TQ *__restrict__ xq, int64_t Q, double blend,
+          const TQ *__restrict__ tval, TQ *__restrict__ out, int space) {
+    for (int64_t q = (int64_t)blockIdx.x * kE + threadIdx.x; q < Q; q += (int64_t)gridDim.x * kE) {
+        const int f = field_of(t, q);
+        if (q < t.fields[f].q_begin || q >= t.fields[f].q_end) continue;
+        const int dim = t.fields[f].dim;
+        AxisTerm at[3];
+        int stride[3];
+        if (axis_terms(t, f, xq, q, blend, at, stride) < 0) continue;
+        double acc = 0.0;
+        for (int c = 0; c < (1 << dim); ++c) {
+            int ds = 0;
+            const double w = term_weight(dim, at, stride, c, &ds);
+            if (w > 0.0) acc += w * (double)tval[(q << dim) | c];
+        }
+        TQ v = (TQ)acc;
+        if (space == 1) {
+            if constexpr (sizeof(TQ) == 4) v = exp10f(v);
+            else v = exp10(v);
+        }
+        out[q] = v;
+    }
+}
+
 // Chunk table: chunk c -> (subdomain, first binned position, count).
 __global__ void __launch_bounds__(kE)
 k_chunks(int n_sub, const int32_t *__restrict__ hist, const int64_t *__restrict__ base,
@@ -186,14 +406,17 @@ k_chunks(int n_sub, const int32_t *__restrict__ hist, const int64_t *__restrict_
 // Evaluation of one chunk. FP32 path: squared distance by direct differences
 // in FP32 and phi = exp2(-r2 * log2(e) / (2 sigma^2)) with the hardware
 // exp2; FP64 path: exp() of the FP64 exponent.
-template <typename TQ>
+// TERMS: perm holds term ids (q * 2^dim + c); the normalized value goes to
+// slot tval[id] with no output transform.
+template <typename TQ, bool TERMS>
 __global__ void __launch_bounds__(kE)
 k_eval_chunks(int dim, int m_cap, const int32_t *__restrict__ n_chunks,
               const int32_t *__restrict__ ch_sub, const int64_t *__restrict__ ch_start,
               const int32_t *__restrict__ ch_len, const int64_t *__restrict__ perm,
               const int32_t *__restrict__ m, const double *__restrict__ c,
               const double *__restrict__ sigma, const double *__restrict__ beta,
-              const TQ *__restrict__ xq, TQ *__restrict__ out, int space) {
+              const TQ *__restrict__ xq, TQ *__restrict__ out, int space,
+              TQ *__restrict__ tval) {
     const int ch = blockIdx.x;
     if (ch >= *n_chunks) return;
     const int s = ch_sub[ch];
@@ -204,10 +427,11 @@ k_eval_chunks(int dim, int m_cap, const int32_t *__restrict__ n_chunks,
     __shared__ TQ sa[kEC];
     __shared__ TQ sb[kEC];
     const bool live = (int)threadIdx.x < len;
-    int64_t q = 0;
+    int64_t q = 0, id = 0;
     TQ x[3] = {0, 0, 0};
     if (live) {
-        q = perm[start + threadIdx.x];
+        id = perm[start + threadIdx.x];
+        q = TERMS ? id >> dim : id;
         for (int d = 0; d < dim; ++d) x[d] = xq[q * dim + d];
     }
     TQ num = 0, den = 0;
@@ -252,22 +476,27 @@ k_eval_chunks(int dim, int m_cap, const int32_t *__restrict__ n_chunks,
     }
     if (live) {
         TQ v = num / den;
-        if (space == 1) {
-            if constexpr (sizeof(TQ) == 4) v = exp10f(v);
-            else v = exp10(v);
+        if constexpr (TERMS) {
+            tval[id] = v;
+        } else {
+            if (space == 1) {
+                if constexpr (sizeof(TQ) == 4) v = exp10f(v);
+                else v = exp10(v);
+            }
+            out[q] = v;
         }
-        out[q] = v;
     }
 }
 
 // ---------------------------------------------------------------- launcher
-pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, const pam_dict *dict,
-                       const double *beta, int dtype, const void *xq, int64_t Q, void *out,
-                       int space, int64_t *n_outside) {
-    // host tables
+namespace {
+
+// Host tables of the fields: per-field descriptors and the concatenated
+// breakpoint coordinates; returns the number of subdomains they span.
+int field_tables(int n_fields, const pam_field *fields, std::vector<FieldDev> &fd,
+                 std::vector<double> &axis) {
     int n_sub_total = 0;
-    std::vector<FieldDev> fd(n_fields);
-    std::vector<double> axis;
+    fd.resize(n_fields);
     for (int f = 0; f < n_fields; ++f) {
         const pam_field &F = fields[f];
         fd[f].dim = F.dim;
@@ -284,22 +513,36 @@ pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, cons
         fd[f].q_end = F.q_end;
         n_sub_total = std::max(n_sub_total, F.sub_base + nsub);
     }
-    const int64_t max_chunks = Q / kQ + n_sub_total + 1;
-    // workspace layout inside BUF_EVAL
+    return n_sub_total;
+}
+
+template <typename TQ>
+pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const pam_dict *dict,
+                      const double *beta, bool blended, double blend, const TQ *xq, int64_t Q,
+                      TQ *out, int space, int64_t *n_outside) {
+    std::vector<FieldDev> fd;
+    std::vector<double> axis;
+    const int n_sub_total = field_tables(n_fields, fields, fd, axis);
+    int dim_max = 1;
+    for (int f = 0; f < n_fields; ++f) dim_max = std::max(dim_max, fields[f].dim);
+    // binned items: queries, or term slots (2^dim per query) in the continuous variant
+    const int64_t slots = blended ? Q << dim_max : Q;
+    const int64_t max_chunks = slots / kQ + n_sub_total + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
     const size_t o_fields = take(sizeof(FieldDev) * n_fields);
     const size_t o_axis = take(sizeof(double) * axis.size());
-    const size_t o_owner = take(sizeof(int32_t) * Q);
+    const size_t o_owner = take(blended ? 0 : sizeof(int32_t) * Q);
     const size_t o_hist = take(sizeof(int32_t) * n_sub_total);
     const size_t o_base = take(sizeof(int64_t) * n_sub_total);
     const size_t o_cbase = take(sizeof(int32_t) * n_sub_total);
     const size_t o_cursor = take(sizeof(int32_t) * n_sub_total);
     const size_t o_nch = take(sizeof(int32_t));
-    const size_t o_perm = take(sizeof(int64_t) * Q);
+    const size_t o_perm = take(sizeof(int64_t) * slots);
     const size_t o_chsub = take(sizeof(int32_t) * max_chunks);
     const size_t o_chstart = take(sizeof(int64_t) * max_chunks);
     const size_t o_chlen = take(sizeof(int32_t) * max_chunks);
+    const size_t o_tval = take(blended ? sizeof(TQ) * slots : 0);
     pam_status st = ensure(ctx, BUF_EVAL, o);
     if (st != PAM_OK) return st;
     char *w = wsp<char>(ctx, BUF_EVAL);
@@ -323,47 +566,228 @@ pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, cons
     int32_t *chsub = (int32_t *)(w + o_chsub);
     int64_t *chstart = (int64_t *)(w + o_chstart);
     int32_t *chlen = (int32_t *)(w + o_chlen);
-    // owner pass: a few thousand resident blocks, each flushing one histogram
+    TQ *tval = (TQ *)(w + o_tval);
+    auto *n_out = (unsigned long long *)n_outside;
+    // owner / term pass: a few thousand resident blocks, each flushing one histogram
     const int grid_o = (int)std::max<int64_t>(1, std::min<int64_t>((Q + kE - 1) / kE, 2048));
     {
-    KernelTimer kt_bin(ctx, PAM_TK_EVAL_BIN);
-    if (Q > 0) {
-        if (dtype == 0)
-            hipLaunchKernelGGL((k_owner<float>), dim3(grid_o), dim3(kE), 0, ctx->stream, t,
-                               (const float *)xq, Q, n_sub_total, owner, hist, (float *)out,
-                               (unsigned long long *)n_outside);
-        else
-            hipLaunchKernelGGL((k_owner<double>), dim3(grid_o), dim3(kE), 0, ctx->stream, t,
-                               (const double *)xq, Q, n_sub_total, owner, hist, (double *)out,
-                               (unsigned long long *)n_outside);
+        KernelTimer kt_bin(ctx, PAM_TK_EVAL_BIN);
+        if (Q > 0) {
+            if (blended)
+                hipLaunchKernelGGL((k_terms<TQ>), dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q,
+                                   n_sub_total, blend, hist, out, n_out);
+            else
+                hipLaunchKernelGGL((k_owner<TQ>), dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q,
+                                   n_sub_total, owner, hist, out, n_out);
+            PAM_CHECK_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, n_sub_total, hist, base,
+                           cbase, cursor, nch);
+        PAM_CHECK_HIP(hipGetLastError());
+        if (Q > 0) {
+            if (blended)
+                hipLaunchKernelGGL((k_scatter_terms<TQ>),
+                                   dim3((unsigned)((Q + kTermBlk - 1) / kTermBlk)), dim3(kE), 0,
+                                   ctx->stream, t, xq, Q, n_sub_total, blend, base, cursor, perm);
+            else
+                hipLaunchKernelGGL(k_scatter, dim3((unsigned)((Q + kScatter - 1) / kScatter)),
+                                   dim3(kE), 0, ctx->stream, Q, n_sub_total, owner, base, cursor,
+                                   perm);
+            PAM_CHECK_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_chunks, dim3((n_sub_total + kE - 1) / kE), dim3(kE), 0, ctx->stream,
+                           n_sub_total, hist, base, cbase, chsub, chstart, chlen);
         PAM_CHECK_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, n_sub_total, hist, base, cbase,
-                       cursor, nch);
-    PAM_CHECK_HIP(hipGetLastError());
-    if (Q > 0) {
-        hipLaunchKernelGGL(k_scatter, dim3((unsigned)((Q + kScatter - 1) / kScatter)), dim3(kE), 0,
-                           ctx->stream, Q, n_sub_total, owner, base, cursor, perm);
-        PAM_CHECK_HIP(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_chunks, dim3((n_sub_total + kE - 1) / kE), dim3(kE), 0, ctx->stream,
-                       n_sub_total, hist, base, cbase, chsub, chstart, chlen);
-    PAM_CHECK_HIP(hipGetLastError());
-    }
-    KernelTimer kt_eval(ctx, PAM_TK_EVAL);
-    if (Q > 0) {
-        if (dtype == 0)
-            hipLaunchKernelGGL((k_eval_chunks<float>), dim3((unsigned)max_chunks), dim3(kE), 0,
+    if (Q == 0) return PAM_OK;
+    {
+        KernelTimer kt_eval(ctx, blended ? PAM_TK_BLEND : PAM_TK_EVAL);
+        if (blended)
+            hipLaunchKernelGGL((k_eval_chunks<TQ, true>), dim3((unsigned)max_chunks), dim3(kE), 0,
                                ctx->stream, dict->dim, dict->m_cap, nch, chsub, chstart, chlen,
-                               perm, dict->m, dict->c, dict->sigma, beta, (const float *)xq,
-                               (float *)out, space);
+                               perm, dict->m, dict->c, dict->sigma, beta, xq, out, space, tval);
         else
-            hipLaunchKernelGGL((k_eval_chunks<double>), dim3((unsigned)max_chunks), dim3(kE), 0,
+            hipLaunchKernelGGL((k_eval_chunks<TQ, false>), dim3((unsigned)max_chunks), dim3(kE), 0,
                                ctx->stream, dict->dim, dict->m_cap, nch, chsub, chstart, chlen,
-                               perm, dict->m, dict->c, dict->sigma, beta, (const double *)xq,
-                               (double *)out, space);
+                               perm, dict->m, dict->c, dict->sigma, beta, xq, out, space, tval);
         PAM_CHECK_HIP(hipGetLastError());
     }
+    if (blended) {
+        // the weighted sum is bookkeeping like the binning: timed with it
+        KernelTimer kt_comb(ctx, PAM_TK_EVAL_BIN);
+        hipLaunchKernelGGL((k_combine<TQ>), dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q, blend,
+                           (const TQ *)tval, out, space);
+        PAM_CHECK_HIP(hipGetLastError());
+    }
+    return PAM_OK;
+}
+
+}  // namespace
+
+pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, const pam_dict *dict,
+                       const double *beta, int dtype, const void *xq, int64_t Q, void *out,
+                       int space, int64_t *n_outside) {
+    if (dtype == 0)
+        return eval_typed(ctx, n_fields, fields, dict, beta, false, 0.0, (const float *)xq, Q,
+                          (float *)out, space, n_outside);
+    return eval_typed(ctx, n_fields, fields, dict, beta, false, 0.0, (const double *)xq, Q,
+                      (double *)out, space, n_outside);
+}
+
+pam_status launch_eval_blend(pam_ctx *ctx, int n_fields, const pam_field *fields,
+                             const pam_dict *dict, const double *beta, double blend, int dtype,
+                             const void *xq, int64_t Q, void *out, int space, int64_t *n_outside) {
+    if (dtype == 0)
+        return eval_typed(ctx, n_fields, fields, dict, beta, true, blend, (const float *)xq, Q,
+                          (float *)out, space, n_outside);
+    return eval_typed(ctx, n_fields, fields, dict, beta, true, blend, (const double *)xq, Q,
+                      (double *)out, space, n_outside);
+}
+
+// ---------------------------------------------------------------- interface jump
+// One block per interior interface piece: the face shared by subdomains A
+// and B = A + e_axis, sampled at the midpoints of an n-per-axis subdivision;
+// both local surrogates in FP64 (centers of A, then of B, staged in LDS).
+struct FaceDev {
+    int32_t a_sub, b_sub, axis, dim;
+    double lo[3], hi[3];   // B's owned box; the face lies at lo[axis]
+};
+
+static constexpr int kJT = 256;
+
+__global__ void __launch_bounds__(kJT)
+k_jump(const FaceDev *__restrict__ faces, int n_faces, int n, int m_cap,
+       const int32_t *__restrict__ m, const double *__restrict__ c,
+       const double *__restrict__ sigma, const double *__restrict__ beta,
+       double *__restrict__ out) {
+    const int f = blockIdx.x;
+    if (f >= n_faces) return;
+    const FaceDev F = faces[f];
+    const int dim = F.dim;
+    int n_pts = 1;
+    for (int b = 0; b < dim - 1; ++b) n_pts *= n;
+    __shared__ double sc[kEC * 3];
+    __shared__ double sa[kEC];
+    __shared__ double sb[kEC];
+    __shared__ double red_max[kJT], red_sum[kJT];
+    double mx = 0.0, sum = 0.0;
+    for (int p0 = 0; p0 < n_pts; p0 += kJT) {
+        const int p = p0 + threadIdx.x;
+        const bool live = p < n_pts;
+        double x[3] = {0.0, 0.0, 0.0};
+        int rest = p;
+        for (int b = 0; b < dim; ++b) {
+            if (b == F.axis) {
+                x[b] = F.lo[b];
+            } else {
+                const int j = rest % n;
+                rest /= n;
+                x[b] = F.lo[b] + (j + 0.5) * (F.hi[b] - F.lo[b]) / n;
+            }
+        }
+        double val[2];
+        for (int side = 0; side < 2; ++side) {
+            const int s = side == 0 ? F.a_sub : F.b_sub;
+            const int M = max(0, min(m[s], m_cap));
+            double num = 0.0, den = 0.0;
+            for (int m0 = 0; m0 < M; m0 += kEC) {
+                const int cnt = min(kEC, M - m0);
+                __syncthreads();
+                for (int t = threadIdx.x; t < cnt; t += kJT) {
+                    for (int d = 0; d < dim; ++d)
+                        sc[t * 3 + d] = c[((size_t)s * m_cap + m0 + t) * dim + d];
+                    const double sg = sigma[(size_t)s * m_cap + m0 + t];
+                    sa[t] = 0.5 / (sg * sg);
+                    sb[t] = beta[(size_t)s * m_cap + m0 + t];
+                }
+                __syncthreads();
+                if (live) {
+                    for (int t = 0; t < cnt; ++t) {
+                        double r2 = 0.0;
+                        for (int d = 0; d < dim; ++d) {
+                            const double df = x[d] - sc[t * 3 + d];
+                            r2 += df * df;
+                        }
+                        const double ph = exp(-r2 * sa[t]);
+                        num += sb[t] * ph;
+                        den += ph;
+                    }
+                }
+            }
+            val[side] = num / den;
+        }
+        if (live) {
+            const double j = fabs(val[0] - val[1]);
+            mx = fmax(mx, j);
+            sum += j;
+        }
+    }
+    red_max[threadIdx.x] = mx;
+    red_sum[threadIdx.x] = sum;
+    __syncthreads();
+    for (int k = kJT / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            red_max[threadIdx.x] = fmax(red_max[threadIdx.x], red_max[threadIdx.x + k]);
+            red_sum[threadIdx.x] += red_sum[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * (size_t)f] = red_max[0];
+        out[2 * (size_t)f + 1] = red_sum[0] / n_pts;
+    }
+}
+
+int64_t interface_count(int n_fields, const pam_field *fields) {
+    int64_t n = 0;
+    for (int f = 0; f < n_fields; ++f) {
+        int64_t tot = 1;
+        for (int d = 0; d < fields[f].dim; ++d) tot *= fields[f].n_sub_axis[d];
+        for (int d = 0; d < fields[f].dim; ++d)
+            n += tot / fields[f].n_sub_axis[d] * (fields[f].n_sub_axis[d] - 1);
+    }
+    return n;
+}
+
+pam_status launch_interface_jump(pam_ctx *ctx, int n_fields, const pam_field *fields,
+                                 const pam_dict *dict, const double *beta, int n, double *out) {
+    std::vector<FaceDev> faces;
+    for (int f = 0; f < n_fields; ++f) {
+        const pam_field &F = fields[f];
+        int ns[3] = {1, 1, 1}, off[3] = {0, 0, 0};
+        for (int d = 0; d < F.dim; ++d) {
+            ns[d] = F.n_sub_axis[d];
+            if (d > 0) off[d] = off[d - 1] + F.n_sub_axis[d - 1] + 1;
+        }
+        const int tot = ns[0] * ns[1] * ns[2];
+        const int stride[3] = {1, ns[0], ns[0] * ns[1]};
+        for (int a = 0; a < F.dim; ++a) {
+            for (int B = 0; B < tot; ++B) {
+                const int kk[3] = {B % ns[0], (B / ns[0]) % ns[1], B / (ns[0] * ns[1])};
+                if (kk[a] == 0) continue;
+                FaceDev fc{};
+                fc.a_sub = F.sub_base + B - stride[a];
+                fc.b_sub = F.sub_base + B;
+                fc.axis = a;
+                fc.dim = F.dim;
+                for (int d = 0; d < F.dim; ++d) {
+                    fc.lo[d] = F.axis_x[off[d] + kk[d]];
+                    fc.hi[d] = F.axis_x[off[d] + kk[d] + 1];
+                }
+                faces.push_back(fc);
+            }
+        }
+    }
+    if (faces.empty()) return PAM_OK;
+    const size_t bytes = sizeof(FaceDev) * faces.size();
+    pam_status st = ensure(ctx, BUF_EVAL, bytes);
+    if (st != PAM_OK) return st;
+    FaceDev *dfaces = wsp<FaceDev>(ctx, BUF_EVAL);
+    if ((st = upload_to(ctx, dfaces, faces.data(), bytes)) != PAM_OK) return st;
+    KernelTimer kt(ctx, PAM_TK_JUMP);
+    hipLaunchKernelGGL(k_jump, dim3((unsigned)faces.size()), dim3(kJT), 0, ctx->stream, dfaces,
+                       (int)faces.size(), n, dict->m_cap, dict->m, dict->c, dict->sigma, beta, out);
+    PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;
 }
 

@@ -101,6 +101,12 @@ void axis_range(int n_cells, int n_sub, const int32_t *brk, int k, double overla
 pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, const pam_dict *dict,
                        const double *beta, int dtype, const void *xq, int64_t Q, void *out,
                        int space, int64_t *n_outside);
+pam_status launch_eval_blend(pam_ctx *ctx, int n_fields, const pam_field *fields,
+                             const pam_dict *dict, const double *beta, double blend, int dtype,
+                             const void *xq, int64_t Q, void *out, int space, int64_t *n_outside);
+int64_t interface_count(int n_fields, const pam_field *fields);
+pam_status launch_interface_jump(pam_ctx *ctx, int n_fields, const pam_field *fields,
+                                 const pam_dict *dict, const double *beta, int n, double *out);
 
 static pam_status check_grid(const pam_grid *g, int *n_sub_total) {
     PAM_REQUIRE(g, "grid is NULL");
@@ -452,22 +458,20 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     return PAM_OK;
 }
 
-pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields, const pam_dict *dict,
-                    const double *beta, int32_t dtype, const void *xq, int64_t Q, void *out,
-                    int32_t space, int64_t *n_outside) {
-    pam_status st = check_ctx(ctx);
-    if (st != PAM_OK) return st;
-    PAM_REQUIRE(n_fields >= 1 && fields && dict && beta, "NULL argument");
-    PAM_REQUIRE(Q >= 0 && (Q == 0 || (xq && out)), "query arrays are NULL");
-    PAM_REQUIRE(dtype == 0 || dtype == 1, "dtype must be 0 (f32) or 1 (f64)");
-    PAM_REQUIRE(space == 0 || space == 1, "space must be 0 or 1");
+// Field table checks shared by the evaluation entry points; with Q < 0 the
+// query ranges are not checked (interface jump).
+static pam_status check_fields(int32_t n_fields, const pam_field *fields, const pam_dict *dict,
+                               int64_t Q) {
+    PAM_REQUIRE(n_fields >= 1 && fields && dict, "NULL argument");
     int64_t prev = 0;
     for (int f = 0; f < n_fields; ++f) {
         const pam_field &F = fields[f];
         PAM_REQUIRE(F.dim == dict->dim && F.axis_x, "field dimension mismatch");
-        PAM_REQUIRE(F.q_begin == prev && F.q_end >= F.q_begin && F.q_end <= Q,
-                    "field query ranges must tile [0, Q) in order");
-        prev = F.q_end;
+        if (Q >= 0) {
+            PAM_REQUIRE(F.q_begin == prev && F.q_end >= F.q_begin && F.q_end <= Q,
+                        "field query ranges must tile [0, Q) in order");
+            prev = F.q_end;
+        }
         int nsub = 1, pos = 0;
         for (int d = 0; d < F.dim; ++d) {
             PAM_REQUIRE(F.n_sub_axis[d] >= 1, "n_sub_axis must be >= 1");
@@ -479,8 +483,65 @@ pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields, con
         PAM_REQUIRE(F.sub_base >= 0 && F.sub_base + nsub <= dict->n_sub,
                     "field subdomains exceed the dictionary");
     }
-    PAM_REQUIRE(prev == Q, "field query ranges must cover [0, Q)");
+    if (Q >= 0) PAM_REQUIRE(prev == Q, "field query ranges must cover [0, Q)");
+    return PAM_OK;
+}
+
+pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields, const pam_dict *dict,
+                    const double *beta, int32_t dtype, const void *xq, int64_t Q, void *out,
+                    int32_t space, int64_t *n_outside) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(beta, "NULL argument");
+    PAM_REQUIRE(Q >= 0 && (Q == 0 || (xq && out)), "query arrays are NULL");
+    PAM_REQUIRE(dtype == 0 || dtype == 1, "dtype must be 0 (f32) or 1 (f64)");
+    PAM_REQUIRE(space == 0 || space == 1, "space must be 0 or 1");
+    if ((st = check_fields(n_fields, fields, dict, Q)) != PAM_OK) return st;
     return launch_eval(ctx, n_fields, fields, dict, beta, dtype, xq, Q, out, space, n_outside);
+}
+
+pam_status pam_eval_blend(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
+                          const pam_dict *dict, const double *beta, double blend, int32_t dtype,
+                          const void *xq, int64_t Q, void *out, int32_t space,
+                          int64_t *n_outside) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(beta, "NULL argument");
+    PAM_REQUIRE(blend >= 0.0 && blend <= 0.5, "blend must be in [0, 1/2]");
+    PAM_REQUIRE(Q >= 0 && (Q == 0 || (xq && out)), "query arrays are NULL");
+    PAM_REQUIRE(dtype == 0 || dtype == 1, "dtype must be 0 (f32) or 1 (f64)");
+    PAM_REQUIRE(space == 0 || space == 1, "space must be 0 or 1");
+    if ((st = check_fields(n_fields, fields, dict, Q)) != PAM_OK) return st;
+    PAM_REQUIRE(Q <= ((int64_t)1 << 59), "too many queries");
+    return launch_eval_blend(ctx, n_fields, fields, dict, beta, blend, dtype, xq, Q, out, space,
+                             n_outside);
+}
+
+int64_t pam_interface_count(int32_t n_fields, const pam_field *fields) {
+    if (n_fields < 1 || !fields) return -1;
+    for (int f = 0; f < n_fields; ++f) {
+        if (fields[f].dim < 1 || fields[f].dim > 3) return -1;
+        for (int d = 0; d < fields[f].dim; ++d)
+            if (fields[f].n_sub_axis[d] < 1) return -1;
+    }
+    return interface_count(n_fields, fields);
+}
+
+pam_status pam_interface_jump(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
+                              const pam_dict *dict, const double *beta, int32_t n_per_axis,
+                              double *out) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(beta, "NULL argument");
+    PAM_REQUIRE(n_per_axis >= 1 && n_per_axis <= 4096, "n_per_axis must be in [1, 4096]");
+    if ((st = check_fields(n_fields, fields, dict, -1)) != PAM_OK) return st;
+    const int64_t nf = interface_count(n_fields, fields);
+    PAM_REQUIRE(nf == 0 || out, "out is NULL");
+    int64_t pts = 1;
+    for (int d = 0; d + 1 < dict->dim; ++d) pts *= n_per_axis;
+    PAM_REQUIRE(pts <= ((int64_t)1 << 24), "too many samples per face");
+    PAM_REQUIRE(nf < ((int64_t)1 << 31), "too many interfaces");
+    return launch_interface_jump(ctx, n_fields, fields, dict, beta, n_per_axis, out);
 }
 
 }  // extern "C"

@@ -22,9 +22,10 @@ EXPORTS = [
     "pam_refine", "pam_eval", "pam_timing_enable", "pam_timing_read",
     "pam_cnn_param_count", "pam_cnn_forward", "pam_cnn_loss_grad", "pam_cnn_adam",
     "pam_grid_patches", "pam_support_hint", "pam_cnn_labels",
+    "pam_eval_blend", "pam_interface_count", "pam_interface_jump",
 ]
 TIMING_KINDS = ["gather", "lattice", "assemble", "gram", "solve", "indicator", "mark",
-                "eval_bin", "eval", "cnn"]
+                "eval_bin", "eval", "cnn", "blend", "jump"]
 
 
 class PamGrid(C.Structure):
@@ -105,6 +106,11 @@ def lib():
                                  C.POINTER(PamEnetOpts), C.POINTER(PamRefineOpts), P]
         L.pam_eval.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P, C.c_int32,
                                P, C.c_int64, P, C.c_int32, P]
+        L.pam_eval_blend.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P,
+                                     C.c_double, C.c_int32, P, C.c_int64, P, C.c_int32, P]
+        L.pam_interface_count.argtypes = [C.c_int32, C.POINTER(PamField)]
+        L.pam_interface_jump.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P,
+                                         C.c_int32, P]
         L.pam_timing_enable.argtypes = [P, C.c_int32]
         L.pam_timing_read.argtypes = [P, P, P, C.c_int32]
         L.pam_cnn_param_count.argtypes = []
@@ -120,6 +126,7 @@ def lib():
             if name not in ("pam_last_error", "pam_version"):
                 getattr(L, name).restype = C.c_int
         L.pam_cnn_param_count.restype = C.c_int64
+        L.pam_interface_count.restype = C.c_int64
         _lib = L
     return _lib
 

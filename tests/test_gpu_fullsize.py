@@ -148,3 +148,59 @@ def test_c5_multifield_fit_and_transfer(ctx):
         print("C5 field", f, "side", g.n_cells[0], "coefficient error", err, "eval error", eerr)
         assert err <= 1e-5
         assert eerr <= 2e-4 * max(1.0, np.abs(ref).max())
+
+
+def _outside_bands(x, g, blend):
+    keep = np.ones(len(x), bool)
+    for a, b in enumerate(O.grid_axis_coords(g)):
+        for i in range(1, len(b) - 1):
+            h = blend * min(b[i] - b[i - 1], b[i + 1] - b[i])
+            keep &= np.abs(x[:, a] - b[i]) >= h
+    return keep
+
+
+def test_c5_continuous_reconstruction(ctx):
+    """The continuous reconstruction at the full multi-field size (64 fields,
+    1e6 FP32 queries each, band = the 10 % fit overlap): bit-for-bit the
+    owner value outside every band on all 6.4e7 queries; sampled queries and
+    the interface jumps of the two smallest fields against the oracle's own
+    fit."""
+    grids = synth.multifield()
+    parts = [api.partition(ctx, g) for g in grids]
+    dicts = [api.init_lattice(ctx, g, [16, 16], 256) for g in grids]
+    S, D = api.concat_samples(parts), api.concat_dicts(dicts)
+    bases = np.cumsum([0] + [d.n_sub for d in dicts])
+    beta, st = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f32"))
+    Q, blend = 1_000_000, 0.1
+    xs = [synth.uniform_queries(2, Q, seed=7000 + f) for f in range(len(grids))]
+    xq = torch.as_tensor(np.concatenate(xs), device="cuda")
+    nout = torch.zeros(1, dtype=torch.int64, device="cuda")
+    own = _t(api.evaluate(ctx, grids, D, beta, xq, q_counts=[Q] * len(grids)))
+    ob = _t(api.evaluate_blend(ctx, grids, D, beta, xq, blend, q_counts=[Q] * len(grids),
+                               n_outside=nout))
+    J = _t(api.interface_jump(ctx, grids, D, beta, 16))
+    torch.cuda.synchronize()
+    assert int(nout.item()) == 0 and np.all(np.isfinite(ob))
+    n_band = 0
+    for f, g in enumerate(grids):
+        keep = _outside_bands(xs[f].astype(np.float64), g, blend)
+        n_band += int((~keep).sum())
+        assert np.array_equal(ob[f * Q:(f + 1) * Q][keep], own[f * Q:(f + 1) * Q][keep]), f
+    print("C5 queries in a band", n_band, "of", Q * len(grids), "interfaces", len(J))
+    assert len(J) == api.interface_count(grids)
+    sizes = np.array([g.n_cells[0] for g in grids])
+    face0 = np.cumsum([0] + [api.interface_count(g) for g in grids])
+    for f in np.argsort(sizes, kind="stable")[:2]:
+        g = grids[f]
+        od = O.init_dictionary(g, [16, 16], 256)
+        bo, sto, _ = O.fit_batch(O.partition(g), od, L1, L2)
+        pick = np.random.default_rng(int(f) + 50).choice(Q, 2000, replace=False)
+        ref, _ = O.evaluate_blend(O.grid_axis_coords(g), od, bo, xs[f][pick].astype(np.float64),
+                                  blend)
+        eerr = np.abs(ob[f * Q + pick].astype(np.float64) - ref).max()
+        jref = O.interface_jump(O.grid_axis_coords(g), od, bo, 16)
+        jerr = np.abs(J[face0[f]:face0[f + 1]] - jref).max()
+        print("C5 field", f, "continuous eval error", eerr, "jump error", jerr,
+              "max jump", jref[:, 0].max())
+        assert eerr <= 2e-4 * max(1.0, np.abs(ref).max())
+        assert jerr <= 1e-4 * max(1.0, jref[:, 0].max())
