@@ -90,6 +90,10 @@ def lib():
         L.ora_interface_jump.restype = C.c_long
         L.ora_interface_jump.argtypes = [C.c_int, _ip, _dp, C.c_int, _ip, _dp, _dp, _dp, C.c_int,
                                          _dp]
+        L.ora_select_lambda.restype = C.c_int
+        L.ora_select_lambda.argtypes = [C.c_int, C.c_int, _lp, _dp, _dp, C.c_int, _ip, _dp, _dp,
+                                        C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, _dp,
+                                        _dp, _ip]
         _lib = L
     return _lib
 
@@ -344,3 +348,23 @@ def interface_jump(axis_x, D: Dictionary, beta, n):
     got = lib().ora_interface_jump(d, ns, ax, D.m_cap, D.m, D.c, D.sigma, _f64(beta), int(n), out)
     assert got == nf
     return out[:2 * nf].reshape(nf, 2)
+
+
+def select_lambda(samples, D: Dictionary, n_alpha=8, ratio=1e-3, rho=0.99, k_folds=5, cd_sweeps=8):
+    """Per-subdomain elastic-net strength by a path over alpha = lambda1 +
+    lambda2 (lambda1 = rho alpha) and K-fold cross-validation; the reading is
+    stated in the C file. Returns (alpha [n_sub, n_alpha], score [n_sub,
+    n_alpha], best [n_sub], lambda1 [n_sub], lambda2 [n_sub])."""
+    n = D.n_sub
+    alpha = np.zeros(n * n_alpha)
+    score = np.zeros(n * n_alpha)
+    best = np.zeros(n, np.int32)
+    bad = lib().ora_select_lambda(D.dim, n, samples["off"], _f64(samples["x"]).ravel(),
+                                  _f64(samples["y"]), D.m_cap, D.m, D.c, D.sigma, int(n_alpha),
+                                  float(ratio), float(rho), int(k_folds), int(cd_sweeps), alpha,
+                                  score, best)
+    if bad:
+        raise RuntimeError(f"{bad} oracle fits failed")
+    alpha, score = alpha.reshape(n, n_alpha), score.reshape(n, n_alpha)
+    a = alpha[np.arange(n), best]
+    return alpha, score, best, rho * a, (1.0 - rho) * a
