@@ -19,7 +19,9 @@ hint map run before the first fit. Beside the timed step the record holds:
 the comparator (the plain GPU fit: one launch per subdomain and kernel, every
 refit from zero, no hint), the learned part's training throughput and gain,
 the error of the GPU coefficients and field against the FP64 oracle on the
-CPU sample, the oracle's own throughput on that sample, and the interface
+CPU sample, the oracle's own throughput on that sample, the per-subdomain
+choice of the elastic-net parameters (alpha path + K-fold cross-validation:
+its fits/s and the field it gives after refinement), and the interface
 treatment on the fitted field (continuous reconstruction across subdomain
 interfaces: its throughput and error beside the owner reconstruction's, and
 the interface jump it removes).
@@ -89,6 +91,12 @@ def parse():
                     help="skip the one-pattern-off runs (batching, precision, learned)")
     ap.add_argument("--no-continuity", action="store_true",
                     help="skip the interface-treatment measurements")
+    ap.add_argument("--no-select", action="store_true",
+                    help="skip the per-subdomain lambda selection measurement")
+    ap.add_argument("--select-alphas", type=int, default=13,
+                    help="path length (half-decade steps down to 1e-6 alpha_max by default)")
+    ap.add_argument("--select-ratio", type=float, default=1e-6)
+    ap.add_argument("--select-folds", type=int, default=5)
     ap.add_argument("--blend", type=float, default=0.1,
                     help="interface band half-width as a fraction of the shorter neighbour")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -239,6 +247,48 @@ def learned_gain(ctx, api, grid, wl, prec, params):
     out["held_out_accuracy"] = {"refine": acc[0][0], "refine_majority": acc[0][1],
                                 "support": acc[1][0], "support_majority": acc[1][1]}
     return out
+
+
+def lambda_selection(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d, ycell, area, n_alpha, k_folds,
+                     ratio, reps=2):
+    """Per-subdomain parameters on the workload's initial lattice: the path
+    timed with HIP events (fits = n_sub * k_folds * n_alpha), then a full
+    refinement with the chosen parameters against the fixed pair."""
+    import torch
+    cell_y = torch.as_tensor(grid.y, dtype=torch.float64, device="cuda")
+    S = api.partition(ctx, grid, cell_y)
+    D0 = api.init_lattice(ctx, grid, wl.g, wl.m0, wl.sigma_factor)   # the initial lattice only
+    o = api.EnetOpts(0.0, 0.0, prec)
+    out = api.select_lambda(ctx, S, D0, o, n_alpha=n_alpha, k_folds=k_folds, alpha_min_ratio=ratio)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = api.select_lambda(ctx, S, D0, o, n_alpha=n_alpha, k_folds=k_folds,
+                                alpha_min_ratio=ratio)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    fits = D0.n_sub * k_folds * n_alpha
+    res = {"n_alpha": n_alpha, "k_folds": k_folds, "alpha_min_ratio": ratio, "l1_ratio": 0.99,
+           "fits": fits, "ms": dt * 1e3, "fits_per_s": fits / dt,
+           "n_failed": int(out["n_failed"].sum().item())}
+    best = out["best"].cpu().numpy()
+    res["chosen_index_histogram"] = np.bincount(best, minlength=n_alpha).tolist()
+    l1 = out["lambda1"].cpu().numpy()
+    res["lambda1_chosen"] = {"min": float(l1.min()), "median": float(np.median(l1)),
+                             "max": float(l1.max())}
+    fields = {}
+    for name, kw in (("fixed_pair", dict(lambda1=wl.lambda1, lambda2=wl.lambda2)),
+                     ("selected", dict(lambda1=0.0, lambda2=0.0, lambda1_sub=out["lambda1"],
+                                       lambda2_sub=out["lambda2"]))):
+        D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
+        ro = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta)
+        beta, lvl, rounds, rs, st = api.refine(ctx, S, D, api.EnetOpts(precision=prec, **kw), ro)
+        f = api.evaluate(ctx, grid, D, beta, xq)
+        fields[name] = {"field_l1_log10": float((w_d * (f.double() - ycell).abs()).sum().item()) / area,
+                        "centers_mean": float(D.m.double().mean().item()),
+                        "support_mean": float(api.stats_to_numpy(st)["support"].mean())}
+    res["refined_field"] = fields
+    return res
 
 
 def blend_pairs(grid, m_sub, xq, blend):
@@ -526,6 +576,10 @@ def main():
         "roofline": roof,
     }
     rec["config"]["learned_warm_start"] = bool(use_learned)
+    if not args.no_select:
+        rec["lambda_selection"] = lambda_selection(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d,
+                                                   ycell, area, args.select_alphas,
+                                                   args.select_folds, args.select_ratio)
     if not args.no_continuity:
         rec["continuity"] = continuity(ctx, api, grid, D, beta, xq, w_d, ycell, area, args.blend)
     if use_learned:

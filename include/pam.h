@@ -247,6 +247,46 @@ pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
                     int64_t Q, void *out, int32_t space, int64_t *n_outside);
 
 /* ------------------------------------------------------------------------
+ * Per-subdomain elastic-net parameters (Sec. 2 after Eq. (elastic): they may
+ * differ between subdomains; Exp. 1.2 chooses them independently per
+ * subdomain; the paper does not say how). lambda1 = l1_ratio * alpha,
+ * lambda2 = (1 - l1_ratio) * alpha (l1_ratio = 0.99 reproduces the printed
+ * pair 4.59e-4 / 4.64e-6 at alpha = 4.64e-4). alpha runs down the geometric
+ * path alpha_k = alpha_max * alpha_min_ratio^(k / (n_alpha - 1)),
+ * k = 0..n_alpha-1, from alpha_max = max_m |(W^T y)_m| / l1_ratio, the
+ * smallest alpha at which the fit on all of the subdomain's samples is zero
+ * (FP64, over the whole dictionary). Each alpha is scored by k_folds-fold
+ * cross-validation: fold f of a subdomain holds its samples whose local index
+ * j has j % k_folds == f; score = (1/N) sum_j (y_j - K*_f(x_j))^2, with K*_f
+ * the surrogate fitted on the other folds (normalized over the whole
+ * dictionary, FP64). The chosen alpha is the first (largest) with the
+ * smallest score.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_alpha;        /* path length, 1..4096                           */
+    int32_t k_folds;        /* 2..64                                          */
+    double alpha_min_ratio; /* (0, 1]: last alpha / alpha_max                 */
+    double l1_ratio;        /* (0, 1]: lambda1 / (lambda1 + lambda2)          */
+} pam_select_opts;
+
+/* Runs the path for all subdomains at once: the k_folds training sets of
+ * every subdomain are fitted as one batch of n_sub * k_folds subdomains per
+ * alpha (opts gives precision, cd_sweeps, max_iter, batched; its lambdas,
+ * warm_start and support_hint are ignored), each warm-started from the
+ * previous alpha's solution; the fits are the FP64 problem's minimizers in
+ * every precision mode. Outputs (device, caller-owned): alpha and score
+ * [n_sub * n_alpha] (row per subdomain), best [n_sub] (chosen index),
+ * lambda1_sub / lambda2_sub [n_sub] (ready for pam_enet_opts), n_failed
+ * [n_sub] or NULL (fits on the path whose status was neither OK nor EMPTY).
+ * Workspace: the training sets, dictionaries and coefficients of the
+ * n_sub * k_folds fits, from the context. Same argument checks as
+ * pam_fit_subdomains plus the ranges above (PAM_ERR_ARG). */
+pam_status pam_select_lambda(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,
+                             const pam_enet_opts *opts, const pam_select_opts *sel, double *alpha,
+                             double *score, int32_t *best, double *lambda1_sub,
+                             double *lambda2_sub, int32_t *n_failed);
+
+/* ------------------------------------------------------------------------
  * Interface treatment (Sec. 2 Step 4 and the remark after it: the piecewise
  * K* of independent local fits is discontinuous across subdomain interfaces
  * in general; a continuous reconstruction averages neighbouring local

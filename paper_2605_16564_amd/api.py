@@ -258,6 +258,33 @@ def fit(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts,
     return beta, stats
 
 
+def select_lambda(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, n_alpha: int = 8,
+                  k_folds: int = 5, alpha_min_ratio: float = 1e-3, l1_ratio: float = 0.99):
+    """Per-subdomain elastic-net parameters by an alpha path and K-fold
+    cross-validation (opts gives the precision and iteration controls).
+    Returns dict of device tensors: alpha and score [n_sub, n_alpha], best
+    [n_sub], lambda1 and lambda2 [n_sub] (for EnetOpts.lambda1_sub/_sub),
+    n_failed [n_sub]."""
+    dev = D.m.device
+    n = D.n_sub
+    out = dict(alpha=torch.empty((n, n_alpha), dtype=torch.float64, device=dev),
+               score=torch.empty((n, n_alpha), dtype=torch.float64, device=dev),
+               best=torch.empty(n, dtype=torch.int32, device=dev),
+               lambda1=torch.empty(n, dtype=torch.float64, device=dev),
+               lambda2=torch.empty(n, dtype=torch.float64, device=dev),
+               n_failed=torch.empty(n, dtype=torch.int32, device=dev))
+    sel = N.PamSelectOpts()
+    sel.n_alpha, sel.k_folds = int(n_alpha), int(k_folds)
+    sel.alpha_min_ratio, sel.l1_ratio = float(alpha_min_ratio), float(l1_ratio)
+    ss, ds, os_ = S.struct(), D.struct(), opts.struct(False)
+    ctx.use_current_stream()
+    N.check(N.lib().pam_select_lambda(ctx.h, C.byref(ss), C.byref(ds), C.byref(os_), C.byref(sel),
+                                      _p(out["alpha"]), _p(out["score"]), _p(out["best"]),
+                                      _p(out["lambda1"]), _p(out["lambda2"]), _p(out["n_failed"])),
+            "pam_select_lambda")
+    return out
+
+
 @dataclass
 class RefineOpts:
     k_top: int = 204

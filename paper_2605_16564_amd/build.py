@@ -14,7 +14,8 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "_build" / "libpam.so"
-SOURCES = ["pam_api.hip", "k_setup.hip", "k_fit.hip", "k_solve.hip", "k_refine.hip", "k_eval.hip", "k_cnn.hip"]
+SOURCES = ["pam_api.hip", "k_setup.hip", "k_fit.hip", "k_solve.hip", "k_refine.hip", "k_eval.hip", "k_cnn.hip",
+           "k_select.hip"]
 ARCH = os.environ.get("PAM_OFFLOAD_ARCH", "gfx950")
 
 

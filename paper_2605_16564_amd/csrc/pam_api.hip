@@ -105,6 +105,18 @@ pam_status launch_eval_blend(pam_ctx *ctx, int n_fields, const pam_field *fields
                              const pam_dict *dict, const double *beta, double blend, int dtype,
                              const void *xq, int64_t Q, void *out, int space, int64_t *n_outside);
 int64_t interface_count(int n_fields, const pam_field *fields);
+// lambda selection (k_select.hip)
+pam_status launch_cv_setup(pam_ctx *ctx, const pam_samples *S, const pam_dict *D, int K,
+                           const int64_t *off_v, double *xv, double *yv, int32_t *mv, double *cv,
+                           double *sv, int32_t *lv, double *beta_v, double *inv_s, int n_alpha,
+                           double ratio, double rho, double *alpha, int32_t *n_failed);
+pam_status launch_cv_lambda(pam_ctx *ctx, int n_sub, int K, int n_alpha, int k, double rho,
+                            const double *alpha, double *l1v, double *l2v);
+pam_status launch_cv_score(pam_ctx *ctx, const pam_samples *S, const pam_dict *D, int K,
+                           int n_alpha, int k, const double *beta_v, const pam_fit_stats *stats_v,
+                           double *score, int32_t *n_failed);
+pam_status launch_cv_choose(pam_ctx *ctx, int n_sub, int n_alpha, double rho, const double *alpha,
+                            const double *score, int32_t *best, double *l1, double *l2);
 pam_status launch_interface_jump(pam_ctx *ctx, int n_fields, const pam_field *fields,
                                  const pam_dict *dict, const double *beta, int n, double *out);
 
@@ -456,6 +468,102 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
         }
     }
     return PAM_OK;
+}
+
+pam_status pam_select_lambda(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,
+                             const pam_enet_opts *opts, const pam_select_opts *sel, double *alpha,
+                             double *score, int32_t *best, double *lambda1_sub,
+                             double *lambda2_sub, int32_t *n_failed) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(opts && sel && alpha && score && best && lambda1_sub && lambda2_sub,
+                "NULL argument");
+    PAM_REQUIRE(sel->n_alpha >= 1 && sel->n_alpha <= 4096, "n_alpha must be in [1, 4096]");
+    PAM_REQUIRE(sel->k_folds >= 2 && sel->k_folds <= 64, "k_folds must be in [2, 64]");
+    PAM_REQUIRE(sel->alpha_min_ratio > 0.0 && sel->alpha_min_ratio <= 1.0,
+                "alpha_min_ratio must be in (0, 1]");
+    PAM_REQUIRE(sel->l1_ratio > 0.0 && sel->l1_ratio <= 1.0, "l1_ratio must be in (0, 1]");
+    pam_enet_opts o = *opts;   // the path sets the parameters; a hint does not apply
+    o.lambda1 = o.lambda2 = 0.0;
+    o.lambda1_sub = o.lambda2_sub = nullptr;
+    o.support_hint = nullptr;
+    if ((st = check_fit_args(samples, dict, &o, alpha)) != PAM_OK) return st;
+    const int n = samples->n_sub, K = sel->k_folds, nv = n * K, dim = samples->dim;
+    const int m_cap = dict->m_cap;
+    // training sets: fold f of subdomain s holds its samples j with j % K == f
+    std::vector<int64_t> off_v((size_t)nv + 1, 0);
+    int n_max_v = 0;
+    for (int s = 0; s < n; ++s) {
+        const int64_t N = samples->off_host[s + 1] - samples->off_host[s];
+        for (int f = 0; f < K; ++f) {
+            const int64_t held = N > f ? (N - 1 - f) / K + 1 : 0;
+            const int64_t cnt = N - held;
+            off_v[(size_t)s * K + f + 1] = off_v[(size_t)s * K + f] + cnt;
+            n_max_v = std::max<int>(n_max_v, (int)cnt);
+        }
+    }
+    const int64_t n_tot = samples->off_host[n];
+    const int64_t n_tot_v = off_v[nv];
+    size_t w = 0;
+    auto take = [&](size_t bytes) { size_t r = w; w += (bytes + 255) / 256 * 256; return r; };
+    const size_t o_off = take(sizeof(int64_t) * (nv + 1));
+    const size_t o_x = take(sizeof(double) * std::max<int64_t>(n_tot_v, 1) * dim);
+    const size_t o_y = take(sizeof(double) * std::max<int64_t>(n_tot_v, 1));
+    const size_t o_m = take(sizeof(int32_t) * nv);
+    const size_t o_c = take(sizeof(double) * (size_t)nv * m_cap * dim);
+    const size_t o_s = take(sizeof(double) * (size_t)nv * m_cap);
+    const size_t o_l = take(sizeof(int32_t) * (size_t)nv * m_cap);
+    const size_t o_b = take(sizeof(double) * (size_t)nv * m_cap);
+    const size_t o_l1 = take(sizeof(double) * nv);
+    const size_t o_l2 = take(sizeof(double) * nv);
+    const size_t o_st = take(sizeof(pam_fit_stats) * nv);
+    const size_t o_inv = take(sizeof(double) * std::max<int64_t>(n_tot, 1));
+    if ((st = ensure(ctx, BUF_EVAL, w)) != PAM_OK) return st;
+    char *base = wsp<char>(ctx, BUF_EVAL);
+    if ((st = upload_to(ctx, base + o_off, off_v.data(), sizeof(int64_t) * (nv + 1))) != PAM_OK)
+        return st;
+    pam_samples Sv;
+    memset(&Sv, 0, sizeof(Sv));
+    Sv.dim = dim;
+    Sv.n_sub = nv;
+    Sv.n_max = n_max_v;
+    Sv.off = (const int64_t *)(base + o_off);
+    Sv.off_host = off_v.data();
+    Sv.x = (const double *)(base + o_x);
+    Sv.y = (const double *)(base + o_y);
+    pam_dict Dv;
+    memset(&Dv, 0, sizeof(Dv));
+    Dv.n_sub = nv;
+    Dv.dim = dim;
+    Dv.m_cap = m_cap;
+    Dv.m = (int32_t *)(base + o_m);
+    Dv.c = (double *)(base + o_c);
+    Dv.sigma = (double *)(base + o_s);
+    Dv.level = (int32_t *)(base + o_l);
+    double *beta_v = (double *)(base + o_b);
+    double *l1v = (double *)(base + o_l1);
+    double *l2v = (double *)(base + o_l2);
+    pam_fit_stats *stats_v = (pam_fit_stats *)(base + o_st);
+    const double rho = sel->l1_ratio;
+    if ((st = launch_cv_setup(ctx, samples, dict, K, Sv.off, (double *)Sv.x, (double *)Sv.y, Dv.m,
+                              Dv.c, Dv.sigma, Dv.level, beta_v, (double *)(base + o_inv),
+                              sel->n_alpha, sel->alpha_min_ratio, rho, alpha, n_failed)) != PAM_OK)
+        return st;
+    o.lambda1_sub = l1v;
+    o.lambda2_sub = l2v;
+    for (int k = 0; k < sel->n_alpha; ++k) {
+        if ((st = launch_cv_lambda(ctx, n, K, sel->n_alpha, k, rho, alpha, l1v, l2v)) != PAM_OK)
+            return st;
+        // path order: each fit starts from the previous alpha's solution
+        if ((st = run_fit(ctx, &Sv, &Dv, &o, beta_v, stats_v, nullptr, k > 0 ? 1 : 0)) != PAM_OK)
+            return st;
+        if ((st = launch_cv_score(ctx, samples, dict, K, sel->n_alpha, k, beta_v, stats_v, score,
+                                  n_failed)) != PAM_OK)
+            return st;
+    }
+    // the host offsets above are read by run_fit during the calls only
+    return launch_cv_choose(ctx, n, sel->n_alpha, rho, alpha, score, best, lambda1_sub,
+                            lambda2_sub);
 }
 
 // Field table checks shared by the evaluation entry points; with Q < 0 the

@@ -22,7 +22,7 @@ EXPORTS = [
     "pam_refine", "pam_eval", "pam_timing_enable", "pam_timing_read",
     "pam_cnn_param_count", "pam_cnn_forward", "pam_cnn_loss_grad", "pam_cnn_adam",
     "pam_grid_patches", "pam_support_hint", "pam_cnn_labels",
-    "pam_eval_blend", "pam_interface_count", "pam_interface_jump",
+    "pam_eval_blend", "pam_interface_count", "pam_interface_jump", "pam_select_lambda",
 ]
 TIMING_KINDS = ["gather", "lattice", "assemble", "gram", "solve", "indicator", "mark",
                 "eval_bin", "eval", "cnn", "blend", "jump"]
@@ -65,6 +65,11 @@ class PamRefineOpts(C.Structure):
                 ("m_max", C.c_int32), ("eta", C.c_double), ("eps_tol", C.c_double),
                 ("space", C.c_int32), ("elem_level", C.c_void_p), ("rounds", C.c_void_p),
                 ("round_stats", C.c_void_p), ("cold_rounds", C.c_int32)]
+
+
+class PamSelectOpts(C.Structure):
+    _fields_ = [("n_alpha", C.c_int32), ("k_folds", C.c_int32), ("alpha_min_ratio", C.c_double),
+                ("l1_ratio", C.c_double)]
 
 
 class PamField(C.Structure):
@@ -111,6 +116,9 @@ def lib():
         L.pam_interface_count.argtypes = [C.c_int32, C.POINTER(PamField)]
         L.pam_interface_jump.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P,
                                          C.c_int32, P]
+        L.pam_select_lambda.argtypes = [P, C.POINTER(PamSamples), C.POINTER(PamDict),
+                                        C.POINTER(PamEnetOpts), C.POINTER(PamSelectOpts), P, P, P,
+                                        P, P, P]
         L.pam_timing_enable.argtypes = [P, C.c_int32]
         L.pam_timing_read.argtypes = [P, P, P, C.c_int32]
         L.pam_cnn_param_count.argtypes = []

@@ -95,6 +95,36 @@ def test_c2_facies256_first_round(ctx):
     assert err <= 1e-5
 
 
+
+def test_c2_lambda_selection_sampled(ctx):
+    """Per-subdomain parameters at the facies256 size (64 subdomains, 12 x 12
+    lattice, 5 folds, 13 alphas down to 1e-6 alpha_max = 4,160 fits in FP32 mode): scores of three
+    sampled subdomains against the oracle's, the choice equal or tied, and
+    every subdomain's path and choice consistent (geometric grid, argmin)."""
+    g = synth.facies256()
+    S = api.partition(ctx, g)
+    D = api.init_lattice(ctx, g, [12, 12], 144)
+    out = api.select_lambda(ctx, S, D, api.EnetOpts(0.0, 0.0, "f32"), n_alpha=13, k_folds=5,
+                            alpha_min_ratio=1e-6)
+    torch.cuda.synchronize()
+    ga, gs, gb = _t(out["alpha"]), _t(out["score"]), _t(out["best"])
+    assert np.all(_t(out["n_failed"]) == 0)
+    assert np.array_equal(gb, np.argmin(gs, axis=1))
+    for s in range(64):
+        if ga[s, 0] > 0:
+            assert np.allclose(ga[s, 1:] / ga[s, :-1], 1e-6 ** (1 / 12), rtol=1e-12)
+    subs = [0, 27, 50]
+    sub, Ds = _sub_problem(O.partition(g), O.init_dictionary(g, [12, 12], 144), subs)
+    alpha, score, best, l1, l2 = O.select_lambda(sub, Ds, n_alpha=13, ratio=1e-6, k_folds=5)
+    tol = 1e-7 * np.abs(score).max() + 1e-12
+    err = np.abs(gs[subs] - score).max()
+    print("C2 selection sampled score error", err, "best", gb[subs], "oracle", best)
+    assert np.abs(ga[subs] - alpha).max() <= 1e-12 * np.abs(alpha).max()
+    assert err <= tol
+    for i, s in enumerate(subs):
+        if gb[s] != best[i]:
+            assert abs(score[i, gb[s]] - score[i, best[i]]) <= tol
+
 def test_c3_layered3d_first_fit(ctx):
     g = synth.layered3d()
     assert g.n_subdomains == 1188
