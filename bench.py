@@ -97,6 +97,8 @@ def parse():
                     help="path length (half-decade steps down to 1e-6 alpha_max by default)")
     ap.add_argument("--select-ratio", type=float, default=1e-6)
     ap.add_argument("--select-folds", type=int, default=5)
+    ap.add_argument("--no-darcy", action="store_true",
+                    help="skip the Darcy consumer (pressure error of the reconstruction)")
     ap.add_argument("--blend", type=float, default=0.1,
                     help="interface band half-width as a fraction of the shorter neighbour")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -288,6 +290,43 @@ def lambda_selection(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d, ycell, area,
                         "centers_mean": float(D.m.double().mean().item()),
                         "support_mean": float(api.stats_to_numpy(st)["support"].mean())}
     res["refined_field"] = fields
+    return res
+
+
+def darcy(ctx, api, grid, D, beta, blend):
+    """Pressure experiment of Exp. 1 on the fitted field: P1 elements on the
+    data grid, K = 10^K* at the triangle centroids (owner and continuous
+    reconstructions) against the data's own coefficient; CG timed with HIP
+    events (one launch group per solve)."""
+    import torch
+    if grid.dim != 2:
+        return None
+    o = api.DarcyOpts(grid.n_cells[0], grid.n_cells[1], grid.lo[:2], grid.hi[:2], tol=1e-10)
+    k_true = api.darcy_k_from_cells(grid, o, "cuda")
+    k_own = api.darcy_k_from_reconstruction(ctx, grid, D, beta, o)
+    k_blend = api.darcy_k_from_reconstruction(ctx, grid, D, beta, o, blend=blend)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read(reset=True)
+    res = {"mesh": [o.n0, o.n1], "nodes": (o.n0 + 1) * (o.n1 + 1), "tol": o.tol}
+    p = {}
+    for name, k in (("true", k_true), ("owner", k_own), ("continuous", k_blend)):
+        p[name], it, rel = api.darcy_solve(ctx, o, k)
+        tk = ctx.timing_read(reset=True)["darcy"]
+        res[name] = {"iterations": it, "rel_residual": rel, "ms": tk[0]}
+    ctx.timing(False)
+    res["E_p_owner"] = api.darcy_error(ctx, o, p["true"], p["owner"])
+    res["E_p_continuous"] = api.darcy_error(ctx, o, p["true"], p["continuous"])
+    # CG bytes per iteration: stencil pass (d, two edge arrays, q), update
+    # (x, d, r, q, diag read; x, r, z written), direction (z, d read; d written)
+    n = res["nodes"]
+    it = res["true"]["iterations"]
+    bytes_it = 8.0 * n * 15
+    ach = bytes_it * it / (res["true"]["ms"] / 1e3) / 1e9
+    res["roofline"] = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": ach / PEAK_HBM_GBS, "bytes_per_iteration": bytes_it,
+                       "note": "three launches per iteration on a 66k-node mesh: launch latency, "
+                               "not HBM, sets the time"}
     return res
 
 
@@ -580,6 +619,8 @@ def main():
         rec["lambda_selection"] = lambda_selection(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d,
                                                    ycell, area, args.select_alphas,
                                                    args.select_folds, args.select_ratio)
+    if not args.no_darcy:
+        rec["darcy"] = darcy(ctx, api, grid, D, beta, args.blend)
     if not args.no_continuity:
         rec["continuity"] = continuity(ctx, api, grid, D, beta, xq, w_d, ycell, area, args.blend)
     if use_learned:

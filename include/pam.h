@@ -337,6 +337,48 @@ pam_status pam_interface_jump(pam_ctx *ctx, int32_t n_fields, const pam_field *f
                               double *out);
 
 /* ------------------------------------------------------------------------
+ * Darcy consumer of the reconstruction (Sec. 5, Eq. (darcy_model); the
+ * pressure experiment of Exp. 1): -div(K grad p) = 0 on the 2-D box
+ * [lo, hi], p = p_left on the face x = lo[0], p = p_right on x = hi[0], no
+ * flow across the other faces; continuous P1 finite elements on the
+ * n[0] x n[1] squares of the box, each split along its diagonal from node
+ * (i, j) to node (i+1, j+1) into a lower-right triangle (i,j),(i+1,j),
+ * (i+1,j+1) and an upper-left one (i,j),(i+1,j+1),(i,j+1); nodes numbered
+ * i + (n[0] + 1) j. K is constant per triangle and given by the caller, e.g.
+ * 10^K* at the triangle centroids from pam_eval (space 1) or the data's own
+ * cell values.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n[2];          /* squares per axis, >= 1                           */
+    double lo[2], hi[2];   /* the box, lo < hi                                 */
+    double p_left, p_right;
+    double tol;            /* stop at ||r|| <= tol ||b||, b the right-hand side
+                              once the Dirichlet values are moved to it      */
+    int32_t max_iter;      /* >= 1                                             */
+    int32_t check_every;   /* iterations between host convergence checks, >= 1 */
+} pam_darcy_opts;
+
+/* Solves for the nodal pressure by Jacobi-preconditioned conjugate gradients
+ * in FP64 (Dirichlet nodes eliminated). k_tri: device double
+ * [n[1]][n[0]][2] (0 lower-right, 1 upper-left), K > 0. p: device double
+ * [(n[0]+1)(n[1]+1)]; with warm = 1 its free-node values are the starting
+ * point, else the start is linear between the two Dirichlet values; on
+ * return the solution. iters, rel_res: [host] outputs (iterations taken and
+ * the final ||r|| / ||b||; 0 when b = 0, whose solution is 0). Synchronizes the context's stream every
+ * check_every iterations. Workspace: seven node vectors and the edge
+ * weights, from the context. */
+pam_status pam_darcy_solve(pam_ctx *ctx, const pam_darcy_opts *opts, const double *k_tri,
+                           double *p, int32_t warm, int32_t *iters, double *rel_res);
+
+/* Relative L2(Omega) error of two P1 pressures on the same mesh (Eq.
+ * (pressure_L2_error)): ||p_ref - p|| / ||p_ref|| with the exact P1 mass
+ * matrix (per triangle |T| / 12 (sum u_a^2 + (sum u_a)^2)), summed in FP64 in
+ * a fixed order. p_ref, p: device double [(n[0]+1)(n[1]+1)]; e_rel: [host]
+ * output (0 if ||p_ref|| = 0). Synchronizes the context's stream. */
+pam_status pam_darcy_error(pam_ctx *ctx, const pam_darcy_opts *opts, const double *p_ref,
+                           const double *p, double *e_rel);
+
+/* ------------------------------------------------------------------------
  * Learned warm start (not part of the paper's method: a support prior for
  * the cold elastic-net fits). A four-layer convolutional network, 5x5
  * "same" convolutions with zero padding, 1 -> 32 -> 32 -> 32 -> 2 channels,
@@ -414,12 +456,12 @@ pam_status pam_cnn_labels(pam_ctx *ctx, const pam_grid *grid, const pam_samples 
  * last reset; reset = 1 clears the totals afterwards. EVAL_BIN covers the
  * query (or term) binning passes of both reconstructions and the weighted
  * sum of the continuous one; EVAL and BLEND the evaluation of the binned
- * queries and terms; JUMP the interface-jump kernel.
+ * queries and terms; JUMP the interface-jump kernel; DARCY a whole Darcy solve.
  * ------------------------------------------------------------------------ */
 enum {
     PAM_TK_GATHER = 0, PAM_TK_LATTICE, PAM_TK_ASSEMBLE, PAM_TK_GRAM, PAM_TK_SOLVE,
     PAM_TK_INDICATOR, PAM_TK_MARK, PAM_TK_EVAL_BIN, PAM_TK_EVAL, PAM_TK_CNN,
-    PAM_TK_BLEND, PAM_TK_JUMP, PAM_TK_COUNT
+    PAM_TK_BLEND, PAM_TK_JUMP, PAM_TK_DARCY, PAM_TK_COUNT
 };
 pam_status pam_timing_enable(pam_ctx *ctx, int32_t on);
 pam_status pam_timing_read(pam_ctx *ctx, double *ms /*[host] PAM_TK_COUNT*/,

@@ -436,6 +436,88 @@ def interface_jump(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, n_per
     return out[:nf]
 
 
+# ---------------------------------------------------------------- Darcy consumer
+@dataclass
+class DarcyOpts:
+    n0: int
+    n1: int
+    lo: Sequence[float] = (0.0, 0.0)
+    hi: Sequence[float] = (1.0, 1.0)
+    p_left: float = 1.0
+    p_right: float = 0.0
+    tol: float = 1e-10
+    max_iter: int = 200000
+    check_every: int = 64
+
+    def struct(self):
+        o = N.PamDarcyOpts()
+        o.n[0], o.n[1] = int(self.n0), int(self.n1)
+        for a in range(2):
+            o.lo[a], o.hi[a] = float(self.lo[a]), float(self.hi[a])
+        o.p_left, o.p_right, o.tol = float(self.p_left), float(self.p_right), float(self.tol)
+        o.max_iter, o.check_every = int(self.max_iter), int(self.check_every)
+        return o
+
+
+def triangle_centroids(o: DarcyOpts) -> np.ndarray:
+    """Centroids [n1, n0, 2 (lower-right, upper-left), 2] of the P1 mesh."""
+    xs = o.lo[0] + (o.hi[0] - o.lo[0]) * np.arange(o.n0 + 1) / o.n0
+    ys = o.lo[1] + (o.hi[1] - o.lo[1]) * np.arange(o.n1 + 1) / o.n1
+    x0, x1 = xs[None, :-1], xs[None, 1:]
+    y0, y1 = ys[:-1, None], ys[1:, None]
+    out = np.empty((o.n1, o.n0, 2, 2))
+    out[:, :, 0, 0] = (x0 + 2.0 * x1) / 3.0 + 0.0 * y0
+    out[:, :, 0, 1] = (2.0 * y0 + y1) / 3.0 + 0.0 * x0
+    out[:, :, 1, 0] = (2.0 * x0 + x1) / 3.0 + 0.0 * y0
+    out[:, :, 1, 1] = (y0 + 2.0 * y1) / 3.0 + 0.0 * x0
+    return out
+
+
+def darcy_k_from_reconstruction(ctx: Context, grid, D: Dictionary, beta: torch.Tensor,
+                                o: DarcyOpts, blend: Optional[float] = None) -> torch.Tensor:
+    """K = 10^K* at the triangle centroids (owner reconstruction, or the
+    continuous one with the given band), float64 [n1, n0, 2] on the device."""
+    xq = torch.as_tensor(triangle_centroids(o).reshape(-1, 2), device=beta.device)
+    if blend is None:
+        k = evaluate(ctx, grid, D, beta, xq, space=1)
+    else:
+        k = evaluate_blend(ctx, grid, D, beta, xq, blend, space=1)
+    return k.reshape(o.n1, o.n0, 2)
+
+
+def darcy_k_from_cells(grid, o: DarcyOpts, device) -> torch.Tensor:
+    """The data's own coefficient 10^y on a mesh whose squares are the data
+    cells (n0, n1 = the grid's cells): both triangles of a square take it."""
+    if (o.n0, o.n1) != (grid.n_cells[0], grid.n_cells[1]):
+        raise N.PamError("the mesh must be the data grid")
+    y = torch.as_tensor(grid.y, dtype=torch.float64, device=device).reshape(o.n1, o.n0)
+    return torch.pow(10.0, y)[:, :, None].expand(o.n1, o.n0, 2).contiguous()
+
+
+def darcy_solve(ctx: Context, o: DarcyOpts, k_tri: torch.Tensor, p: Optional[torch.Tensor] = None):
+    """Nodal pressure (float64 [(n1+1)(n0+1)]), iterations, final relative residual."""
+    _require_cuda(k_tri, "k_tri")
+    warm = p is not None
+    if p is None:
+        p = torch.empty((o.n0 + 1) * (o.n1 + 1), dtype=torch.float64, device=k_tri.device)
+    it = C.c_int32(0)
+    res = C.c_double(0.0)
+    os_ = o.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_darcy_solve(ctx.h, C.byref(os_), _p(k_tri.contiguous()), _p(p),
+                                    1 if warm else 0, C.byref(it), C.byref(res)), "pam_darcy_solve")
+    return p, int(it.value), float(res.value)
+
+
+def darcy_error(ctx: Context, o: DarcyOpts, p_ref: torch.Tensor, p: torch.Tensor) -> float:
+    e = C.c_double(0.0)
+    os_ = o.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_darcy_error(ctx.h, C.byref(os_), _p(p_ref), _p(p), C.byref(e)),
+            "pam_darcy_error")
+    return float(e.value)
+
+
 # ---------------------------------------------------------------- learned warm start
 CNN_PATCH = 16
 

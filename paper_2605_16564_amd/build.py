@@ -15,7 +15,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "_build" / "libpam.so"
 SOURCES = ["pam_api.hip", "k_setup.hip", "k_fit.hip", "k_solve.hip", "k_refine.hip", "k_eval.hip", "k_cnn.hip",
-           "k_select.hip"]
+           "k_select.hip", "k_darcy.hip"]
 ARCH = os.environ.get("PAM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -105,6 +105,11 @@ pam_status launch_eval_blend(pam_ctx *ctx, int n_fields, const pam_field *fields
                              const pam_dict *dict, const double *beta, double blend, int dtype,
                              const void *xq, int64_t Q, void *out, int space, int64_t *n_outside);
 int64_t interface_count(int n_fields, const pam_field *fields);
+// Darcy consumer (k_darcy.hip)
+pam_status launch_darcy_solve(pam_ctx *ctx, const pam_darcy_opts *o, const double *k_tri,
+                              double *p, int warm, int32_t *iters, double *rel_res);
+pam_status launch_darcy_error(pam_ctx *ctx, const pam_darcy_opts *o, const double *p_ref,
+                              const double *p, double *e_rel);
 // lambda selection (k_select.hip)
 pam_status launch_cv_setup(pam_ctx *ctx, const pam_samples *S, const pam_dict *D, int K,
                            const int64_t *off_v, double *xv, double *yv, int32_t *mv, double *cv,
@@ -564,6 +569,34 @@ pam_status pam_select_lambda(pam_ctx *ctx, const pam_samples *samples, const pam
     // the host offsets above are read by run_fit during the calls only
     return launch_cv_choose(ctx, n, sel->n_alpha, rho, alpha, score, best, lambda1_sub,
                             lambda2_sub);
+}
+
+static pam_status check_darcy(const pam_darcy_opts *o) {
+    PAM_REQUIRE(o, "NULL options");
+    PAM_REQUIRE(o->n[0] >= 1 && o->n[1] >= 1, "n must be >= 1");
+    PAM_REQUIRE((int64_t)(o->n[0] + 1) * (o->n[1] + 1) <= ((int64_t)1 << 30), "mesh too large");
+    PAM_REQUIRE(o->hi[0] > o->lo[0] && o->hi[1] > o->lo[1], "the box needs lo < hi");
+    PAM_REQUIRE(o->tol > 0.0 && o->max_iter >= 1 && o->check_every >= 1,
+                "tol > 0, max_iter >= 1 and check_every >= 1 required");
+    return PAM_OK;
+}
+
+pam_status pam_darcy_solve(pam_ctx *ctx, const pam_darcy_opts *opts, const double *k_tri,
+                           double *p, int32_t warm, int32_t *iters, double *rel_res) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    if ((st = check_darcy(opts)) != PAM_OK) return st;
+    PAM_REQUIRE(k_tri && p && iters && rel_res, "NULL argument");
+    return launch_darcy_solve(ctx, opts, k_tri, p, warm ? 1 : 0, iters, rel_res);
+}
+
+pam_status pam_darcy_error(pam_ctx *ctx, const pam_darcy_opts *opts, const double *p_ref,
+                           const double *p, double *e_rel) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    if ((st = check_darcy(opts)) != PAM_OK) return st;
+    PAM_REQUIRE(p_ref && p && e_rel, "NULL argument");
+    return launch_darcy_error(ctx, opts, p_ref, p, e_rel);
 }
 
 // Field table checks shared by the evaluation entry points; with Q < 0 the

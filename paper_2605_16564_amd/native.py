@@ -23,9 +23,11 @@ EXPORTS = [
     "pam_cnn_param_count", "pam_cnn_forward", "pam_cnn_loss_grad", "pam_cnn_adam",
     "pam_grid_patches", "pam_support_hint", "pam_cnn_labels",
     "pam_eval_blend", "pam_interface_count", "pam_interface_jump", "pam_select_lambda",
+    "pam_darcy_solve", "pam_darcy_error",
 ]
 TIMING_KINDS = ["gather", "lattice", "assemble", "gram", "solve", "indicator", "mark",
-                "eval_bin", "eval", "cnn", "blend", "jump"]
+                "eval_bin", "eval", "cnn", "blend", "jump",
+                "darcy"]
 
 
 class PamGrid(C.Structure):
@@ -70,6 +72,12 @@ class PamRefineOpts(C.Structure):
 class PamSelectOpts(C.Structure):
     _fields_ = [("n_alpha", C.c_int32), ("k_folds", C.c_int32), ("alpha_min_ratio", C.c_double),
                 ("l1_ratio", C.c_double)]
+
+
+class PamDarcyOpts(C.Structure):
+    _fields_ = [("n", C.c_int32 * 2), ("lo", C.c_double * 2), ("hi", C.c_double * 2),
+                ("p_left", C.c_double), ("p_right", C.c_double), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("check_every", C.c_int32)]
 
 
 class PamField(C.Structure):
@@ -119,6 +127,8 @@ def lib():
         L.pam_select_lambda.argtypes = [P, C.POINTER(PamSamples), C.POINTER(PamDict),
                                         C.POINTER(PamEnetOpts), C.POINTER(PamSelectOpts), P, P, P,
                                         P, P, P]
+        L.pam_darcy_solve.argtypes = [P, C.POINTER(PamDarcyOpts), P, P, C.c_int32, P, P]
+        L.pam_darcy_error.argtypes = [P, C.POINTER(PamDarcyOpts), P, P, P]
         L.pam_timing_enable.argtypes = [P, C.c_int32]
         L.pam_timing_read.argtypes = [P, P, P, C.c_int32]
         L.pam_cnn_param_count.argtypes = []

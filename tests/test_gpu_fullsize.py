@@ -125,6 +125,21 @@ def test_c2_lambda_selection_sampled(ctx):
         if gb[s] != best[i]:
             assert abs(score[i, gb[s]] - score[i, best[i]]) <= tol
 
+
+def test_c2_darcy_on_the_data_coefficient(ctx):
+    """The Darcy consumer at the facies256 size (P1 on the 256 x 256 data
+    grid, 66,049 nodes, contrast 1e4) on the data's own coefficient: the CG
+    pressure against the oracle's sparse direct solve."""
+    from oracle import darcy_oracle as DO
+    g = synth.facies256()
+    o = api.DarcyOpts(256, 256, tol=1e-12)
+    p, it, rel = api.darcy_solve(ctx, o, api.darcy_k_from_cells(g, o, "cuda"))
+    lo, hi = np.zeros(2), np.ones(2)
+    ref = DO.solve(256, 256, lo, hi, DO.k_from_cells(256, 256, lo, hi, g.y, 256, 256))
+    err = np.abs(_t(p) - ref).max()
+    print("C2 Darcy iterations", it, "residual", rel, "max pressure error", err)
+    assert rel <= 1e-12 and err <= 1e-8
+
 def test_c3_layered3d_first_fit(ctx):
     g = synth.layered3d()
     assert g.n_subdomains == 1188
