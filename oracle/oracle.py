@@ -94,8 +94,18 @@ def lib():
         L.ora_select_lambda.argtypes = [C.c_int, C.c_int, _lp, _dp, _dp, C.c_int, _ip, _dp, _dp,
                                         C.c_int, C.c_double, C.c_double, C.c_int, C.c_int, _dp,
                                         _dp, _ip]
+        L.ora_set_basis.restype = None
+        L.ora_set_basis.argtypes = [C.c_int]
         _lib = L
     return _lib
+
+
+def _basis(basis):
+    """Select the basis for the next oracle call ("shepard": the normalized
+    functions of Sec. 3.2; "plain": the unnormalized Gaussians of Example 1)."""
+    if basis not in ("shepard", "plain"):
+        raise ValueError("basis must be 'shepard' or 'plain'")
+    lib().ora_set_basis(1 if basis == "plain" else 0)
 
 
 def _f64(a):
@@ -146,8 +156,9 @@ def lattice(box_lo, box_hi, g, sigma_factor=1.0):
 
 
 # ---------------------------------------------------------------- a3-a6
-def design(x, c, sigma):
+def design(x, c, sigma, basis="shepard"):
     x = _f64(x); c = _f64(c)
+    _basis(basis)
     N, d = x.shape
     M = c.shape[0]
     W = np.zeros((N, M))
@@ -184,9 +195,10 @@ def kkt(G, b, lambda1, lambda2, beta):
     return lib().ora_kkt(len(b), _f64(G).reshape(-1), _f64(b), lambda1, lambda2, _f64(beta))
 
 
-def fit_one(x, y, c, sigma, lambda1, lambda2, cd_sweeps=8, beta=None):
+def fit_one(x, y, c, sigma, lambda1, lambda2, cd_sweeps=8, beta=None, basis="shepard"):
     """Steps a3-a6 on one subdomain; returns (beta, status, stats)."""
     x = _f64(x); c = _f64(c)
+    _basis(basis)
     N, d = x.shape
     M = c.shape[0]
     beta = np.zeros(M) if beta is None else _f64(beta).copy()
@@ -196,8 +208,9 @@ def fit_one(x, y, c, sigma, lambda1, lambda2, cd_sweeps=8, beta=None):
     return beta, st, stats
 
 
-def indicator(x, y, h, c, sigma, beta, space=0):
+def indicator(x, y, h, c, sigma, beta, space=0, basis="shepard"):
     x = _f64(x); c = _f64(c)
+    _basis(basis)
     N, d = x.shape
     R = np.zeros(N)
     lib().ora_indicator(d, N, c.shape[0], x.ravel(), _f64(y), _f64(h).ravel(), c.ravel(),
@@ -222,19 +235,22 @@ class Dictionary:
         self.c = np.zeros(n_sub * m_cap * dim)
         self.sigma = np.zeros(n_sub * m_cap)
         self.level = np.zeros(n_sub * m_cap, np.int32)
+        self.basis = "shepard"
 
     def copy(self):
         o = Dictionary(self.n_sub, self.m_cap, self.dim)
         o.m = self.m.copy(); o.c = self.c.copy(); o.sigma = self.sigma.copy()
         o.level = self.level.copy()
+        o.basis = self.basis
         return o
 
 
-def init_dictionary(grid, g, m_cap, sigma_factor=1.0) -> Dictionary:
+def init_dictionary(grid, g, m_cap, sigma_factor=1.0, basis="shepard") -> Dictionary:
     """Lattice dictionary for every owned box of a grid partition (a2)."""
     d = grid.dim
     boxes = grid_owned_boxes(grid)
     D = Dictionary(len(boxes), m_cap, d)
+    D.basis = basis
     M = int(np.prod(g[:d]))
     for s, (lo, hi) in enumerate(boxes):
         c, sg, lv = lattice(lo, hi, list(g[:d]), sigma_factor)
@@ -275,6 +291,7 @@ def fit_batch(samples, D: Dictionary, lambda1, lambda2, cd_sweeps=8, beta=None):
     beta = np.zeros(n * D.m_cap) if beta is None else _f64(beta).copy()
     stats = np.zeros(3 * n)
     status = np.zeros(n, np.int32)
+    _basis(D.basis)
     lib().ora_fit_batch(d, n, samples["off"], _f64(samples["x"]).ravel(), _f64(samples["y"]),
                         D.m_cap, D.m, D.c, D.sigma, lambda1, lambda2, cd_sweeps, beta, stats,
                         status)
@@ -294,6 +311,7 @@ def refine_batch(samples, D: Dictionary, lambda1, lambda2, k_top, max_rounds, m_
     rs = np.zeros(n * (max_rounds + 1) * 5)
     rounds = np.zeros(n, np.int32)
     status = np.zeros(n, np.int32)
+    _basis(D.basis)
     lib().ora_refine_batch(d, n, samples["off"], _f64(samples["x"]).ravel(),
                            _f64(samples["y"]), _f64(samples["h"]).ravel(), D.m_cap, D.m, D.c,
                            D.sigma, D.level, beta, lvl, lambda1, lambda2, cd_sweeps, k_top,
@@ -310,6 +328,7 @@ def evaluate(axis_x, D: Dictionary, beta, xq, space=0):
     out = np.zeros(Q)
     ns = _i32([len(a) - 1 for a in axis_x])
     ax = _f64(np.concatenate(axis_x))
+    _basis(D.basis)
     n_out = lib().ora_eval(d, ns, ax, D.m_cap, D.m, D.c, D.sigma, _f64(beta), Q, xq.ravel(),
                            space, out)
     return out, n_out
@@ -325,6 +344,7 @@ def evaluate_blend(axis_x, D: Dictionary, beta, xq, blend, space=0):
     out = np.zeros(Q)
     ns = _i32([len(a) - 1 for a in axis_x])
     ax = _f64(np.concatenate(axis_x))
+    _basis(D.basis)
     n_out = lib().ora_eval_blend(d, ns, ax, float(blend), D.m_cap, D.m, D.c, D.sigma, _f64(beta),
                                  Q, xq.ravel(), space, out)
     return out, n_out
@@ -345,6 +365,7 @@ def interface_jump(axis_x, D: Dictionary, beta, n):
     nf = interface_count(ns)
     out = np.zeros(2 * max(nf, 1))
     ax = _f64(np.concatenate(axis_x))
+    _basis(D.basis)
     got = lib().ora_interface_jump(d, ns, ax, D.m_cap, D.m, D.c, D.sigma, _f64(beta), int(n), out)
     assert got == nf
     return out[:2 * nf].reshape(nf, 2)
@@ -359,6 +380,7 @@ def select_lambda(samples, D: Dictionary, n_alpha=8, ratio=1e-3, rho=0.99, k_fol
     alpha = np.zeros(n * n_alpha)
     score = np.zeros(n * n_alpha)
     best = np.zeros(n, np.int32)
+    _basis(D.basis)
     bad = lib().ora_select_lambda(D.dim, n, samples["off"], _f64(samples["x"]).ravel(),
                                   _f64(samples["y"]), D.m_cap, D.m, D.c, D.sigma, int(n_alpha),
                                   float(ratio), float(rho), int(k_folds), int(cd_sweeps), alpha,

@@ -216,9 +216,18 @@ static double ora_phi(int dim, const double *x, const double *c, double sigma)
     return exp(-r2 / (2.0 * sigma * sigma));
 }
 
+/* Basis of the local expansion, a process-wide switch that the Python
+ * wrappers set before every call: 0 = Shepard-normalized (Sec. 3.2, the
+ * method's), 1 = the plain Gaussians (the unnormalized comparison of
+ * Example 1). Every function below builds its design with ora_design and
+ * evaluates with ora_surrogate, the only two places that read it. */
+static int ora_plain = 0;
+
+void ora_set_basis(int plain) { ora_plain = plain ? 1 : 0; }
+
 /* W is N x M row-major. Returns ORA_ERR_UNDERFLOW if a row sum is not a
  * positive normal number (the normalization is defined only where the sum of
- * the basis functions is positive). */
+ * the basis functions is positive). The plain basis keeps phi itself. */
 int ora_design(int dim, int N, int M, const double *x, const double *c,
                const double *sigma, double *W)
 {
@@ -229,6 +238,7 @@ int ora_design(int dim, int N, int M, const double *x, const double *c,
             W[(long)j * M + m] = p;
             s += p;
         }
+        if (ora_plain) continue;
         if (!(s >= DBL_MIN)) return ORA_ERR_UNDERFLOW;
         for (int m = 0; m < M; ++m) W[(long)j * M + m] /= s;
     }
@@ -515,7 +525,7 @@ static double ora_surrogate(int dim, int M, const double *c, const double *sigma
         num += beta[m] * p;
         den += p;
     }
-    return num / den;
+    return ora_plain ? num : num / den;
 }
 
 /* ------------------------------------------------------------------------- */
