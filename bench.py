@@ -471,9 +471,9 @@ def main():
         from paper_2605_16564_amd import learned
         params, learned_rec = train_learned(ctx, api, wl, prec, args.train_mosaics)
 
-    def step(batched=True, cold=False, hinted=use_learned, precision=prec):
+    def step(batched=True, cold=False, hinted=use_learned, precision=prec, basis="shepard"):
         S = api.partition(ctx, grid, cell_y)
-        D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
+        D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor, basis=basis)
         hint = learned.hint(ctx, params, grid, D, precision="bf16") if hinted else None
         o = api.EnetOpts(wl.lambda1, wl.lambda2, precision, cd_sweeps=args.cd_sweeps, batched=batched,
                          support_hint=hint)
@@ -631,7 +631,8 @@ def main():
         # unbatched run is one timed step): fits/s and the ratio it costs
         abl = {}
         variants = [("no_learned", dict(hinted=False), 1), ("fp64", dict(precision="f64"), 1),
-                    ("unbatched", dict(batched=False), 0)]
+                    ("unbatched", dict(batched=False), 0),
+                    ("plain_basis", dict(basis="plain", hinted=False), 1)]
         for name, kw, warm in variants:
             if name == "no_learned" and not use_learned:
                 continue
@@ -642,7 +643,9 @@ def main():
             ra = step(**kw)
             torch.cuda.synchronize()
             va = int(ra[3].sum().item()) / (time.perf_counter() - ta)
-            abl[name] = {"value": va, "unit": "fits/s", "speedup_of_pattern": value / va}
+            l1a = float((w_d * (ra[6].double() - ycell).abs()).sum().item()) / area
+            abl[name] = {"value": va, "unit": "fits/s", "speedup_of_pattern": value / va,
+                         "field_l1_log10": l1a}
         rec["ablations"] = abl
     if not args.no_comparator:
         # plain GPU fit: one launch per subdomain and kernel, every refit from

@@ -112,7 +112,16 @@ typedef struct {
     double *c;         /* [n_sub*m_cap*dim] centers                           */
     double *sigma;     /* [n_sub*m_cap] widths, > 0                           */
     int32_t *level;    /* [n_sub*m_cap] refinement level of each center       */
+    int32_t basis;     /* PAM_BASIS_SHEPARD (default) or PAM_BASIS_PLAIN       */
 } pam_dict;
+
+/* Basis of the local expansion. SHEPARD: the normalized functions
+ * phi_m / sum_k phi_k over the subdomain's whole dictionary (Sec. 3.2, Def. 1,
+ * Eq. (shepard_rbf)), the method's own. PLAIN: the Gaussians phi_m
+ * themselves, the unnormalized construction the paper compares against in
+ * Example 1 (an ablation: every fit, indicator and evaluation entry point
+ * then uses sum_m beta_m phi_m). */
+enum { PAM_BASIS_SHEPARD = 0, PAM_BASIS_PLAIN = 1 };
 
 /* a2. Initial dictionary: g[0]*..*g[dim-1] lattice at the cell centers of
  * each owned box, common width sigma0 = sigma_factor * max_axis(h_c) where

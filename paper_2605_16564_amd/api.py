@@ -160,6 +160,7 @@ class Dictionary:
     c: torch.Tensor        # f64 [n_sub, m_cap, dim]
     sigma: torch.Tensor    # f64 [n_sub, m_cap]
     level: torch.Tensor    # int32 [n_sub, m_cap]
+    basis: str = "shepard" # "shepard" (the method's) or "plain" (the unnormalized ablation)
 
     @staticmethod
     def empty(n_sub, dim, m_cap, device):
@@ -172,28 +173,34 @@ class Dictionary:
 
     def clone(self):
         return Dictionary(self.n_sub, self.dim, self.m_cap, self.m.clone(), self.c.clone(),
-                          self.sigma.clone(), self.level.clone())
+                          self.sigma.clone(), self.level.clone(), self.basis)
 
     def struct(self):
         s = N.PamDict()
         s.n_sub, s.dim, s.m_cap = self.n_sub, self.dim, self.m_cap
         s.m, s.c, s.sigma, s.level = _p(self.m), _p(self.c), _p(self.sigma), _p(self.level)
+        if self.basis not in N.BASIS:
+            raise N.PamError("basis must be 'shepard' or 'plain'")
+        s.basis = N.BASIS[self.basis]
         return s
 
 
 def concat_dicts(parts: Sequence["Dictionary"]) -> "Dictionary":
     """Dictionaries of several grids (same dim and m_cap) as one batch."""
     d0 = parts[0]
-    if any(D.m_cap != d0.m_cap or D.dim != d0.dim for D in parts):
-        raise N.PamError("dictionaries to concatenate need the same dim and m_cap")
+    if any(D.m_cap != d0.m_cap or D.dim != d0.dim or D.basis != d0.basis for D in parts):
+        raise N.PamError("dictionaries to concatenate need the same dim, m_cap and basis")
     return Dictionary(int(sum(D.n_sub for D in parts)), d0.dim, d0.m_cap, torch.cat([D.m for D in parts]),
                       torch.cat([D.c for D in parts]), torch.cat([D.sigma for D in parts]),
-                      torch.cat([D.level for D in parts]))
+                      torch.cat([D.level for D in parts]), d0.basis)
 
 
-def init_lattice(ctx: Context, grid, g: Sequence[int], m_cap: int, sigma_factor: float = 1.0):
-    """a2: g^d lattice dictionary per owned box."""
+def init_lattice(ctx: Context, grid, g: Sequence[int], m_cap: int, sigma_factor: float = 1.0,
+                 basis: str = "shepard"):
+    """a2: g^d lattice dictionary per owned box (basis: "shepard", the method's
+    normalized functions, or "plain", the unnormalized Gaussians)."""
     D = Dictionary.empty(int(np.prod(grid.n_sub[: grid.dim])), grid.dim, m_cap, ctx.device)
+    D.basis = basis
     gs, brk = _grid_struct(grid)
     garr = np.ascontiguousarray(np.asarray(g[: grid.dim], np.int32))
     ds = D.struct()

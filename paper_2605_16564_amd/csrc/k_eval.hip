@@ -416,7 +416,7 @@ k_eval_chunks(int dim, int m_cap, const int32_t *__restrict__ n_chunks,
               const int32_t *__restrict__ m, const double *__restrict__ c,
               const double *__restrict__ sigma, const double *__restrict__ beta,
               const TQ *__restrict__ xq, TQ *__restrict__ out, int space,
-              TQ *__restrict__ tval) {
+              TQ *__restrict__ tval, int plain) {
     const int ch = blockIdx.x;
     if (ch >= *n_chunks) return;
     const int s = ch_sub[ch];
@@ -475,7 +475,7 @@ k_eval_chunks(int dim, int m_cap, const int32_t *__restrict__ n_chunks,
         }
     }
     if (live) {
-        TQ v = num / den;
+        TQ v = plain ? num : num / den;
         if constexpr (TERMS) {
             tval[id] = v;
         } else {
@@ -605,11 +605,13 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
         if (blended)
             hipLaunchKernelGGL((k_eval_chunks<TQ, true>), dim3((unsigned)max_chunks), dim3(kE), 0,
                                ctx->stream, dict->dim, dict->m_cap, nch, chsub, chstart, chlen,
-                               perm, dict->m, dict->c, dict->sigma, beta, xq, out, space, tval);
+                               perm, dict->m, dict->c, dict->sigma, beta, xq, out, space, tval,
+                               dict->basis == PAM_BASIS_PLAIN);
         else
             hipLaunchKernelGGL((k_eval_chunks<TQ, false>), dim3((unsigned)max_chunks), dim3(kE), 0,
                                ctx->stream, dict->dim, dict->m_cap, nch, chsub, chstart, chlen,
-                               perm, dict->m, dict->c, dict->sigma, beta, xq, out, space, tval);
+                               perm, dict->m, dict->c, dict->sigma, beta, xq, out, space, tval,
+                               dict->basis == PAM_BASIS_PLAIN);
         PAM_CHECK_HIP(hipGetLastError());
     }
     if (blended) {
@@ -659,7 +661,7 @@ __global__ void __launch_bounds__(kJT)
 k_jump(const FaceDev *__restrict__ faces, int n_faces, int n, int m_cap,
        const int32_t *__restrict__ m, const double *__restrict__ c,
        const double *__restrict__ sigma, const double *__restrict__ beta,
-       double *__restrict__ out) {
+       double *__restrict__ out, int plain) {
     const int f = blockIdx.x;
     if (f >= n_faces) return;
     const FaceDev F = faces[f];
@@ -714,7 +716,7 @@ k_jump(const FaceDev *__restrict__ faces, int n_faces, int n, int m_cap,
                     }
                 }
             }
-            val[side] = num / den;
+            val[side] = plain ? num : num / den;
         }
         if (live) {
             const double j = fabs(val[0] - val[1]);
@@ -786,7 +788,8 @@ pam_status launch_interface_jump(pam_ctx *ctx, int n_fields, const pam_field *fi
     if ((st = upload_to(ctx, dfaces, faces.data(), bytes)) != PAM_OK) return st;
     KernelTimer kt(ctx, PAM_TK_JUMP);
     hipLaunchKernelGGL(k_jump, dim3((unsigned)faces.size()), dim3(kJT), 0, ctx->stream, dfaces,
-                       (int)faces.size(), n, dict->m_cap, dict->m, dict->c, dict->sigma, beta, out);
+                       (int)faces.size(), n, dict->m_cap, dict->m, dict->c, dict->sigma, beta, out,
+                       dict->basis == PAM_BASIS_PLAIN);
     PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;
 }

@@ -19,7 +19,8 @@ static constexpr int kChunk = 256;   // centers staged in LDS per pass
 // One thread per sample row j of subdomain s: pass 1 accumulates the Shepard
 // denominator sum_m phi_m(x_j), pass 2 writes W_jm = phi_m(x_j)/sum into the
 // transposed design Wt[m][j]; row M of Wt carries the data y so that the Gram
-// product also yields b = W'y. Columns j >= N are zero padding.
+// product also yields b = W'y. Columns j >= N are zero padding. The plain
+// (unnormalized) basis skips pass 1 and writes phi_m(x_j) itself.
 template <typename TW>
 __device__ __forceinline__ TW to_w(double v);
 template <> __device__ __forceinline__ double to_w<double>(double v) { return v; }
@@ -49,10 +50,13 @@ k_assemble(FitArgs a, TW *__restrict__ Wt, int32_t *__restrict__ flags) {
     const double *ss = a.sigma + (size_t)s * a.m_cap;
     double sum = 0.0;
     float sumf = 0.0f;
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = a.basis == PAM_BASIS_PLAIN ? 1 : 0; pass < 2; ++pass) {
         double inv = 0.0;
         float invf = 0.0f;
-        if (pass == 1) {
+        if (pass == 1 && a.basis == PAM_BASIS_PLAIN) {
+            inv = 1.0;
+            invf = 1.0f;
+        } else if (pass == 1) {
             if (kF64) {
                 if (live && !(sum >= DBL_MIN)) atomicOr(&flags[s], 1);
                 inv = 1.0 / sum;

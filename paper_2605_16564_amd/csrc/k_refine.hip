@@ -79,7 +79,7 @@ k_indicator(RefineArgs a, double *__restrict__ R) {
     const double w = vol / (double)nq;
     double acc = 0.0;
     for (int q = 0; q < nq; ++q) {
-        const double v = num[q] / den[q];
+        const double v = a.basis == PAM_BASIS_PLAIN ? num[q] : num[q] / den[q];
         const double e = a.space == 0 ? v - yv : exp10(v) - exp10(yv);
         acc += w * e * e;
     }

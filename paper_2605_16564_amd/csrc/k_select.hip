@@ -91,7 +91,7 @@ k_alpha_path(int n_sub, int dim, int m_cap, const int64_t *__restrict__ off,
              const double *__restrict__ x, const double *__restrict__ y,
              const int32_t *__restrict__ m, const double *__restrict__ c,
              const double *__restrict__ sigma, double *__restrict__ inv_s, int n_alpha,
-             double ratio, double rho, double *__restrict__ alpha) {
+             double ratio, double rho, double *__restrict__ alpha, int plain) {
     const int s = blockIdx.x;
     if (s >= n_sub) return;
     __shared__ double red[kS];
@@ -110,7 +110,7 @@ k_alpha_path(int n_sub, int dim, int m_cap, const int64_t *__restrict__ off,
             }
             sum += exp(-r2 / (2.0 * sg[mm] * sg[mm]));
         }
-        inv_s[j0 + j] = sum > 0.0 ? 1.0 / sum : 0.0;
+        inv_s[j0 + j] = plain ? 1.0 : (sum > 0.0 ? 1.0 / sum : 0.0);
     }
     __syncthreads();
     double amax = 0.0;
@@ -154,7 +154,7 @@ k_cv_score(int n_sub, int K, int dim, int m_cap, int n_alpha, int k,
            const double *__restrict__ y, const int32_t *__restrict__ m,
            const double *__restrict__ c, const double *__restrict__ sigma,
            const double *__restrict__ beta_v, const pam_fit_stats *__restrict__ stats_v,
-           double *__restrict__ score, int32_t *__restrict__ n_failed) {
+           double *__restrict__ score, int32_t *__restrict__ n_failed, int plain) {
     const int s = blockIdx.x;
     if (s >= n_sub) return;
     __shared__ double sc[kSC * 3];
@@ -199,7 +199,7 @@ k_cv_score(int n_sub, int K, int dim, int m_cap, int n_alpha, int k,
             }
         }
         if (live) {
-            const double e = y[j0 + j] - (den > 0.0 ? num / den : 0.0);
+            const double e = y[j0 + j] - (plain ? num : (den > 0.0 ? num / den : 0.0));
             err += e * e;
         }
     }
@@ -248,7 +248,8 @@ pam_status launch_cv_setup(pam_ctx *ctx, const pam_samples *S, const pam_dict *D
                        D->c, D->sigma, D->level, mv, cv, sv, lv, beta_v);
     PAM_CHECK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_alpha_path, dim3(n), dim3(kS), 0, ctx->stream, n, S->dim, D->m_cap, S->off,
-                       S->x, S->y, D->m, D->c, D->sigma, inv_s, n_alpha, ratio, rho, alpha);
+                       S->x, S->y, D->m, D->c, D->sigma, inv_s, n_alpha, ratio, rho, alpha,
+                       D->basis == PAM_BASIS_PLAIN);
     PAM_CHECK_HIP(hipGetLastError());
     if (n_failed) {
         hipLaunchKernelGGL(k_cv_zero, dim3((n + kS - 1) / kS), dim3(kS), 0, ctx->stream, n, n_failed);
@@ -270,7 +271,7 @@ pam_status launch_cv_score(pam_ctx *ctx, const pam_samples *S, const pam_dict *D
                            double *score, int32_t *n_failed) {
     hipLaunchKernelGGL(k_cv_score, dim3(S->n_sub), dim3(kS), 0, ctx->stream, S->n_sub, K, S->dim,
                        D->m_cap, n_alpha, k, S->off, S->x, S->y, D->m, D->c, D->sigma, beta_v,
-                       stats_v, score, n_failed);
+                       stats_v, score, n_failed, D->basis == PAM_BASIS_PLAIN);
     PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;
 }

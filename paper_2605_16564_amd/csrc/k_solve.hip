@@ -686,6 +686,31 @@ __device__ __forceinline__ bool activate(Sv<TG> &v, int *list, int n, Red &red, 
     return any;
 }
 
+// Rebuild the inverse of the active block from the Gram: the frozen set is
+// applied, the active coordinates are collected in position order and enter
+// an empty block again by bordering (kB at a time). Used when a violating
+// coordinate can no longer enter because the incrementally updated inverse
+// has lost accuracy (ill-conditioned blocks after many updates). Signs are
+// kept; coordinates that cannot re-enter are deactivated.
+template <typename TG>
+__device__ __forceinline__ void rebuild(Sv<TG> &v, int *list, Red &red, double *cinv, int *blk,
+                                        double *tile) {
+    compact(v, tile);
+    const int s = v.s;
+    for (int i = threadIdx.x; i < s; i += kT) v.rhs[i] = (double)v.S[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < s; i += kT) v.pos[v.S[i]] = -1;
+    __syncthreads();
+    v.s = 0;
+    for (int b0 = 0; b0 < s; b0 += kB) {
+        const int nb = min(kB, s - b0);
+        if (threadIdx.x < nb) list[threadIdx.x] = (int)v.rhs[b0 + threadIdx.x];
+        __syncthreads();
+        activate(v, list, nb, red, cinv, blk, tile);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- FP64 phase
 // Low-precision Gram modes: the first pass of the iteration solves the
 // problem whose design and Gram are rounded to FP32 (or BF16). A second pass
@@ -702,7 +727,8 @@ struct Pol {
     double *w;            // [M] -1 / (2 sigma_m^2)
     double *p, *q, *t;    // [m_cap] CG vectors by active position
     double *u;            // [N] per-sample vector
-    double *is;           // [N] 1 / s_j
+    double *is;           // [N] 1 / s_j (1 for the plain basis)
+    int plain;            // unnormalized basis: W64 = Phi
 };
 
 // Per-sample pass: for samples j (two per thread at a time, for independent
@@ -781,7 +807,7 @@ __device__ __forceinline__ void center_pass(const Pol &P, int n, K key, F out) {
 template <typename TG>
 __device__ __forceinline__ void grad64(Sv<TG> &v, const Pol &P) {
     sample_pass(P, v.M, [](int i) { return i; }, v.beta, [&](int j, double sj, double num) {
-        const double is = 1.0 / sj;
+        const double is = P.plain ? 1.0 : 1.0 / sj;
         P.is[j] = is;
         P.u[j] = (P.y[j] - num * is) * is;
     });
@@ -1027,7 +1053,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         for (int m = threadIdx.x; m < M; m += kT) t = fmax(t, fabs(v.b[m]));
         return t;
     }(), red);
-    int it = 0, status = PAM_ST_NOCONV, refines = 0, n_cg = 0;
+    int it = 0, status = PAM_ST_NOCONV, refines = 0, n_cg = 0, rebuilds = 0;
     bool skip_solve = false, ran_ex = false;
     // v.z holds the solution of the current signed block (zv): line searches
     // and activations then carry it by rank-one and bordering identities
@@ -1052,6 +1078,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         P.q = P.p + a.m_cap;
         P.t = P.q + a.m_cap;
         P.u = P.t + a.m_cap;
+        P.plain = a.basis == PAM_BASIS_PLAIN;
         P.is = P.u + a.npad;
         for (int m = threadIdx.x; m < M; m += kT) P.w[m] = -0.5 / (P.sg[m] * P.sg[m]);
         __syncthreads();
@@ -1067,6 +1094,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         grad64(v, P);
         status = PAM_ST_NOCONV;
         refines = 0;
+        rebuilds = 0;
         skip_solve = false;
         ran_ex = true;
 #ifdef PAM_PHASE_PROFILE
@@ -1082,6 +1110,15 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     const int it_end = ex ? min(a.max_iter, it + 2 * M + 100) : a.max_iter;
     while (it < it_end) {
         ++it;
+        // a long run means sign decisions taken on an inverse that the many
+        // incremental updates made inexact (ill-conditioned blocks): start
+        // it afresh from the Gram at 4M and 8M iterations
+        if (!ex && (it == 4 * M || it == 8 * M) && v.s > 0) {
+            rebuild(v, list, red, cinv, blk, tile);
+            zv = false;
+            n_inc = 0;
+            skip_solve = false;
+        }
         if (v.s > 0 && !skip_solve) {
             if (ex) compact(v, tile);   // the CG solve runs on live positions only
             const int s = v.s;
@@ -1315,7 +1352,17 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
 #ifdef PAM_PHASE_PROFILE
             n_add += nadd;
 #endif
-            if (!activate(v, list, nadd, red, cinv, blk, tile, zv && !ex)) break;
+            if (!activate(v, list, nadd, red, cinv, blk, tile, zv && !ex)) {
+                // none could enter: rebuild the block inverse (at most twice
+                // per phase) and take the step again from the same point
+                if (rebuilds >= 2) break;
+                ++rebuilds;
+                rebuild(v, list, red, cinv, blk, tile);
+                zv = false;
+                n_inc = 0;
+                skip_solve = false;
+                continue;
+            }
             n_inc += 1;
             refines = 0;
 #ifdef PAM_INC_CHECK

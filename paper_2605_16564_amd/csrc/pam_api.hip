@@ -184,6 +184,7 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
     a.beta = beta;
     a.stats = stats;
     a.active = active;
+    a.basis = D->basis;
     const size_t per_sub = (size_t)a.mpad * a.npad * wbytes(a.precision) +
                            (size_t)a.mpad * a.mpad * gbytes(a.precision) +
                            solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad) * 8;
@@ -223,6 +224,7 @@ static pam_status check_fit_args(const pam_samples *S, const pam_dict *D, const 
     PAM_REQUIRE(S->off && S->off_host && S->x && S->y, "sample arrays are NULL");
     PAM_REQUIRE(D->m && D->c && D->sigma && D->level, "dictionary arrays are NULL");
     PAM_REQUIRE(D->m_cap >= 1, "m_cap must be >= 1");
+    PAM_REQUIRE(D->basis == PAM_BASIS_SHEPARD || D->basis == PAM_BASIS_PLAIN, "unknown basis");
     PAM_REQUIRE(o->lambda1_sub || o->lambda1 >= 0.0, "lambda1 must be >= 0");
     PAM_REQUIRE(o->lambda2_sub || o->lambda2 >= 0.0, "lambda2 must be >= 0");
     PAM_REQUIRE(o->precision >= PAM_PREC_F64 && o->precision <= PAM_PREC_BF16, "unknown precision");
@@ -459,6 +461,7 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     ra.rounds = r->rounds;
     ra.round_stats = r->round_stats;
     ra.stats = stats;
+    ra.basis = dict->basis;
     for (int round = 0; round <= r->max_rounds; ++round) {
         const int warm = round == 0 ? opts->warm_start : (r->cold_rounds ? 0 : 1);
         if ((st = run_fit(ctx, samples, dict, opts, beta, stats, active, warm)) != PAM_OK) return st;
@@ -545,6 +548,7 @@ pam_status pam_select_lambda(pam_ctx *ctx, const pam_samples *samples, const pam
     Dv.c = (double *)(base + o_c);
     Dv.sigma = (double *)(base + o_s);
     Dv.level = (int32_t *)(base + o_l);
+    Dv.basis = dict->basis;
     double *beta_v = (double *)(base + o_b);
     double *l1v = (double *)(base + o_l1);
     double *l2v = (double *)(base + o_l2);

@@ -127,6 +127,7 @@ struct FitArgs {
     double *beta;
     pam_fit_stats *stats;
     const int32_t *active;          // [n_sub] 1 = fit this subdomain (refinement), or NULL
+    int32_t basis;                  // PAM_BASIS_SHEPARD or PAM_BASIS_PLAIN
 };
 
 pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);
@@ -153,6 +154,7 @@ struct RefineArgs {
     int32_t *rounds;
     double *round_stats;
     pam_fit_stats *stats;
+    int32_t basis;
 };
 
 pam_status launch_indicator(pam_ctx *ctx, const RefineArgs &a);

@@ -39,7 +39,9 @@ class PamGrid(C.Structure):
 class PamDict(C.Structure):
     _fields_ = [("n_sub", C.c_int32), ("dim", C.c_int32), ("m_cap", C.c_int32),
                 ("m", C.c_void_p), ("c", C.c_void_p), ("sigma", C.c_void_p),
-                ("level", C.c_void_p)]
+                ("level", C.c_void_p), ("basis", C.c_int32)]
+
+BASIS = {"shepard": 0, "plain": 1}
 
 
 class PamSamples(C.Structure):
