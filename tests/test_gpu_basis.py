@@ -1,6 +1,7 @@
-"""GPU parity of the plain (unnormalized) basis, the ablation of Example 1
-(Sec. 3.2), through the C ABI against the FP64 oracle with the same switch:
-fits (FP64 and FP32 modes), a two-round refinement and the evaluation.
+"""GPU parity of the ablations the paper describes, through the C ABI against
+the FP64 oracle: the plain (unnormalized) basis of Example 1 (Sec. 3.2) --
+fits in FP64 and FP32 modes, a two-round refinement and the evaluation --
+and the indicator measured on K itself instead of log10 K (Alg. 1 literal).
 
 Tolerances as for the Shepard basis: FP64 coefficients 1e-9 of max|beta|,
 FP32 mode 1e-5, refinement dictionaries and levels bit-exact, FP64
@@ -91,3 +92,24 @@ def test_unknown_basis_is_rejected(ctx):
     D.basis = "other"
     with pytest.raises(api.N.PamError):
         api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64"))
+
+
+def test_linear_space_indicator_refine_matches_oracle(ctx):
+    g = synth.facies256(n=64, n_sub=4)
+    S = api.partition(ctx, g)
+    m_cap = 64 + 2 * 3 * 51
+    D = api.init_lattice(ctx, g, [8, 8], m_cap=m_cap)
+    tol = 1e-3 * (1 / 64) ** 2
+    beta, lvl, rounds, rs, st = api.refine(ctx, S, D, api.EnetOpts(L1, L2, "f64"),
+                                           api.RefineOpts(k_top=51, max_rounds=2, eps_tol=tol,
+                                                          space=1))
+    torch.cuda.synchronize()
+    od = O.init_dictionary(g, [8, 8], m_cap)
+    odr, bo, lvo, info = O.refine_batch(O.partition(g), od, L1, L2, k_top=51, max_rounds=2,
+                                        m_max=1 << 30, eps_tol=tol, space=1)
+    assert np.array_equal(_t(D.m), odr.m)
+    assert np.array_equal(_t(lvl), lvo)
+    assert np.array_equal(_t(rounds), info["rounds"])
+    err = _coef_err(_t(beta), bo, odr.m, m_cap)
+    print("linear-space indicator refine coefficient error", err, "centers", _t(D.m))
+    assert err <= 1e-9

@@ -9,7 +9,9 @@ compares the Shepard-normalized one against in Example 1 (Sec. 3.2):
   - the indicator of the plain expansion equals the Gauss-Legendre sum of
     its squared misfit computed here directly;
   - the switch does not leak: a Shepard call after a plain one gives the
-    Shepard answer again.
+    Shepard answer again;
+  - the indicator on K itself (Alg. 1 literal, the other ablation) equals
+    the Gauss-Legendre sum of the squared misfit of 10^K* against 10^y.
 """
 import itertools
 
@@ -118,3 +120,23 @@ def test_switch_does_not_leak():
     O.design(x, c, sg, basis="plain")
     w2 = O.design(x, c, sg)
     assert np.array_equal(w1, w2) and abs(w1.sum() - 1.0) <= 1e-15
+
+
+def test_linear_space_indicator_is_the_quadrature_of_the_k_misfit():
+    """Alg. 1 literal: R_T measured on K = 10^(log10 K) rather than on the
+    log values (the ablation of the indicator space)."""
+    rng = np.random.default_rng(611)
+    x = rng.random((6, 2))
+    h = np.full((6, 2), 0.2)
+    y = rng.normal(size=6)
+    c = rng.random((5, 2))
+    sg = np.full(5, 0.25)
+    beta = rng.normal(size=5)
+    R = O.indicator(x, y, h, c, sg, beta, space=1)
+    off = 0.2 / (2 * np.sqrt(3))
+    want = np.zeros(6)
+    for q in itertools.product((-1, 1), repeat=2):
+        P = _raw(x + off * np.array(q), c, sg)
+        v = (P @ beta) / P.sum(1)
+        want += 0.04 / 4 * (10.0 ** v - 10.0 ** y) ** 2
+    assert np.allclose(R, want, rtol=1e-12, atol=0)
