@@ -32,17 +32,20 @@ def test_exports_match_header(lib):
 
 
 def test_struct_sizes_match_header(tmp_path):
+    names = ["pam_grid", "pam_dict", "pam_samples", "pam_enet_opts", "pam_fit_stats",
+             "pam_refine_opts", "pam_field", "pam_select_opts", "pam_darcy_opts"]
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include "pam.h"\nint main(){printf("%zu %zu %zu %zu '
-                   '%zu %zu %zu\\n",sizeof(pam_grid),sizeof(pam_dict),sizeof(pam_samples),'
-                   'sizeof(pam_enet_opts),sizeof(pam_fit_stats),sizeof(pam_refine_opts),'
-                   'sizeof(pam_field));}\n')
+    fmt = " ".join(["%zu"] * len(names))
+    args = ",".join(f"sizeof({n})" for n in names)
+    src.write_text('#include <stdio.h>\n#include "pam.h"\nint main(){printf("' + fmt + '\\n",'
+                   + args + ');}\n')
     import subprocess
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", str(ROOT / "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(s) for s in (N.PamGrid, N.PamDict, N.PamSamples, N.PamEnetOpts,
-                                  N.PamFitStats, N.PamRefineOpts, N.PamField)]
+                                  N.PamFitStats, N.PamRefineOpts, N.PamField, N.PamSelectOpts,
+                                  N.PamDarcyOpts)]
     assert got == want
 
 
