@@ -330,6 +330,19 @@ def darcy(ctx, api, grid, D, beta, blend):
     return res
 
 
+def sub_problem(api, S, D, lo, hi):
+    """Samples and dictionary of subdomains lo..hi-1 (device slices)."""
+    import torch
+    a, b = int(S.off_host[lo]), int(S.off_host[hi])
+    off_h = S.off_host[lo:hi + 1] - a
+    n_max = int(np.diff(off_h).max()) if hi > lo else 0
+    Ss = api.Samples(S.dim, hi - lo, n_max, torch.as_tensor(off_h, device=S.x.device), off_h,
+                     S.x[a:b], S.y[a:b], S.h[a:b])
+    Ds = api.Dictionary(hi - lo, D.dim, D.m_cap, D.m[lo:hi].clone(), D.c[lo:hi].clone(),
+                        D.sigma[lo:hi].clone(), D.level[lo:hi].clone(), D.basis)
+    return Ss, Ds
+
+
 def blend_pairs(grid, m_sub, xq, blend):
     """Query-center pairs of the continuous reconstruction: per query, each
     subdomain with non-zero weight contributes its dictionary size."""
@@ -432,13 +445,20 @@ def continuity(ctx, api, grid, D, beta, xq, w_d, ycell, area, blend, reps=3):
     }
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON result goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs the hot path on one GPU; --gpus {args.gpus} is not "
               "supported (see the sharding notes in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    progress("importing torch")
     import torch
+    progress("torch imported")
     if args.copy_calibration:
         n = 1 << 28
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -483,6 +503,7 @@ def main():
         out = api.evaluate(ctx, grid, D, beta, xq)
         return S, D, beta, rounds, rs, stats, out
 
+    progress("start" if not use_learned else "learned warm start trained")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -615,17 +636,21 @@ def main():
         "roofline": roof,
     }
     rec["config"]["learned_warm_start"] = bool(use_learned)
+    progress(f"timed steps done: {value:.1f} fits/s")
     if not args.no_select:
         rec["lambda_selection"] = lambda_selection(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d,
                                                    ycell, area, args.select_alphas,
                                                    args.select_folds, args.select_ratio)
+    progress("lambda selection done")
     if not args.no_darcy:
         rec["darcy"] = darcy(ctx, api, grid, D, beta, args.blend)
+    progress("Darcy consumer done")
     if not args.no_continuity:
         rec["continuity"] = continuity(ctx, api, grid, D, beta, xq, w_d, ycell, area, args.blend)
     if use_learned:
         learned_rec["gain_first_fit"] = learned_gain(ctx, api, grid, wl, prec, params)
         rec["learned"] = learned_rec
+    progress("continuity done")
     if not args.no_ablations:
         # each pattern switched off alone (one untimed and one timed step; the
         # unbatched run is one timed step): fits/s and the ratio it costs
@@ -647,20 +672,38 @@ def main():
             abl[name] = {"value": va, "unit": "fits/s", "speedup_of_pattern": value / va,
                          "field_l1_log10": l1a}
         rec["ablations"] = abl
+    progress("ablations done")
     if not args.no_comparator:
         # plain GPU fit: one launch per subdomain and kernel, every refit from
-        # zero, no hint; same path otherwise (one step, kernels already loaded)
+        # zero, no hint; same path otherwise. The per-subdomain launches are
+        # serial, so the subdomains are run in two halves (the same work) with
+        # a progress line between them
         torch.cuda.synchronize()
         tc0 = time.perf_counter()
-        resc = step(batched=False, cold=True, hinted=False)
+        S = api.partition(ctx, grid, cell_y)
+        D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
+        o = api.EnetOpts(wl.lambda1, wl.lambda2, prec, cd_sweeps=args.cd_sweeps, batched=False)
+        ro = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta,
+                            cold_rounds=True)
+        half = D.n_sub // 2
+        parts = []
+        for lo, hi in ((0, half), (half, D.n_sub)):
+            Sh, Dh = sub_problem(api, S, D, lo, hi)
+            bh, _, rh, _, _ = api.refine(ctx, Sh, Dh, o, ro)
+            torch.cuda.synchronize()
+            parts.append((Dh, bh, rh))
+            progress(f"comparator subdomains {lo}..{hi - 1} done")
+        Dc = api.concat_dicts([p_[0] for p_ in parts])
+        bc = torch.cat([p_[1] for p_ in parts])
+        oc = api.evaluate(ctx, grid, Dc, bc, xq)
         torch.cuda.synchronize()
         tc = time.perf_counter() - tc0
-        fits_c = int(resc[3].sum().item())
-        oc = resc[6]
+        fits_c = int(sum(int(p_[2].sum().item()) for p_ in parts))
         l1c = float((w_d * (oc.double() - ycell).abs()).sum().item()) / area
         rec["comparator"] = {"kind": "plain GPU fit (per-subdomain launches, cold refits, no hint)",
                              "value": fits_c / tc, "unit": "fits/s", "field_l1_log10": l1c,
                              "speedup": value / (fits_c / tc)}
+    progress("comparator done")
     if not args.no_cpu_baseline:
         base, sample = cpu_baseline(grid, wl, args.cpu_sample_subdomains,
                                     min(args.cpu_sample_rounds, wl.max_rounds))

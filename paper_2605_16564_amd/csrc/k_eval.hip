@@ -42,12 +42,13 @@ struct EvalTables {
     int32_t n_fields;
 };
 
-template <typename TQ>
+template <typename TQ, int DIM>
 __device__ __forceinline__ int owner_of(const EvalTables &t, int f, const TQ *xq, int64_t q) {
     const FieldDev F = t.fields[f];
     int sub = 0, stride = 1, pos = F.axis_off;
-    for (int d = 0; d < F.dim; ++d) {
-        const double v = (double)xq[q * F.dim + d];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double v = (double)xq[q * DIM + d];
         const int n = F.n_sub_axis[d];
         const double *bx = t.axis + pos;
         if (!(v >= bx[0] && v <= bx[n])) return -1;
@@ -73,19 +74,26 @@ struct AxisTerm {
     double w_own, w_nb;
 };
 
+// The band tests and weights are evaluated with contraction off, so that the
+// term, scatter and combine passes take identical decisions and weights.
 __device__ __forceinline__ double ramp(double s) {
+#pragma clang fp contract(off)
     return s <= 0.0 ? 0.0 : (s >= 1.0 ? 1.0 : s * s * (3.0 - 2.0 * s));
 }
 
 // Per-axis terms of query q of field f; returns the owner subdomain (field
 // local) or -1 outside the closed domain.
-template <typename TQ>
+// DIM is the fields' dimension (one per launch), so that the per-axis state
+// stays in registers.
+template <typename TQ, int DIM>
 __device__ __forceinline__ int axis_terms(const EvalTables &t, int f, const TQ *xq, int64_t q,
                                           double blend, AxisTerm *at, int *stride_out) {
+#pragma clang fp contract(off)
     const FieldDev F = t.fields[f];
     int sub = 0, stride = 1, pos = F.axis_off;
-    for (int d = 0; d < F.dim; ++d) {
-        const double v = (double)xq[q * F.dim + d];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double v = (double)xq[q * DIM + d];
         const int n = F.n_sub_axis[d];
         const double *bx = t.axis + pos;
         if (!(v >= bx[0] && v <= bx[n])) return -1;
@@ -120,15 +128,21 @@ __device__ __forceinline__ int axis_terms(const EvalTables &t, int f, const TQ *
     return sub;
 }
 
-// Term c of a query with axis terms at: weight (0 if the term is absent) and
-// subdomain offset from the owner.
-__device__ __forceinline__ double term_weight(int dim, const AxisTerm *at, const int *stride, int c,
+// Term c of a query with axis terms at: weight and subdomain offset from the
+// owner, or -1 if the term is absent. A term exists when the query lies
+// strictly inside the band of every axis its bits select (a decision taken
+// by comparisons only, so every pass agrees on it); its weight may still
+// round to 0 at a band edge and then adds nothing.
+template <int DIM>
+__device__ __forceinline__ double term_weight(const AxisTerm *at, const int *stride, int c,
                                               int *dsub) {
+#pragma clang fp contract(off)
     double w = 1.0;
     int o = 0;
-    for (int d = 0; d < dim; ++d) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
         if ((c >> d) & 1) {
-            if (at[d].nb == 0) return 0.0;
+            if (at[d].nb == 0) return -1.0;
             w *= at[d].w_nb;
             o += at[d].nb * stride[d];
         } else {
@@ -151,7 +165,7 @@ __device__ __forceinline__ int field_of(const EvalTables &t, int64_t q) {
 // per query would serialize on a handful of counters).
 static constexpr int kBinsLds = 8192;
 
-template <typename TQ>
+template <typename TQ, int DIM>
 __global__ void __launch_bounds__(kE)
 k_owner(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, int32_t *__restrict__ owner,
         int32_t *__restrict__ hist, TQ *__restrict__ out, unsigned long long *__restrict__ n_out) {
@@ -164,7 +178,7 @@ k_owner(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, int32_t *
         int f = 0;
         while (f + 1 < t.n_fields && q >= t.fields[f].q_end) ++f;
         int o = -1;
-        if (q >= t.fields[f].q_begin && q < t.fields[f].q_end) o = owner_of(t, f, xq, q);
+        if (q >= t.fields[f].q_begin && q < t.fields[f].q_end) o = owner_of<TQ, DIM>(t, f, xq, q);
         owner[q] = o;
         if (o >= 0) {
             if (local) atomicAdd(&lh[o], 1);
@@ -262,7 +276,7 @@ k_scatter(int64_t Q, int n_sub, const int32_t *__restrict__ owner, const int64_t
 
 // Continuous variant, pass 1: terms of every query and the per-subdomain
 // term counts (LDS histogram as in k_owner). Outside points get NaN.
-template <typename TQ>
+template <typename TQ, int DIM>
 __global__ void __launch_bounds__(kE)
 k_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, double blend,
         int32_t *__restrict__ hist, TQ *__restrict__ out, unsigned long long *__restrict__ n_out) {
@@ -273,21 +287,21 @@ k_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, double bl
     __syncthreads();
     for (int64_t q = (int64_t)blockIdx.x * kE + threadIdx.x; q < Q; q += (int64_t)gridDim.x * kE) {
         const int f = field_of(t, q);
-        const int dim = t.fields[f].dim;
-        AxisTerm at[3];
-        int stride[3];
+        AxisTerm at[DIM];
+        int stride[DIM];
         int o = -1;
         if (q >= t.fields[f].q_begin && q < t.fields[f].q_end)
-            o = axis_terms(t, f, xq, q, blend, at, stride);
+            o = axis_terms<TQ, DIM>(t, f, xq, q, blend, at, stride);
         if (o < 0) {
             out[q] = (TQ)NAN;
             if (n_out) atomicAdd(n_out, 1ull);
             continue;
         }
         o += t.fields[f].sub_base;
-        for (int c = 0; c < (1 << dim); ++c) {
+#pragma unroll
+        for (int c = 0; c < (1 << DIM); ++c) {
             int ds = 0;
-            if (term_weight(dim, at, stride, c, &ds) > 0.0) {
+            if (term_weight<DIM>(at, stride, c, &ds) >= 0.0) {
                 if (local) atomicAdd(&lh[o + ds], 1);
                 else atomicAdd(&hist[o + ds], 1);
             }
@@ -300,12 +314,39 @@ k_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, double bl
 }
 
 // Continuous variant, pass 2: binned positions of the terms (term id
-// q * 2^dim + c), ranked in LDS per block like k_scatter. The terms are
-// recomputed from the query, bit-identically to pass 1.
-static constexpr int kTermPer = 2;                 // queries per thread
+// q * 2^dim + c). A block takes kTermBlk consecutive queries in two sweeps
+// that recompute the terms bit-identically to pass 1: the first counts them
+// per bin in LDS and reserves one range per touched bin with a global
+// atomic, the second ranks them inside the block's range and writes the
+// permutation (the order inside a bin does not matter: every term has its
+// own slot).
+static constexpr int kTermPer = 8;                 // queries per thread
 static constexpr int kTermBlk = kE * kTermPer;     // queries per block
 
-template <typename TQ>
+template <typename TQ, int DIM>
+__device__ __forceinline__ int query_terms(const EvalTables &t, const TQ *xq, int64_t Q, double blend,
+                                           int64_t q, int *sub) {
+    if (q >= Q) return 0;
+    const int f = field_of(t, q);
+    if (q < t.fields[f].q_begin || q >= t.fields[f].q_end) return 0;
+    AxisTerm at[DIM];
+    int stride[DIM];
+    const int o = axis_terms<TQ, DIM>(t, f, xq, q, blend, at, stride);
+    if (o < 0) return 0;
+    int mask = 0;
+#pragma unroll
+    for (int c = 0; c < (1 << DIM); ++c) {
+        int ds = 0;
+        sub[c] = 0;
+        if (term_weight<DIM>(at, stride, c, &ds) >= 0.0) {
+            sub[c] = t.fields[f].sub_base + o + ds;
+            mask |= 1 << c;
+        }
+    }
+    return mask;
+}
+
+template <typename TQ, int DIM>
 __global__ void __launch_bounds__(kE)
 k_scatter_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, double blend,
                 const int64_t *__restrict__ base, int32_t *__restrict__ cursor,
@@ -314,68 +355,66 @@ k_scatter_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, d
     __shared__ int32_t lbase[kBinsLds];
     const bool local = n_sub <= kBinsLds;
     const int64_t q0 = (int64_t)blockIdx.x * kTermBlk;
-    if (local) {
-        for (int b = threadIdx.x; b < n_sub; b += kE) lcount[b] = 0;
-        __syncthreads();
-    }
-    int ow[kTermPer][8], rk[kTermPer][8];
+    if (!local) {
+        for (int e = 0; e < kTermPer; ++e) {
+            const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
+            int sub[1 << DIM];
+            const int mask = query_terms<TQ, DIM>(t, xq, Q, blend, q, sub);
 #pragma unroll
-    for (int e = 0; e < kTermPer; ++e) {
-        const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) { ow[e][c] = -1; rk[e][c] = 0; }
-        if (q >= Q) continue;
-        const int f = field_of(t, q);
-        if (q < t.fields[f].q_begin || q >= t.fields[f].q_end) continue;
-        const int dim = t.fields[f].dim;
-        AxisTerm at[3];
-        int stride[3];
-        const int o = axis_terms(t, f, xq, q, blend, at, stride);
-        if (o < 0) continue;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            int ds = 0;
-            if (c < (1 << dim) && term_weight(dim, at, stride, c, &ds) > 0.0) {
-                ow[e][c] = t.fields[f].sub_base + o + ds;
-                if (local) rk[e][c] = atomicAdd(&lcount[ow[e][c]], 1);
-                else perm[base[ow[e][c]] + atomicAdd(&cursor[ow[e][c]], 1)] = (q << dim) | c;
-            }
+            for (int c = 0; c < (1 << DIM); ++c)
+                if ((mask >> c) & 1)
+                    perm[base[sub[c]] + atomicAdd(&cursor[sub[c]], 1)] = (q << DIM) | c;
         }
+        return;
     }
-    if (!local) return;
+    for (int b = threadIdx.x; b < n_sub; b += kE) lcount[b] = 0;
     __syncthreads();
-    for (int b = threadIdx.x; b < n_sub; b += kE)
-        if (lcount[b]) lbase[b] = atomicAdd(&cursor[b], lcount[b]);
-    __syncthreads();
-#pragma unroll
     for (int e = 0; e < kTermPer; ++e) {
         const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
-        if (q >= Q) continue;
-        const int dim = t.fields[field_of(t, q)].dim;
+        int sub[1 << DIM];
+        const int mask = query_terms<TQ, DIM>(t, xq, Q, blend, q, sub);
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (ow[e][c] >= 0) perm[base[ow[e][c]] + lbase[ow[e][c]] + rk[e][c]] = (q << dim) | c;
+        for (int c = 0; c < (1 << DIM); ++c)
+            if ((mask >> c) & 1) atomicAdd(&lcount[sub[c]], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < n_sub; b += kE) {
+        const int n = lcount[b];
+        lbase[b] = n ? atomicAdd(&cursor[b], n) : 0;
+        lcount[b] = 0;
+    }
+    __syncthreads();
+    for (int e = 0; e < kTermPer; ++e) {
+        const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
+        int sub[1 << DIM];
+        const int mask = query_terms<TQ, DIM>(t, xq, Q, blend, q, sub);
+#pragma unroll
+        for (int c = 0; c < (1 << DIM); ++c)
+            if ((mask >> c) & 1) {
+                const int r = atomicAdd(&lcount[sub[c]], 1);
+                perm[base[sub[c]] + lbase[sub[c]] + r] = (q << DIM) | c;
+            }
     }
 }
 
 // Continuous variant, pass 4: out[q] = sum_c w_c K*_{sub(c)}(x_q) over the
 // present terms in c order (FP64 weights and sum), then 10^ if asked.
-template <typename TQ>
+template <typename TQ, int DIM>
 __global__ void __launch_bounds__(kE)
 k_combine(EvalTables t, const TQ *__restrict__ xq, int64_t Q, double blend,
           const TQ *__restrict__ tval, TQ *__restrict__ out, int space) {
     for (int64_t q = (int64_t)blockIdx.x * kE + threadIdx.x; q < Q; q += (int64_t)gridDim.x * kE) {
         const int f = field_of(t, q);
         if (q < t.fields[f].q_begin || q >= t.fields[f].q_end) continue;
-        const int dim = t.fields[f].dim;
-        AxisTerm at[3];
-        int stride[3];
-        if (axis_terms(t, f, xq, q, blend, at, stride) < 0) continue;
+        AxisTerm at[DIM];
+        int stride[DIM];
+        if (axis_terms<TQ, DIM>(t, f, xq, q, blend, at, stride) < 0) continue;
         double acc = 0.0;
-        for (int c = 0; c < (1 << dim); ++c) {
+#pragma unroll
+        for (int c = 0; c < (1 << DIM); ++c) {
             int ds = 0;
-            const double w = term_weight(dim, at, stride, c, &ds);
-            if (w > 0.0) acc += w * (double)tval[(q << dim) | c];
+            const double w = term_weight<DIM>(at, stride, c, &ds);
+            if (w >= 0.0) acc += w * (double)tval[(q << DIM) | c];
         }
         TQ v = (TQ)acc;
         if (space == 1) {
@@ -569,27 +608,34 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
     TQ *tval = (TQ *)(w + o_tval);
     auto *n_out = (unsigned long long *)n_outside;
     // owner / term pass: a few thousand resident blocks, each flushing one histogram
-    const int grid_o = (int)std::max<int64_t>(1, std::min<int64_t>((Q + kE - 1) / kE, 2048));
+    // owner / term histograms: every block flushes one global atomic per
+    // touched bin, so the grid is kept at 2 blocks per CU to bound the
+    // contention on the few bins that spatially coherent queries touch
+    const int grid_o = (int)std::max<int64_t>(1, std::min<int64_t>((Q + kE - 1) / kE, 512));
     {
         KernelTimer kt_bin(ctx, PAM_TK_EVAL_BIN);
         if (Q > 0) {
-            if (blended)
-                hipLaunchKernelGGL((k_terms<TQ>), dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q,
-                                   n_sub_total, blend, hist, out, n_out);
-            else
-                hipLaunchKernelGGL((k_owner<TQ>), dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q,
-                                   n_sub_total, owner, hist, out, n_out);
+            if (blended) {
+                auto kt = dim_max == 1 ? k_terms<TQ, 1> : dim_max == 2 ? k_terms<TQ, 2> : k_terms<TQ, 3>;
+                hipLaunchKernelGGL(kt, dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q, n_sub_total,
+                                   blend, hist, out, n_out);
+            } else {
+                auto ko = dim_max == 1 ? k_owner<TQ, 1> : dim_max == 2 ? k_owner<TQ, 2> : k_owner<TQ, 3>;
+                hipLaunchKernelGGL(ko, dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q, n_sub_total,
+                                   owner, hist, out, n_out);
+            }
             PAM_CHECK_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, ctx->stream, n_sub_total, hist, base,
                            cbase, cursor, nch);
         PAM_CHECK_HIP(hipGetLastError());
         if (Q > 0) {
-            if (blended)
-                hipLaunchKernelGGL((k_scatter_terms<TQ>),
-                                   dim3((unsigned)((Q + kTermBlk - 1) / kTermBlk)), dim3(kE), 0,
+            if (blended) {
+                auto ks = dim_max == 1 ? k_scatter_terms<TQ, 1>
+                        : dim_max == 2 ? k_scatter_terms<TQ, 2> : k_scatter_terms<TQ, 3>;
+                hipLaunchKernelGGL(ks, dim3((unsigned)((Q + kTermBlk - 1) / kTermBlk)), dim3(kE), 0,
                                    ctx->stream, t, xq, Q, n_sub_total, blend, base, cursor, perm);
-            else
+            } else
                 hipLaunchKernelGGL(k_scatter, dim3((unsigned)((Q + kScatter - 1) / kScatter)),
                                    dim3(kE), 0, ctx->stream, Q, n_sub_total, owner, base, cursor,
                                    perm);
@@ -617,7 +663,8 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
     if (blended) {
         // the weighted sum is bookkeeping like the binning: timed with it
         KernelTimer kt_comb(ctx, PAM_TK_EVAL_BIN);
-        hipLaunchKernelGGL((k_combine<TQ>), dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q, blend,
+        auto kc = dim_max == 1 ? k_combine<TQ, 1> : dim_max == 2 ? k_combine<TQ, 2> : k_combine<TQ, 3>;
+        hipLaunchKernelGGL(kc, dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q, blend,
                            (const TQ *)tval, out, space);
         PAM_CHECK_HIP(hipGetLastError());
     }
