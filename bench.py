@@ -97,6 +97,8 @@ def parse():
                     help="path length (half-decade steps down to 1e-6 alpha_max by default)")
     ap.add_argument("--select-ratio", type=float, default=1e-6)
     ap.add_argument("--select-folds", type=int, default=5)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (circle64 replicas, layered3d, multifield)")
     ap.add_argument("--no-darcy", action="store_true",
                     help="skip the Darcy consumer (pressure error of the reconstruction)")
     ap.add_argument("--blend", type=float, default=0.1,
@@ -341,6 +343,80 @@ def sub_problem(api, S, D, lo, hi):
     Ds = api.Dictionary(hi - lo, D.dim, D.m_cap, D.m[lo:hi].clone(), D.c[lo:hi].clone(),
                         D.sigma[lo:hi].clone(), D.level[lo:hi].clone(), D.basis)
     return Ss, Ds
+
+
+def other_configs(ctx, api, synth, progress):
+    """The other configurations as single timed runs (wall clock around
+    synchronized calls, kernel split from HIP events): circle64 as 1,024
+    replicas (4,096 FP64 fits), layered3d (1,188 subdomains, BF16 Gram + FP64
+    pass, three enrichment rounds), multifield (5,820 FP32 fits, then 6.4e7
+    FP32 query evaluations)."""
+    import torch
+    L1, L2 = synth.LAMBDA1, synth.LAMBDA2
+    out = {}
+
+    def timed(fn):
+        fn()                                   # untimed: kernels loaded, workspace sized
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        ctx.timing_read(reset=True)
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tk = ctx.timing_read(reset=True)
+        ctx.timing(False)
+        return r, dt, {k: v[0] for k, v in tk.items() if v[1] > 0}
+
+    g = synth.circle64()
+    S1 = api.partition(ctx, g)
+    D1 = api.init_lattice(ctx, g, [16, 16], 256)
+    reps = 1024
+    S, D = api.concat_samples([S1] * reps), api.concat_dicts([D1] * reps)
+    (beta, st), dt, tk = timed(lambda: api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64")))
+    stn = api.stats_to_numpy(st)
+    out["circle64_x1024"] = {"fits": D.n_sub, "s": dt, "fits_per_s": D.n_sub / dt, "dtype": "f64",
+                             "status_ok": bool(np.all(stn["status"] == 0)),
+                             "kkt_max": float(stn["kkt"].max()), "kernel_ms": tk}
+    progress("circle64 replicas done")
+
+    g3 = synth.layered3d()
+    S3 = api.partition(ctx, g3)
+    ktop = np.floor(0.05 * np.diff(S3.off_host)).astype(np.int32)
+    m_cap = 512 + 3 * int(ktop.max()) * 7
+
+    def run3():
+        D3 = api.init_lattice(ctx, g3, [8, 8, 8], m_cap)
+        r = api.refine(ctx, S3, D3, api.EnetOpts(L1, L2, "bf16"),
+                       api.RefineOpts(k_top=0, k_top_sub=ktop, max_rounds=3, eps_tol=1e-4))
+        return D3, r
+    (D3, (b3, lvl3, rounds3, rs3, st3)), dt, tk = timed(run3)
+    stn = api.stats_to_numpy(st3)
+    fits = int(rounds3.sum().item())
+    out["layered3d"] = {"subdomains": D3.n_sub, "fits": fits, "s": dt, "fits_per_s": fits / dt,
+                        "dtype": "bf16", "centers_final_mean": float(D3.m.double().mean().item()),
+                        "status_ok": bool(np.all(stn["status"] == 0)),
+                        "kkt_max": float(stn["kkt"].max()), "kernel_ms": tk}
+    progress("layered3d done")
+
+    grids = synth.multifield()
+    parts = [api.partition(ctx, gg) for gg in grids]
+    dicts = [api.init_lattice(ctx, gg, [16, 16], 256) for gg in grids]
+    S5, D5 = api.concat_samples(parts), api.concat_dicts(dicts)
+    (b5, st5), dt, tk = timed(lambda: api.fit(ctx, S5, D5, api.EnetOpts(L1, L2, "f32")))
+    stn = api.stats_to_numpy(st5)
+    Q = 1_000_000
+    xs = np.concatenate([synth.uniform_queries(2, Q, seed=5100 + f) for f in range(len(grids))])
+    xq = torch.as_tensor(xs, device="cuda")
+    o5, dte, tke = timed(lambda: api.evaluate(ctx, grids, D5, b5, xq, q_counts=[Q] * len(grids)))
+    out["multifield"] = {"fields": len(grids), "subdomains": D5.n_sub, "fit_s": dt,
+                         "fits_per_s": D5.n_sub / dt, "queries": Q * len(grids), "eval_s": dte,
+                         "query_evals_per_s": Q * len(grids) / dte, "dtype": "f32",
+                         "status_ok": bool(np.all(stn["status"] == 0)),
+                         "kkt_max": float(stn["kkt"].max()), "fit_kernel_ms": tk,
+                         "eval_kernel_ms": tke}
+    progress("multifield done")
+    return out
 
 
 def blend_pairs(grid, m_sub, xq, blend):
@@ -642,6 +718,8 @@ def main():
                                                    ycell, area, args.select_alphas,
                                                    args.select_folds, args.select_ratio)
     progress("lambda selection done")
+    if not args.no_configs:
+        rec["other_configs"] = other_configs(ctx, api, synth, progress)
     if not args.no_darcy:
         rec["darcy"] = darcy(ctx, api, grid, D, beta, args.blend)
     progress("Darcy consumer done")

@@ -40,7 +40,24 @@ struct EvalTables {
     const FieldDev *fields;
     const double *axis;
     int32_t n_fields;
+    int32_t n_axis;     // entries of the axis table
 };
+
+// The field and breakpoint tables in LDS when they fit: the owner search
+// reads them once per axis and query, a chain of dependent loads.
+static constexpr int kFieldsLds = 128;
+static constexpr int kAxisLds = 4096;
+
+__device__ __forceinline__ EvalTables stage_tables(const EvalTables &t, FieldDev *lf, double *la) {
+    if (t.n_fields > kFieldsLds || t.n_axis > kAxisLds) return t;
+    for (int i = threadIdx.x; i < t.n_fields; i += blockDim.x) lf[i] = t.fields[i];
+    for (int i = threadIdx.x; i < t.n_axis; i += blockDim.x) la[i] = t.axis[i];
+    __syncthreads();
+    EvalTables l = t;
+    l.fields = lf;
+    l.axis = la;
+    return l;
+}
 
 template <typename TQ, int DIM>
 __device__ __forceinline__ int owner_of(const EvalTables &t, int f, const TQ *xq, int64_t q) {
@@ -153,10 +170,16 @@ __device__ __forceinline__ double term_weight(const AxisTerm *at, const int *str
     return w;
 }
 
+// Field of query q: the first f with q < q_end(f) (ranges tile [0, Q) in
+// order), by binary search, clamped to the last field.
 __device__ __forceinline__ int field_of(const EvalTables &t, int64_t q) {
-    int f = 0;
-    while (f + 1 < t.n_fields && q >= t.fields[f].q_end) ++f;
-    return f;
+    int lo = 0, hi = t.n_fields - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (q < t.fields[mid].q_end) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
 }
 
 // Owner of every query and the per-subdomain query counts. Counts go to an
@@ -167,16 +190,18 @@ static constexpr int kBinsLds = 8192;
 
 template <typename TQ, int DIM>
 __global__ void __launch_bounds__(kE)
-k_owner(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, int32_t *__restrict__ owner,
+k_owner(EvalTables tg, const TQ *__restrict__ xq, int64_t Q, int n_sub, int32_t *__restrict__ owner,
         int32_t *__restrict__ hist, TQ *__restrict__ out, unsigned long long *__restrict__ n_out) {
     __shared__ int32_t lh[kBinsLds];
+    __shared__ FieldDev lf[kFieldsLds];
+    __shared__ double la[kAxisLds];
+    const EvalTables t = stage_tables(tg, lf, la);
     const bool local = n_sub <= kBinsLds;
     if (local)
         for (int b = threadIdx.x; b < n_sub; b += kE) lh[b] = 0;
     __syncthreads();
     for (int64_t q = (int64_t)blockIdx.x * kE + threadIdx.x; q < Q; q += (int64_t)gridDim.x * kE) {
-        int f = 0;
-        while (f + 1 < t.n_fields && q >= t.fields[f].q_end) ++f;
+        const int f = field_of(t, q);
         int o = -1;
         if (q >= t.fields[f].q_begin && q < t.fields[f].q_end) o = owner_of<TQ, DIM>(t, f, xq, q);
         owner[q] = o;
@@ -232,45 +257,43 @@ k_scan(int n_sub, const int32_t *__restrict__ hist, int64_t *__restrict__ base,
     if (threadIdx.x == 0) *n_chunks = carry_c;
 }
 
-// Binned positions: each block takes kScatter consecutive queries, ranks
-// them inside their bins in LDS, reserves one range per touched bin with a
-// global atomic, and writes the permutation.
-static constexpr int kScatterPer = 16;
-static constexpr int kScatter = kE * kScatterPer;
-
+// Binned positions: each block takes `per` consecutive queries per thread
+// in two sweeps over owner[]: the first counts them per bin in LDS and
+// reserves one range per touched bin with a global atomic, the second ranks
+// them inside the block's range and writes the permutation. `per` grows with
+// the number of bins so that clearing and flushing the LDS bins stays a small
+// part of a block's work.
 __global__ void __launch_bounds__(kE)
-k_scatter(int64_t Q, int n_sub, const int32_t *__restrict__ owner, const int64_t *__restrict__ base,
-          int32_t *__restrict__ cursor, int64_t *__restrict__ perm) {
+k_scatter(int64_t Q, int n_sub, int per, const int32_t *__restrict__ owner,
+          const int64_t *__restrict__ base, int32_t *__restrict__ cursor,
+          int64_t *__restrict__ perm) {
     __shared__ int32_t lcount[kBinsLds];
     __shared__ int32_t lbase[kBinsLds];
-    const int64_t q0 = (int64_t)blockIdx.x * kScatter;
+    const int64_t q0 = (int64_t)blockIdx.x * kE * per;
+    const int64_t q1 = min(Q, q0 + (int64_t)kE * per);
     if (n_sub > kBinsLds) {
-        for (int e = 0; e < kScatterPer; ++e) {
-            const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
-            if (q >= Q) break;
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += kE) {
             const int o = owner[q];
-            if (o < 0) continue;
-            perm[base[o] + atomicAdd(&cursor[o], 1)] = q;
+            if (o >= 0) perm[base[o] + atomicAdd(&cursor[o], 1)] = q;
         }
         return;
     }
     for (int b = threadIdx.x; b < n_sub; b += kE) lcount[b] = 0;
     __syncthreads();
-    int ow[kScatterPer], rk[kScatterPer];
-#pragma unroll
-    for (int e = 0; e < kScatterPer; ++e) {
-        const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
-        ow[e] = q < Q ? owner[q] : -1;
-        rk[e] = ow[e] >= 0 ? atomicAdd(&lcount[ow[e]], 1) : 0;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kE) {
+        const int o = owner[q];
+        if (o >= 0) atomicAdd(&lcount[o], 1);
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < n_sub; b += kE)
-        if (lcount[b]) lbase[b] = atomicAdd(&cursor[b], lcount[b]);
+    for (int b = threadIdx.x; b < n_sub; b += kE) {
+        const int n = lcount[b];
+        lbase[b] = n ? atomicAdd(&cursor[b], n) : 0;
+        lcount[b] = 0;
+    }
     __syncthreads();
-#pragma unroll
-    for (int e = 0; e < kScatterPer; ++e) {
-        const int64_t q = q0 + (int64_t)e * kE + threadIdx.x;
-        if (ow[e] >= 0) perm[base[ow[e]] + lbase[ow[e]] + rk[e]] = q;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kE) {
+        const int o = owner[q];
+        if (o >= 0) perm[base[o] + lbase[o] + atomicAdd(&lcount[o], 1)] = q;
     }
 }
 
@@ -278,9 +301,12 @@ k_scatter(int64_t Q, int n_sub, const int32_t *__restrict__ owner, const int64_t
 // term counts (LDS histogram as in k_owner). Outside points get NaN.
 template <typename TQ, int DIM>
 __global__ void __launch_bounds__(kE)
-k_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, double blend,
+k_terms(EvalTables tg, const TQ *__restrict__ xq, int64_t Q, int n_sub, double blend,
         int32_t *__restrict__ hist, TQ *__restrict__ out, unsigned long long *__restrict__ n_out) {
     __shared__ int32_t lh[kBinsLds];
+    __shared__ FieldDev lf[kFieldsLds];
+    __shared__ double la[kAxisLds];
+    const EvalTables t = stage_tables(tg, lf, la);
     const bool local = n_sub <= kBinsLds;
     if (local)
         for (int b = threadIdx.x; b < n_sub; b += kE) lh[b] = 0;
@@ -401,8 +427,11 @@ k_scatter_terms(EvalTables t, const TQ *__restrict__ xq, int64_t Q, int n_sub, d
 // present terms in c order (FP64 weights and sum), then 10^ if asked.
 template <typename TQ, int DIM>
 __global__ void __launch_bounds__(kE)
-k_combine(EvalTables t, const TQ *__restrict__ xq, int64_t Q, double blend,
+k_combine(EvalTables tg, const TQ *__restrict__ xq, int64_t Q, double blend,
           const TQ *__restrict__ tval, TQ *__restrict__ out, int space) {
+    __shared__ FieldDev lf[kFieldsLds];
+    __shared__ double la[kAxisLds];
+    const EvalTables t = stage_tables(tg, lf, la);
     for (int64_t q = (int64_t)blockIdx.x * kE + threadIdx.x; q < Q; q += (int64_t)gridDim.x * kE) {
         const int f = field_of(t, q);
         if (q < t.fields[f].q_begin || q >= t.fields[f].q_end) continue;
@@ -595,6 +624,7 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
     t.fields = (const FieldDev *)(w + o_fields);
     t.axis = (const double *)(w + o_axis);
     t.n_fields = n_fields;
+    t.n_axis = (int32_t)axis.size();
     int32_t *owner = (int32_t *)(w + o_owner);
     int32_t *hist = (int32_t *)(w + o_hist);
     int64_t *base = (int64_t *)(w + o_base);
@@ -635,10 +665,12 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
                         : dim_max == 2 ? k_scatter_terms<TQ, 2> : k_scatter_terms<TQ, 3>;
                 hipLaunchKernelGGL(ks, dim3((unsigned)((Q + kTermBlk - 1) / kTermBlk)), dim3(kE), 0,
                                    ctx->stream, t, xq, Q, n_sub_total, blend, base, cursor, perm);
-            } else
-                hipLaunchKernelGGL(k_scatter, dim3((unsigned)((Q + kScatter - 1) / kScatter)),
-                                   dim3(kE), 0, ctx->stream, Q, n_sub_total, owner, base, cursor,
-                                   perm);
+            } else {
+                const int per = std::min(256, std::max(16, (4 * n_sub_total + kE - 1) / kE));
+                const int64_t span = (int64_t)kE * per;
+                hipLaunchKernelGGL(k_scatter, dim3((unsigned)((Q + span - 1) / span)), dim3(kE), 0,
+                                   ctx->stream, Q, n_sub_total, per, owner, base, cursor, perm);
+            }
             PAM_CHECK_HIP(hipGetLastError());
         }
         hipLaunchKernelGGL(k_chunks, dim3((n_sub_total + kE - 1) / kE), dim3(kE), 0, ctx->stream,
