@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--train-mosaics", type=int, default=12,
                     help="training fields: mosaics of 8x8 facies256 fields (16384 patches each)")
     ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-paper-ablations", action="store_true",
+                    help="skip the uniform-lattice sweep and the indicator-on-K run")
     ap.add_argument("--no-ablations", action="store_true",
                     help="skip the one-pattern-off runs (batching, precision, learned)")
     ap.add_argument("--no-continuity", action="store_true",
@@ -416,6 +418,47 @@ def other_configs(ctx, api, synth, progress):
                          "kkt_max": float(stn["kkt"].max()), "fit_kernel_ms": tk,
                          "eval_kernel_ms": tke}
     progress("multifield done")
+    return out
+
+
+def paper_ablations(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d, ycell, area, progress):
+    """The comparisons the paper makes with the method's own parts: uniform
+    lattices of growing size without refinement (Table 1, Example 2) against
+    the adaptive result, and the refinement indicator measured on K itself
+    (Alg. 1 literal) instead of log10 K."""
+    import torch
+    cell_y = torch.as_tensor(grid.y, dtype=torch.float64, device="cuda")
+    S = api.partition(ctx, grid, cell_y)
+
+    def l1_of(D, beta):
+        f = api.evaluate(ctx, grid, D, beta, xq)
+        return float((w_d * (f.double() - ycell).abs()).sum().item()) / area
+
+    out = {"uniform_lattice": []}
+    for g in (6, 12, 24, 44):
+        D = api.init_lattice(ctx, grid, [g] * grid.dim, g ** grid.dim, wl.sigma_factor)
+        o = api.EnetOpts(wl.lambda1, wl.lambda2, prec)
+        api.fit(ctx, S, D, o)                  # untimed: workspace sized
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        beta, st = api.fit(ctx, S, D, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["uniform_lattice"].append({"g": g, "centers": g ** grid.dim, "fits_per_s": D.n_sub / dt,
+                                       "field_l1_log10": l1_of(D, beta),
+                                       "status_ok": bool(np.all(api.stats_to_numpy(st)["status"] == 0))})
+    progress("uniform lattices done")
+    D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
+    ro = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta, space=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    beta, lvl, rounds, rs, st = api.refine(ctx, S, D, api.EnetOpts(wl.lambda1, wl.lambda2, prec), ro)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["indicator_on_k"] = {"fits": int(rounds.sum().item()), "fits_per_s": int(rounds.sum().item()) / dt,
+                             "centers_final_mean": float(D.m.double().mean().item()),
+                             "field_l1_log10": l1_of(D, beta)}
+    progress("indicator on K done")
     return out
 
 
@@ -751,6 +794,9 @@ def main():
                          "field_l1_log10": l1a}
         rec["ablations"] = abl
     progress("ablations done")
+    if not args.no_ablations and not args.no_paper_ablations and grid.dim == 2:
+        rec["paper_ablations"] = paper_ablations(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d, ycell,
+                                                 area, progress)
     if not args.no_comparator:
         # plain GPU fit: one launch per subdomain and kernel, every refit from
         # zero, no hint; same path otherwise. The per-subdomain launches are
