@@ -554,17 +554,22 @@ struct CnnWs {
 static constexpr int kPack16 = 2 * 32 * 32 * kTaps;   // BF16 elements per pack
 
 static constexpr int kWgradPer = 8;     // patches per weight-gradient block (vector ALU kernels)
+static constexpr int kWgradPerThin = 2; // the same for the thin first and last layers: their
+                                        // blocks are small (128 / 256 threads), so more of them
 static constexpr int kWgradPer16 = 4;   // patches per block of the MFMA weight gradient
 
 static size_t cnn_ws_floats(int B, bool train) {
     const size_t A = (size_t)B * 32 * kPix;
     size_t n = 2 * (size_t)kParams + 3 * A + (size_t)B * 2 * kPix + kPack16;   // two BF16 packs = kPack16 floats
     if (train) {
+        // partial gradient rows of the largest layer: thin layers 16 (first) or
+        // 8 (last) rows per block, the 32 -> 32 layers one per block
         const size_t nblk = (B + kWgradPer - 1) / kWgradPer;
-        // partial rows: at most 16 per block (layer 1), each of the largest layer size
+        const size_t nthin = (B + kWgradPerThin - 1) / kWgradPerThin;
         const size_t nblk16 = (B + kWgradPer16 - 1) / kWgradPer16;
-        n += 2 * A + (size_t)B * 2 * kPix + 2 * kBceBlocks +
-             std::max(nblk * 16, nblk16) * (size_t)layer_size(1);
+        const size_t part = std::max({nthin * 16 * (size_t)layer_size(0), nthin * 8 * (size_t)layer_size(3),
+                                      std::max(nblk, nblk16) * (size_t)layer_size(1)});
+        n += 2 * A + (size_t)B * 2 * kPix + 2 * kBceBlocks + part;
     }
     return n;
 }
@@ -701,19 +706,20 @@ pam_status pam_cnn_loss_grad(pam_ctx *ctx, const float *params, int32_t B, const
     hipLaunchKernelGGL(k_bce_scale, dim3(kBceBlocks), dim3(256), 0, ctx->stream, w.bpart, kBceBlocks, w.gz, nz,
                        loss);
     const int nblk = (B + kWgradPer - 1) / kWgradPer;
+    const int nthin = (B + kWgradPerThin - 1) / kWgradPerThin;
     const float *act_in[4] = {x, w.a[0], w.a[1], w.a[2]};
     const float *gout = w.gz;
     for (int l = 3; l >= 0; --l) {
         const int nw = layer_size(l);
         int n_part = nblk;
         if (l == 3) {
-            hipLaunchKernelGGL((k_wgrad<32, 2, 2, 8>), dim3(nblk), dim3(256), 0, ctx->stream, act_in[l], gout, B,
-                               kWgradPer, w.part);
-            n_part = nblk * 8;
+            hipLaunchKernelGGL((k_wgrad<32, 2, 2, 8>), dim3(nthin), dim3(256), 0, ctx->stream, act_in[l], gout, B,
+                               kWgradPerThin, w.part);
+            n_part = nthin * 8;
         } else if (l == 0) {
-            hipLaunchKernelGGL((k_wgrad<1, 32, 4, 16>), dim3(nblk), dim3(128), 0, ctx->stream, act_in[l], gout, B,
-                               kWgradPer, w.part);
-            n_part = nblk * 16;
+            hipLaunchKernelGGL((k_wgrad<1, 32, 4, 16>), dim3(nthin), dim3(128), 0, ctx->stream, act_in[l], gout, B,
+                               kWgradPerThin, w.part);
+            n_part = nthin * 16;
         } else if (bf16) {
             n_part = (B + kWgradPer16 - 1) / kWgradPer16;
             hipLaunchKernelGGL(k_wgrad32_mfma, dim3(n_part), dim3(256), 0, ctx->stream, act_in[l], gout, B,
