@@ -40,11 +40,12 @@ static constexpr int kIncMax = 48;     // incremental solution updates between f
 
 __host__ __device__ size_t solve_ldh(int m_cap) { return (size_t)round_up(m_cap, kPass); }
 __host__ __device__ size_t solve_h_elems(int m_cap) { return (size_t)(m_cap + 1) * solve_ldh(m_cap); }
-__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad) {
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision) {
     // blocked-bordering rows [3][kQ][m_cap], then for the FP64 phase of the
-    // low-precision modes: -1/(2 sigma^2) [m_cap], three CG vectors [3][m_cap]
-    // and two per-sample vectors [2][npad]
-    return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad;
+    // low-precision modes: -1/(2 sigma^2) [m_cap], three CG vectors [3][m_cap],
+    // two per-sample vectors [2][npad] and the FP64 design W64 [m_cap][npad]
+    const size_t w64 = precision == PAM_PREC_F64 ? 0 : (size_t)m_cap * npad;
+    return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad + w64;
 }
 size_t solve_lds_bytes(int m_cap) { return (size_t)57 * round_up(m_cap, 8) + 64; }   // 57 B per center: see the carve-out in k_solve
 
@@ -729,6 +730,8 @@ struct Pol {
     double *u;            // [N] per-sample vector
     double *is;           // [N] 1 / s_j (1 for the plain basis)
     int plain;            // unnormalized basis: W64 = Phi
+    double *W;            // [M][npad] the FP64 design W64, built once per FP64 phase
+    int ldw;              // npad
 };
 
 // Per-sample pass: for samples j (two per thread at a time, for independent
@@ -802,28 +805,122 @@ __device__ __forceinline__ void center_pass(const Pol &P, int n, K key, F out) {
     __syncthreads();
 }
 
-// s_j over all centers, the residual e_j = y_j - (W64 beta)_j and
-// u_j = e_j / s_j; then g_m = (W64' e)_m - lambda2 beta_m for every m < M.
+// The FP64 design W64[m][j] = phi_{j,m} / s_j (phi itself for the plain
+// basis) for all m < M, j < N: one exponential per entry, built once when the
+// FP64 phase starts; every later product streams it.
 template <typename TG>
-__device__ __forceinline__ void grad64(Sv<TG> &v, const Pol &P) {
-    sample_pass(P, v.M, [](int i) { return i; }, v.beta, [&](int j, double sj, double num) {
+__device__ __forceinline__ void build_w64(Sv<TG> &v, const Pol &P) {
+    v.bytes += (P.plain ? 8.0 : 24.0) * (double)v.M * (double)P.N;
+    for (int j = threadIdx.x; j < P.N; j += kT) {
+        double xj[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) xj[a] = a < P.dim ? P.x[(size_t)j * P.dim + a] : 0.0;
+        double sj = 0.0;
+        for (int m = 0; m < v.M; ++m) {
+            double d = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double ca = a < P.dim ? P.c[(size_t)m * P.dim + a] : 0.0;
+                d += (xj[a] - ca) * (xj[a] - ca);
+            }
+            const double f = exp(d * P.w[m]);
+            P.W[(size_t)m * P.ldw + j] = f;
+            sj += f;
+        }
         const double is = P.plain ? 1.0 : 1.0 / sj;
         P.is[j] = is;
-        P.u[j] = (P.y[j] - num * is) * is;
-    });
-    center_pass(P, v.M, [](int i) { return i; }, [&](int m, double acc) { v.g[m] = acc - v.l2 * v.beta[m]; });
+        if (!P.plain)
+            for (int m = 0; m < v.M; ++m) P.W[(size_t)m * P.ldw + j] *= is;
+    }
+    __syncthreads();
 }
 
-// q = (W64_S' W64_S + lambda2 I) p over active positions (1 / s_j from the
-// last grad64, which does not depend on beta).
+// t_j = sum_{i < n} W64[key(i)][j] p_i for every sample j (threads over j,
+// eight rows in flight; each row read coalesced).
+template <typename K>
+__device__ __forceinline__ void w_combine(const Pol &P, int n, K key, const double *p, double *t) {
+    for (int j = threadIdx.x; j < P.N; j += kT) {
+        double acc = 0.0;
+        int i = 0;
+        for (; i + 8 <= n; i += 8) {
+            double w[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) w[e] = P.W[(size_t)key(i + e) * P.ldw + j];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc += w[e] * p[i + e];
+        }
+        for (; i < n; ++i) acc += P.W[(size_t)key(i) * P.ldw + j] * p[i];
+        t[j] = acc;
+    }
+    __syncthreads();
+}
+
+// out(i, sum_j W64[key(i)][j] u_j) for i < n: each wave takes four rows at a
+// time, the lanes over j (eight loads in flight per lane), then a wave
+// reduction per row.
+template <typename K, typename F>
+__device__ __forceinline__ void w_dot(const Pol &P, int n, K key, const double *u, F out) {
+    constexpr int RW = 4;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i0 = wid * RW; i0 < n; i0 += kW * RW) {
+        const double *row[RW];
+        double acc[RW];
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            row[r] = P.W + (size_t)key(min(i0 + r, n - 1)) * P.ldw;
+            acc[r] = 0.0;
+        }
+        int j = lane;
+        for (; j + 64 < P.N; j += 128) {
+            const double u0 = u[j], u1 = u[j + 64];
+            double a[RW], b[RW];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) { a[r] = row[r][j]; b[r] = row[r][j + 64]; }
+#pragma unroll
+            for (int r = 0; r < RW; ++r) acc[r] += a[r] * u0 + b[r] * u1;
+        }
+        if (j < P.N) {
+            const double u0 = u[j];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) acc[r] += row[r][j] * u0;
+        }
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int r = 0; r < RW; ++r)
+                if (i0 + r < n) out(i0 + r, acc[r]);
+    }
+    __syncthreads();
+}
+
+// The residual e_j = y_j - (W64 beta)_j over the active coordinates, then
+// g_m = (W64' e)_m - lambda2 beta_m for every m < M.
+template <typename TG>
+__device__ __forceinline__ void grad64(Sv<TG> &v, const Pol &P) {
+    const int *S = v.S;
+    const double *beta = v.beta;
+    v.bytes += 8.0 * (double)(v.s + v.M) * (double)P.N;
+    // active coordinates carry all of W64 beta (beta is zero elsewhere);
+    // p_i = beta at position i, staged in P.t
+    for (int i = threadIdx.x; i < v.s; i += kT) P.t[i] = beta[S[i]];
+    __syncthreads();
+    w_combine(P, v.s, [S](int i) { return S[i]; }, P.t, P.u);
+    for (int j = threadIdx.x; j < P.N; j += kT) P.u[j] = P.y[j] - P.u[j];
+    __syncthreads();
+    w_dot(P, v.M, [](int i) { return i; }, P.u, [&](int m, double acc) { v.g[m] = acc - v.l2 * beta[m]; });
+}
+
+// q = (W64_S' W64_S + lambda2 I) p over active positions.
 template <typename TG>
 __device__ __forceinline__ void apply64(Sv<TG> &v, const Pol &P, const double *p, double *q) {
     const int *S = v.S;
-    sample_pass(P, v.s, [S](int i) { return S[i]; }, p, [&](int j, double, double t) {
-        const double is = P.is[j];
-        P.u[j] = t * is * is;
-    });
-    center_pass(P, v.s, [S](int i) { return S[i]; }, [&](int i, double acc) { q[i] = acc + v.l2 * p[i]; });
+    v.bytes += 16.0 * (double)v.s * (double)P.N;
+    w_combine(P, v.s, [S](int i) { return S[i]; }, p, P.u);
+    w_dot(P, v.s, [S](int i) { return S[i]; }, P.u, [&](int i, double acc) { q[i] = acc + v.l2 * p[i]; });
 }
 
 // z (by position) solves the FP64 reduced system on the signed active set,
@@ -901,7 +998,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.l1 = a.lambda1_sub ? a.lambda1_sub[s_id] : a.lambda1;
     v.l2 = a.lambda2_sub ? a.lambda2_sub[s_id] : a.lambda2;
     v.H = Hall + (size_t)loc * solve_h_elems(a.m_cap);
-    double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap, a.npad);
+    double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap, a.npad, a.precision);
     v.Ag = sc;
     v.U = sc + (size_t)kQ * a.m_cap;
     v.V = sc + (size_t)2 * kQ * a.m_cap;
@@ -1080,6 +1177,8 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         P.u = P.t + a.m_cap;
         P.plain = a.basis == PAM_BASIS_PLAIN;
         P.is = P.u + a.npad;
+        P.W = P.is + a.npad;
+        P.ldw = a.npad;
         for (int m = threadIdx.x; m < M; m += kT) P.w[m] = -0.5 / (P.sg[m] * P.sg[m]);
         __syncthreads();
     }
@@ -1091,6 +1190,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         if (status != PAM_ST_OK) break;
         __syncthreads();
         compact(v, tile);
+        build_w64(v, P);
         grad64(v, P);
         status = PAM_ST_NOCONV;
         refines = 0;

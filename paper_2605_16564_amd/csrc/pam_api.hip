@@ -187,14 +187,14 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
     a.basis = D->basis;
     const size_t per_sub = (size_t)a.mpad * a.npad * wbytes(a.precision) +
                            (size_t)a.mpad * a.mpad * gbytes(a.precision) +
-                           solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad) * 8;
+                           solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad, a.precision) * 8;
     int batch = o->batched ? (int)std::max<size_t>(1, ws_budget() / std::max<size_t>(per_sub, 1)) : 1;
     batch = std::min(batch, a.n_sub);
     pam_status st;
     if ((st = ensure(ctx, BUF_WT, (size_t)batch * a.mpad * a.npad * wbytes(a.precision))) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_G, (size_t)batch * a.mpad * a.mpad * gbytes(a.precision))) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_H, (size_t)batch * solve_h_elems(a.m_cap) * 8)) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_VEC, (size_t)batch * solve_scratch_elems(a.m_cap, a.npad) * 8)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_VEC, (size_t)batch * solve_scratch_elems(a.m_cap, a.npad, a.precision) * 8)) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_FLAGS, (size_t)a.n_sub * 4)) != PAM_OK) return st;
     PAM_CHECK_HIP(hipMemsetAsync(ctx->ws.ptr[BUF_FLAGS], 0, (size_t)a.n_sub * 4, ctx->stream));
     for (int b0 = 0; b0 < a.n_sub; b0 += batch) {

@@ -135,7 +135,7 @@ pam_status launch_gram(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a);
 pam_status solve_check_capacity(int m_cap, int precision);   // LDS of the solve's vectors
 __host__ __device__ size_t solve_h_elems(int m_cap);
-__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad);
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision);
 
 struct RefineArgs {
     int32_t n_sub, dim, m_cap, n_max;
