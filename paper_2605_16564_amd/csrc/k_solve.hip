@@ -836,21 +836,37 @@ __device__ __forceinline__ void build_w64(Sv<TG> &v, const Pol &P) {
 }
 
 // t_j = sum_{i < n} W64[key(i)][j] p_i for every sample j (threads over j,
-// eight rows in flight; each row read coalesced).
+// two samples per thread and eight rows in flight for each; every row read
+// coalesced).
 template <typename K>
 __device__ __forceinline__ void w_combine(const Pol &P, int n, K key, const double *p, double *t) {
-    for (int j = threadIdx.x; j < P.N; j += kT) {
-        double acc = 0.0;
+    for (int j0 = threadIdx.x; j0 < P.N; j0 += 2 * kT) {
+        const int j1 = j0 + kT;
+        const bool two = j1 < P.N;
+        const int j1c = two ? j1 : j0;
+        double acc0 = 0.0, acc1 = 0.0;
         int i = 0;
         for (; i + 8 <= n; i += 8) {
-            double w[8];
+            double w0[8], w1[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) w[e] = P.W[(size_t)key(i + e) * P.ldw + j];
+            for (int e = 0; e < 8; ++e) {
+                const double *row = P.W + (size_t)key(i + e) * P.ldw;
+                w0[e] = row[j0];
+                w1[e] = row[j1c];
+            }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) acc += w[e] * p[i + e];
+            for (int e = 0; e < 8; ++e) {
+                acc0 += w0[e] * p[i + e];
+                acc1 += w1[e] * p[i + e];
+            }
         }
-        for (; i < n; ++i) acc += P.W[(size_t)key(i) * P.ldw + j] * p[i];
-        t[j] = acc;
+        for (; i < n; ++i) {
+            const double *row = P.W + (size_t)key(i) * P.ldw;
+            acc0 += row[j0] * p[i];
+            acc1 += row[j1c] * p[i];
+        }
+        t[j0] = acc0;
+        if (two) t[j1] = acc1;
     }
     __syncthreads();
 }
