@@ -350,9 +350,9 @@ def sub_problem(api, S, D, lo, hi):
 def other_configs(ctx, api, synth, progress):
     """The other configurations as single timed runs (wall clock around
     synchronized calls, kernel split from HIP events): circle64 as 1,024
-    replicas (4,096 FP64 fits), layered3d (1,188 subdomains, BF16 Gram + FP64
-    pass, three enrichment rounds), multifield (5,820 FP32 fits, then 6.4e7
-    FP32 query evaluations)."""
+    replicas (4,096 FP64 fits), layered3d (1,188 subdomains, FP32 Gram + FP64
+    pass, three enrichment rounds; the same with the BF16 Gram beside it),
+    multifield (5,820 FP32 fits, then 6.4e7 FP32 query evaluations)."""
     import torch
     L1, L2 = synth.LAMBDA1, synth.LAMBDA2
     out = {}
@@ -387,19 +387,20 @@ def other_configs(ctx, api, synth, progress):
     ktop = np.floor(0.05 * np.diff(S3.off_host)).astype(np.int32)
     m_cap = 512 + 3 * int(ktop.max()) * 7
 
-    def run3():
+    def run3(prec):
         D3 = api.init_lattice(ctx, g3, [8, 8, 8], m_cap)
-        r = api.refine(ctx, S3, D3, api.EnetOpts(L1, L2, "bf16"),
+        r = api.refine(ctx, S3, D3, api.EnetOpts(L1, L2, prec),
                        api.RefineOpts(k_top=0, k_top_sub=ktop, max_rounds=3, eps_tol=1e-4))
         return D3, r
-    (D3, (b3, lvl3, rounds3, rs3, st3)), dt, tk = timed(run3)
-    stn = api.stats_to_numpy(st3)
-    fits = int(rounds3.sum().item())
-    out["layered3d"] = {"subdomains": D3.n_sub, "fits": fits, "s": dt, "fits_per_s": fits / dt,
-                        "dtype": "bf16", "centers_final_mean": float(D3.m.double().mean().item()),
-                        "status_ok": bool(np.all(stn["status"] == 0)),
-                        "kkt_max": float(stn["kkt"].max()), "kernel_ms": tk}
-    progress("layered3d done")
+    for key, prec in (("layered3d", "f32"), ("layered3d_bf16", "bf16")):
+        (D3, (b3, lvl3, rounds3, rs3, st3)), dt, tk = timed(lambda: run3(prec))
+        stn = api.stats_to_numpy(st3)
+        fits = int(rounds3.sum().item())
+        out[key] = {"subdomains": D3.n_sub, "fits": fits, "s": dt, "fits_per_s": fits / dt,
+                    "dtype": prec, "centers_final_mean": float(D3.m.double().mean().item()),
+                    "status_ok": bool(np.all(stn["status"] == 0)),
+                    "kkt_max": float(stn["kkt"].max()), "kernel_ms": tk}
+        progress(key + " done")
 
     grids = synth.multifield()
     parts = [api.partition(ctx, gg) for gg in grids]

@@ -272,7 +272,7 @@ def workload(name: str) -> Workload:
         return Workload(name, [facies256()], [12, 12], precision="f32", k_top=204,
                         max_rounds=3)
     if name == "layered3d":
-        return Workload(name, [layered3d()], [8, 8, 8], precision="bf16", k_top_frac=0.05,
+        return Workload(name, [layered3d()], [8, 8, 8], precision="f32", k_top_frac=0.05,
                         max_rounds=3)
     if name == "multifield":
         return Workload(name, multifield(), [16, 16], precision="f32",
