@@ -164,6 +164,18 @@ typedef struct {
                                     certificate follow, so beta is the same
                                     minimizer with or without a hint. In
                                     pam_refine it seeds the first fit only.  */
+    int32_t team;                /* workgroups per subdomain in the solve of a
+                                    batched launch: 0 = as many as fit on the
+                                    device at once (4, else 2, else 1), 1 = one,
+                                    2 or 4 = at most that many. A team's first
+                                    workgroup runs the iteration; the others
+                                    take row slices of its passes over the
+                                    active-block inverse and the Gram. The
+                                    minimizer and certificate are the same;
+                                    sums are taken in another order. Unbatched
+                                    launches always use one.                  */
+    int32_t team_min;            /* active-set size from which a team shares
+                                    those passes (0 = 384)                     */
 } pam_enet_opts;
 
 /* Per-subdomain results (device array of n_sub). */
@@ -184,7 +196,7 @@ typedef struct {
                            early on a sign change or lost curvature, the kkt
                            field then shows how far from the FP64 minimizer);
                            0 for FP64                                         */
-    int32_t reserved;
+    int32_t team;       /* workgroups that served the solve (1, 2 or 4)        */
 } pam_fit_stats;
 
 /* a3-a6. For every subdomain: Gaussian RBF design at the samples (Eq.

@@ -222,6 +222,8 @@ class EnetOpts:
     lambda1_sub: Optional[torch.Tensor] = None
     lambda2_sub: Optional[torch.Tensor] = None
     support_hint: Optional[torch.Tensor] = None
+    team: int = 0          # workgroups per subdomain in the solve (0 auto, 1, 2, 4)
+    team_min: int = 0      # active-set size from which a team shares passes (0: 384)
 
     def struct(self, warm_start: bool):
         o = N.PamEnetOpts()
@@ -232,13 +234,14 @@ class EnetOpts:
         o.warm_start = 1 if warm_start else 0
         o.batched = 1 if self.batched else 0
         o.support_hint = _p(self.support_hint)
+        o.team, o.team_min = int(self.team), int(self.team_min)
         return o
 
 
 STATS_DTYPE = np.dtype([("status", np.int32), ("cd_sweeps", np.int32), ("iters", np.int32),
                         ("support", np.int32), ("kkt", np.float64),
                         ("stream_bytes", np.float64), ("polish", np.int32),
-                        ("reserved", np.int32)])
+                        ("team", np.int32)])
 
 
 def new_stats(n_sub, device):

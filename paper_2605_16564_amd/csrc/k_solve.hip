@@ -18,6 +18,8 @@
 
 #include "pam_internal.h"
 
+#include <algorithm>
+
 #ifdef PAM_PHASE_PROFILE
 #define PHASE_MARK(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); ph[k] += _t - ph_last; ph_last = _t; } } while (0)
 #else
@@ -37,15 +39,32 @@ static constexpr int kQ = 16;      // rows of the low-rank update scratch (>= kB
 static constexpr int kPass = kR * kT;
 static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the polish
 static constexpr int kIncMax = 48;     // incremental solution updates between full solves
+static_assert(kFz <= kB && kB <= kQ, "the low-rank passes are instantiated for kB rows");
+
+// A team of up to kTeamMax workgroups, co-resident by a cooperative launch,
+// may serve one subdomain: its first workgroup (the leader) runs the whole
+// iteration; the others only take row slices of the passes that stream the
+// active-block inverse H and the Gram once the active set reaches team_min
+// coordinates. Commands and completions go through a per-team control block
+// (one 128-byte line each) with agent-scope release/acquire; every wait is
+// bounded, after which the leader finishes alone and reports NOCONV.
+static constexpr int kTeamMax = 4;
+static constexpr int kCtl = 16 * (kTeamMax + 1);       // u64 control words per team
+static constexpr long long kTeamWait = 1000000000LL;   // 10 s of the 100 MHz constant clock
+static constexpr unsigned kWaitVm0 = 0x0F70;           // s_waitcnt vmcnt(0) (gfx9 encoding)
+enum TeamOp { OP_QUIT = 0, OP_GEMV = 1, OP_UPASS = 2, OP_UPDATE = 3, OP_GRAD = 4 };
 
 __host__ __device__ size_t solve_ldh(int m_cap) { return (size_t)round_up(m_cap, kPass); }
 __host__ __device__ size_t solve_h_elems(int m_cap) { return (size_t)(m_cap + 1) * solve_ldh(m_cap); }
-__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision) {
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team) {
     // blocked-bordering rows [3][kQ][m_cap], then for the FP64 phase of the
     // low-precision modes: -1/(2 sigma^2) [m_cap], three CG vectors [3][m_cap],
-    // two per-sample vectors [2][npad] and the FP64 design W64 [m_cap][npad]
+    // two per-sample vectors [2][npad] and the FP64 design W64 [m_cap][npad];
+    // with a team: partial results [kTeamMax][kB][m_cap], the input vector,
+    // beta by coordinate and the active list [3][m_cap]
     const size_t w64 = precision == PAM_PREC_F64 ? 0 : (size_t)m_cap * npad;
-    return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad + w64;
+    const size_t tm = team > 1 ? (size_t)(kTeamMax * kB + 3) * m_cap : 0;
+    return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad + w64 + tm;
 }
 size_t solve_lds_bytes(int m_cap) { return (size_t)57 * round_up(m_cap, 8) + 64; }   // 57 B per center: see the carve-out in k_solve
 
@@ -151,17 +170,74 @@ struct Sv {
     int r;                 // frozen positions awaiting the batched downdate
     int *Rp;               // LDS [kFz] frozen positions
     double *Cri;           // LDS [kFz*kFz] inverse of H[R, R]
+    // team (T > 1): see kTeamMax. The team scratch holds partial results
+    // [kTeamMax][kB * m_cap], the input vector [m_cap], beta by coordinate
+    // [m_cap] and the active list [m_cap]; T drops to 1 when a member did
+    // not answer in time (tsh[3] then records the failure).
+    int T, team_min;
+    unsigned long long *ctl;   // [kCtl] command, arguments, completion words
+    double *part;              // team scratch
+    unsigned *tsh;             // LDS [5]: command broadcast, commands posted, failure
+    __device__ double *xin() const { return part + (size_t)kTeamMax * kB * m_cap; }
+    __device__ double *bco() const { return part + (size_t)(kTeamMax * kB + 1) * m_cap; }
+    __device__ int *Sg() const { return reinterpret_cast<int *>(part + (size_t)(kTeamMax * kB + 2) * m_cap); }
 };
+
+template <typename TG>
+__device__ __forceinline__ bool team_on(const Sv<TG> &v) { return v.T > 1 && v.s >= v.team_min; }
+
+// rows [row0(k), row0(k+1)) of an s-row pass belong to member k
+__device__ __forceinline__ int team_row0(int k, int s, int T) { return (int)((long long)k * s / T); }
+
+__device__ __forceinline__ unsigned long long ld_relaxed(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Leader: publish a command (every wave's earlier stores are in L2 before
+// the barrier; the release store writes them back for the other members).
+template <typename TG>
+__device__ __forceinline__ void team_post(Sv<TG> &v, int op, int s, int n) {
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned seq = ++v.tsh[4];
+        v.ctl[1] = (unsigned long long)op;
+        v.ctl[2] = (unsigned long long)s;
+        v.ctl[3] = (unsigned long long)n;
+        __hip_atomic_store(&v.ctl[0], (unsigned long long)seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Leader: wait for every member's completion of the last command (bounded);
+// an unanswered command leaves the leader alone for the rest of the solve.
+template <typename TG>
+__device__ __forceinline__ void team_join(Sv<TG> &v) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long seq = v.tsh[4];
+        const long long t0 = wall_clock64();
+        bool ok = true;
+        for (int k = 1; k < v.T && ok; ++k)
+            while (ld_relaxed(&v.ctl[16 * k]) != seq) {
+                if (wall_clock64() - t0 > kTeamWait) { ok = false; break; }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (!ok) v.tsh[3] = 1;
+    }
+    __syncthreads();
+    if (v.tsh[3]) v.T = 1;   // uniform: the leader goes on alone
+}
 
 template <typename TG>
 __device__ __forceinline__ double Gat(const Sv<TG> &v, int i, int j) {
     return (double)v.G[(size_t)i * v.mpad + j];
 }
 
-// out_i = sum_j H[j][i] in_j, i < s (H symmetric; rows streamed coalesced,
-// four rows in flight per thread).
+// out_i = sum_{r0 <= j < r1} H[j][i] in_j, i < s (H symmetric; rows
+// streamed coalesced, eight rows in flight per thread).
 template <int R, typename TG>
-__device__ __forceinline__ void hgemv_r(Sv<TG> &v, const double *in, double *out) {
+__device__ __forceinline__ void hgemv_r(Sv<TG> &v, const double *in, double *out, int r0, int r1) {
     constexpr int kRows = 8;   // rows loaded before use
     const int s = v.s;
     for (int base = 0; base < s; base += R * kT) {
@@ -169,8 +245,8 @@ __device__ __forceinline__ void hgemv_r(Sv<TG> &v, const double *in, double *out
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
         const double *Hc = v.H + base + threadIdx.x;
-        int jj = 0;
-        for (; jj + kRows <= s; jj += kRows) {
+        int jj = r0;
+        for (; jj + kRows <= r1; jj += kRows) {
             double h[kRows][R];
 #pragma unroll
             for (int q = 0; q < kRows; ++q)
@@ -183,7 +259,7 @@ __device__ __forceinline__ void hgemv_r(Sv<TG> &v, const double *in, double *out
                 for (int r = 0; r < R; ++r) acc[r] += h[q][r] * x;
             }
         }
-        for (; jj < s; ++jj) {
+        for (; jj < r1; ++jj) {
             const double x = in[jj];
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] += Hc[(size_t)jj * v.ldh + r * kT] * x;
@@ -197,21 +273,45 @@ __device__ __forceinline__ void hgemv_r(Sv<TG> &v, const double *in, double *out
     __syncthreads();
 }
 
-// out_i = sum_j H[j][i] in_j, i < s (H symmetric; rows streamed coalesced,
-// up to four outputs per thread so that more rows are in flight).
+// rows [r0, r1) of out = H in, up to four outputs per thread so that more
+// rows are in flight
 template <typename TG>
-__device__ __forceinline__ void hgemv(Sv<TG> &v, const double *in, double *out) {
-    v.bytes += 8.0 * (double)v.s * (double)v.s;
-    if (v.s <= kT) hgemv_r<1>(v, in, out);
-    else if (v.s <= 2 * kT) hgemv_r<2>(v, in, out);
-    else hgemv_r<4>(v, in, out);
+__device__ __forceinline__ void hgemv_rows(Sv<TG> &v, const double *in, double *out, int r0, int r1) {
+    if (v.s <= kT) hgemv_r<1>(v, in, out, r0, r1);
+    else if (v.s <= 2 * kT) hgemv_r<2>(v, in, out, r0, r1);
+    else hgemv_r<4>(v, in, out, r0, r1);
 }
 
-// H[i][j] += sum_q Vr[q][i] Ur[q][j] for i, j < s and q < nq (nq <= kQ):
-// thread-owned columns j keep Ur[.][j] in registers, rows i stream in
-// batches of eight with Vr[.][i] staged in LDS tiles.
+// out_i = sum_j H[j][i] in_j, i < s; a team sums its members' row slices
+// (in member order).
+template <typename TG>
+__device__ __forceinline__ void hgemv(Sv<TG> &v, const double *in, double *out) {
+    const int s = v.s;
+    v.bytes += 8.0 * (double)s * (double)s;
+    if (!team_on(v)) {
+        hgemv_rows(v, in, out, 0, s);
+        return;
+    }
+    double *xin = v.xin();
+    for (int i = threadIdx.x; i < s; i += kT) xin[i] = in[i];
+    team_post(v, OP_GEMV, s, 0);
+    hgemv_rows(v, in, v.part, 0, team_row0(1, s, v.T));
+    team_join(v);
+    const size_t lp = (size_t)kB * v.m_cap;
+    for (int i = threadIdx.x; i < s; i += kT) {
+        double acc = v.part[i];
+        for (int k = 1; k < v.T; ++k) acc += v.part[k * lp + i];
+        out[i] = acc;
+    }
+    __syncthreads();
+}
+
+// H[i][j] += sum_q Vr[q][i] Ur[q][j] for r0 <= i < r1, j < s and q < nq
+// (nq <= NQ): thread-owned columns j keep Ur[.][j] in registers, rows i
+// stream in batches of eight with Vr[.][i] staged in LDS tiles.
 template <int NQ, typename TG>
-__device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *Vr, const double *Ur, double *tile) {
+__device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *Vr, const double *Ur, double *tile,
+                                        int r0, int r1) {
     for (int jb = 0; jb < s; jb += kT) {
         const int j = jb + threadIdx.x;
         const bool live = j < s;
@@ -219,8 +319,8 @@ __device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *
 #pragma unroll
         for (int q = 0; q < NQ; ++q) uj[q] = (live && q < nq) ? Ur[(size_t)q * v.m_cap + j] : 0.0;
         double *Hc = v.H + j;
-        for (int t0 = 0; t0 < s; t0 += kTile) {
-            const int tn = min(kTile, s - t0);
+        for (int t0 = r0; t0 < r1; t0 += kTile) {
+            const int tn = min(kTile, r1 - t0);
             __syncthreads();
             for (int e = threadIdx.x; e < NQ * kTile; e += kT) {
                 const int q = e / kTile, r = e - q * kTile;
@@ -255,31 +355,32 @@ __device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *
     __syncthreads();
 }
 
-// Blocked bordering: append the nb (<= kB) coordinates ks[] to the active
-// set. With A_SB = G[S, B], U = H A_SB, C = A_BB + lambda2 I - A_SB' U,
-//   H <- [[H + U C^-1 U', -U C^-1], [-C^-1 U', C^-1]].
-// Returns false (set unchanged) if C is not numerically positive definite.
-// Rows of A_SB and of V = U C^-1 are staged through LDS in tiles so that
-// the streaming passes over H read them as broadcasts.
-// With upd_z, v.z holds H r_S for the current block (r = b - lambda1 theta)
-// on entry and the solution for the enlarged block on return:
-//   z_S <- z_S + V (U' r_S - r_B),  z_B = C^-1 (r_B - U' r_S).
+// H += V' U over all s rows (nq <= kB rank): shared by the team in row
+// slices once the block is large.
 template <typename TG>
-__device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile,
-                                          bool upd_z = false) {
+__device__ __forceinline__ void hupdate_all(Sv<TG> &v, int s, int nq, double *tile) {
+    if (v.T > 1 && s >= v.team_min) {
+        team_post(v, OP_UPDATE, s, nq);
+        hupdate<kB>(v, s, nq, v.V, v.U, tile, 0, team_row0(1, s, v.T));
+        team_join(v);
+    } else {
+        hupdate<kB>(v, s, nq, v.V, v.U, tile, 0, s);
+    }
+}
+
+// out[q][i] = sum_{r0 <= t < r1} H[t][i] Ag[q][t] for i < s, q < nb (rows
+// [q * m_cap, ...) of out): one pass over rows [r0, r1) of H for all nb
+// columns, the rows of Ag staged through LDS tiles.
+template <typename TG>
+__device__ __forceinline__ void upass(Sv<TG> &v, int nb, int r0, int r1, double *out, double *tile) {
     const int s = v.s;
-    v.bytes += 24.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
-    for (int q = 0; q < nb; ++q)
-        for (int i = threadIdx.x; i < s; i += kT) v.Ag[(size_t)q * v.m_cap + i] = Gat(v, ks[q], v.S[i]);
-    __syncthreads();
-    // U = H A_SB: one pass over H for all nb columns
     for (int base = 0; base < s; base += kPass) {
         double acc[kB];
 #pragma unroll
         for (int q = 0; q < kB; ++q) acc[q] = 0.0;
         const double *Hc = v.H + base + threadIdx.x;
-        for (int t0 = 0; t0 < s; t0 += kTile) {
-            const int tn = min(kTile, s - t0);
+        for (int t0 = r0; t0 < r1; t0 += kTile) {
+            const int tn = min(kTile, r1 - t0);
             __syncthreads();
             for (int e = threadIdx.x; e < kB * kTile; e += kT) {
                 const int q = e / kTile, r = e - q * kTile;
@@ -304,9 +405,45 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         }
         const int i = base + threadIdx.x;
         if (i < s)
-            for (int q = 0; q < nb; ++q) v.U[(size_t)q * v.m_cap + i] = acc[q];
+            for (int q = 0; q < nb; ++q) out[(size_t)q * v.m_cap + i] = acc[q];
     }
     __syncthreads();
+}
+
+// Blocked bordering: append the nb (<= kB) coordinates ks[] to the active
+// set. With A_SB = G[S, B], U = H A_SB, C = A_BB + lambda2 I - A_SB' U,
+//   H <- [[H + U C^-1 U', -U C^-1], [-C^-1 U', C^-1]].
+// Returns false (set unchanged) if C is not numerically positive definite.
+// Rows of A_SB and of V = U C^-1 are staged through LDS in tiles so that
+// the streaming passes over H read them as broadcasts.
+// With upd_z, v.z holds H r_S for the current block (r = b - lambda1 theta)
+// on entry and the solution for the enlarged block on return:
+//   z_S <- z_S + V (U' r_S - r_B),  z_B = C^-1 (r_B - U' r_S).
+template <typename TG>
+__device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile,
+                                          bool upd_z = false) {
+    const int s = v.s;
+    v.bytes += 24.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
+    for (int q = 0; q < nb; ++q)
+        for (int i = threadIdx.x; i < s; i += kT) v.Ag[(size_t)q * v.m_cap + i] = Gat(v, ks[q], v.S[i]);
+    __syncthreads();
+    // U = H A_SB: one pass over H for all nb columns
+    if (!team_on(v)) {
+        upass(v, nb, 0, s, v.U, tile);
+    } else {
+        team_post(v, OP_UPASS, s, nb);
+        upass(v, nb, 0, team_row0(1, s, v.T), v.part, tile);
+        team_join(v);
+        const size_t lp = (size_t)kB * v.m_cap;
+        for (int e = threadIdx.x; e < nb * s; e += kT) {
+            const int q = e / s, i = e - q * s;
+            const size_t o = (size_t)q * v.m_cap + i;
+            double acc = v.part[o];
+            for (int k = 1; k < v.T; ++k) acc += v.part[k * lp + o];
+            v.U[o] = acc;
+        }
+        __syncthreads();
+    }
     // C = A_BB + lambda2 I - A_SB' U: 16 threads per (p, q) pair
     for (int pair0 = 0; pair0 < kB * kB; pair0 += kT / 16) {
         const int pair = pair0 + (threadIdx.x >> 4), l16 = threadIdx.x & 15;
@@ -399,7 +536,7 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         __syncthreads();
     }
     // H[i][j] += sum_q V[q][i] U[q][j] over the old block
-    hupdate<kB>(v, s, nb, v.V, v.U, tile);
+    hupdate_all(v, s, nb, tile);
     for (int j = threadIdx.x; j < s; j += kT)
         for (int q = 0; q < nb; ++q) {
             const double val = -v.V[(size_t)q * v.m_cap + j];
@@ -541,8 +678,7 @@ __device__ __forceinline__ void compact(Sv<TG> &v, double *tile) {
         }
     }
     __syncthreads();
-    if (r <= kB) hupdate<kB>(v, s, r, v.V, v.U, tile);
-    else hupdate<kFz>(v, s, r, v.V, v.U, tile);
+    hupdate_all(v, s, r, tile);
     // drop frozen positions in descending order (each hole takes the last live one)
     for (int n = 0; n < r; ++n) {
         int best = -1;
@@ -606,13 +742,16 @@ template <typename TG> struct Vec16;
 template <> struct Vec16<float> { using type = float4; };
 template <> struct Vec16<double> { using type = double2; };
 
-template <typename TG>
-__device__ __forceinline__ void full_gradient(Sv<TG> &v) {
+// Rows [r0, r1) of the active list Sl (beta by coordinate in bl): with
+// Part, out_m = -sum_i G[Sl_i][m] bl[Sl_i] (a member's partial sum);
+// otherwise out_m = b_m - lambda2 beta_m - sum_i G[Sl_i][m] bl[Sl_i].
+template <bool Part, typename TG>
+__device__ __forceinline__ void grad_rows(Sv<TG> &v, const int *Sl, const double *bl, int r0, int r1,
+                                          double *out) {
     constexpr int kRows = 16;
     constexpr int VW = 16 / (int)sizeof(TG);
     using V = typename Vec16<TG>::type;
-    const int s = v.s, M = v.M;
-    v.bytes += (double)s * M * sizeof(TG);
+    const int M = v.M;
     const int ncol = (M + VW - 1) / VW;
     const size_t ldv = (size_t)v.mpad / VW;   // mpad is a multiple of 64
     for (int cb = threadIdx.x; cb < ncol; cb += kT) {
@@ -621,18 +760,18 @@ __device__ __forceinline__ void full_gradient(Sv<TG> &v) {
 #pragma unroll
         for (int c = 0; c < VW; ++c) {
             const int m = m0 + c;
-            acc[c] = m < M ? v.b[m] - v.l2 * v.beta[m] : 0.0;
+            acc[c] = (!Part && m < M) ? v.b[m] - v.l2 * bl[m] : 0.0;
         }
         const V *col = reinterpret_cast<const V *>(v.G + m0);
-        int i = 0;
-        for (; i + kRows <= s; i += kRows) {
+        int i = r0;
+        for (; i + kRows <= r1; i += kRows) {
             V gv[kRows];
             double bb[kRows];
 #pragma unroll
             for (int e = 0; e < kRows; ++e) {
-                const int k = v.S[i + e];
+                const int k = Sl[i + e];
                 gv[e] = col[(size_t)k * ldv];
-                bb[e] = v.beta[k];
+                bb[e] = bl[k];
             }
 #pragma unroll
             for (int e = 0; e < kRows; ++e) {
@@ -641,17 +780,41 @@ __device__ __forceinline__ void full_gradient(Sv<TG> &v) {
                 for (int c = 0; c < VW; ++c) acc[c] -= (double)g[c] * bb[e];
             }
         }
-        for (; i < s; ++i) {
-            const int k = v.S[i];
+        for (; i < r1; ++i) {
+            const int k = Sl[i];
             const V gv = col[(size_t)k * ldv];
             const TG *g = reinterpret_cast<const TG *>(&gv);
-            const double bk = v.beta[k];
+            const double bk = bl[k];
 #pragma unroll
             for (int c = 0; c < VW; ++c) acc[c] -= (double)g[c] * bk;
         }
 #pragma unroll
         for (int c = 0; c < VW; ++c)
-            if (m0 + c < M) v.g[m0 + c] = acc[c];
+            if (m0 + c < M) out[m0 + c] = acc[c];
+    }
+    __syncthreads();
+}
+
+template <typename TG>
+__device__ __forceinline__ void full_gradient(Sv<TG> &v) {
+    const int s = v.s, M = v.M;
+    v.bytes += (double)s * M * sizeof(TG);
+    if (!team_on(v)) {
+        grad_rows<false>(v, v.S, v.beta, 0, s, v.g);
+        return;
+    }
+    int *Sg = v.Sg();
+    double *bco = v.bco();
+    for (int i = threadIdx.x; i < s; i += kT) Sg[i] = v.S[i];
+    for (int m = threadIdx.x; m < M; m += kT) bco[m] = v.beta[m];
+    team_post(v, OP_GRAD, s, M);
+    grad_rows<true>(v, v.S, v.beta, 0, team_row0(1, s, v.T), v.part);
+    team_join(v);
+    const size_t lp = (size_t)kB * v.m_cap;
+    for (int m = threadIdx.x; m < M; m += kT) {
+        double acc = v.part[m];
+        for (int k = 1; k < v.T; ++k) acc += v.part[k * lp + m];
+        v.g[m] = (v.b[m] - v.l2 * v.beta[m]) + acc;
     }
     __syncthreads();
 }
@@ -990,10 +1153,52 @@ __device__ __forceinline__ int cg64(Sv<TG> &v, const Pol &P, Red &red, double to
     return it;
 }
 
+// Members other than the leader: take row slices of the leader's passes
+// until it quits (or a bounded wait for the next command runs out).
+template <typename TG>
+__device__ __forceinline__ void team_serve(Sv<TG> &v, int rank, double *tile) {
+    unsigned long long seen = 0;   // meaningful in thread 0
+    double *mine = v.part + (size_t)rank * kB * v.m_cap;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const long long t0 = wall_clock64();
+            unsigned long long c;
+            while ((c = ld_relaxed(&v.ctl[0])) == seen) {
+                if (wall_clock64() - t0 > kTeamWait) break;
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            v.tsh[0] = c == seen ? (int)OP_QUIT : (int)v.ctl[1];
+            v.tsh[1] = (int)v.ctl[2];
+            v.tsh[2] = (int)v.ctl[3];
+            seen = c;
+        }
+        __syncthreads();
+        const int op = v.tsh[0], s = v.tsh[1], n = v.tsh[2];
+        __syncthreads();
+        if (op < OP_GEMV || op > OP_GRAD) return;
+        v.s = s;
+        const int r0 = team_row0(rank, s, v.T), r1 = team_row0(rank + 1, s, v.T);
+        if (op == OP_GEMV) hgemv_rows(v, v.xin(), mine, r0, r1);
+        else if (op == OP_UPASS) upass(v, n, r0, r1, mine, tile);
+        else if (op == OP_UPDATE) hupdate<kB>(v, s, n, v.V, v.U, tile, r0, r1);
+        else grad_rows<true>(v, v.Sg(), v.bco(), r0, r1, mine);
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&v.ctl[16 * rank], seen, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <typename TG>
+__device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id, double *sc,
+                                          const int32_t *__restrict__ flags, Red &red, double *cinv, int *blk,
+                                          int *list, double *tile);
+
 template <typename TG>
 __global__ void __launch_bounds__(kT)
 k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
-        double *__restrict__ scratch, const int32_t *__restrict__ flags) {
+        double *__restrict__ scratch, const int32_t *__restrict__ flags, unsigned long long *__restrict__ tctl) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     __shared__ Red red;
     __shared__ double cinv[kB * kB];
@@ -1002,9 +1207,11 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __shared__ double tile[kQ * kTile];
     __shared__ int frz[kFz];
     __shared__ double cri[kFz * kFz + 3 * kFz + 1];
-    const int s_id = a.sub_begin + blockIdx.x;
-    if (a.active && !a.active[s_id]) return;
-    const int loc = s_id - a.sub_begin;
+    __shared__ unsigned tsh[5];
+    const int T = a.team > 1 ? a.team : 1;
+    const int loc = (int)blockIdx.x / T, rank = (int)blockIdx.x - loc * T;
+    const int s_id = a.sub_begin + loc;
+    if (a.active && !a.active[s_id]) return;   // the whole team
     Sv<TG> v;
     v.G = Gall + (size_t)loc * a.mpad * a.mpad;
     v.mpad = a.mpad;
@@ -1014,7 +1221,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.l1 = a.lambda1_sub ? a.lambda1_sub[s_id] : a.lambda1;
     v.l2 = a.lambda2_sub ? a.lambda2_sub[s_id] : a.lambda2;
     v.H = Hall + (size_t)loc * solve_h_elems(a.m_cap);
-    double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap, a.npad, a.precision);
+    double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap, a.npad, a.precision, T);
     v.Ag = sc;
     v.U = sc + (size_t)kQ * a.m_cap;
     v.V = sc + (size_t)2 * kQ * a.m_cap;
@@ -1034,6 +1241,29 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.r = 0;
     v.Rp = frz;
     v.Cri = cri;
+    v.T = T;
+    v.team_min = a.team_min;
+    v.tsh = tsh;
+    v.ctl = nullptr;
+    v.part = nullptr;
+    if (threadIdx.x < 5) tsh[threadIdx.x] = 0;
+    __syncthreads();
+    if (T > 1) {
+        v.ctl = tctl + (size_t)loc * kCtl;
+        v.part = sc + solve_scratch_elems(a.m_cap, a.npad, a.precision, 1);
+        if (rank > 0) {
+            team_serve(v, rank, tile);
+            return;
+        }
+    }
+    solve_one(a, v, s_id, sc, flags, red, cinv, blk, list, tile);
+    if (T > 1) team_post(v, OP_QUIT, 0, 0);   // also after a failure: members still waiting exit
+}
+
+template <typename TG>
+__device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id, double *sc,
+                                          const int32_t *__restrict__ flags, Red &red, double *cinv, int *blk,
+                                          int *list, double *tile) {
     const int M = v.M;
 #ifdef PAM_PHASE_PROFILE
     long long ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1051,7 +1281,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
             const bool empty = M <= 0 || a.off[s_id + 1] <= a.off[s_id];
             st->status = empty ? PAM_ST_EMPTY : PAM_ST_UNDERFLOW;
             st->cd_sweeps = 0; st->iters = 0; st->support = 0; st->kkt = 0.0;
-            st->stream_bytes = 0.0; st->polish = 0; st->reserved = 0;
+            st->stream_bytes = 0.0; st->polish = 0; st->team = 1;
         }
         return;
     }
@@ -1551,6 +1781,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
                ph[0] * 0.01, ph[1] * 0.01, ph[2] * 0.01, ph[3] * 0.01, ph[4] * 0.01, ph[5] * 0.01, ph[6] * 0.01,
                ph[7] * 0.01, ran_ex ? (wall_clock64() - t_ex0) * 0.01 : 0.0);
 #endif
+    if (v.tsh[3]) status = PAM_ST_NOCONV;   // a team member did not answer: the result is not certified
     if (st && threadIdx.x == 0) {
         st->status = status;
         st->cd_sweeps = sweeps;
@@ -1559,7 +1790,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         st->kkt = kkt;
         st->stream_bytes = v.bytes;
         st->polish = n_cg;
-        st->reserved = 0;
+        st->team = v.T;
     }
 }
 
@@ -1581,6 +1812,33 @@ pam_status solve_check_capacity(int m_cap, int precision) {
     return PAM_OK;
 }
 
+template <typename TG>
+static pam_status solve_set_lds(size_t lds) {
+    PAM_CHECK_HIP(hipFuncSetAttribute((const void *)k_solve<TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)lds));
+    return PAM_OK;
+}
+
+int solve_team_size(int sub_count, int m_cap, int precision, int requested) {
+    if (requested == 1 || sub_count < 1) return 1;
+    const size_t lds = solve_lds_bytes(m_cap);
+    const void *fn = precision == PAM_PREC_F64 ? (const void *)k_solve<double> : (const void *)k_solve<float>;
+    if ((precision == PAM_PREC_F64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return 1;
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kT, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    if (!coop) return 1;
+    const long long resident = (long long)per_cu * cus;
+    int T = requested >= 2 ? std::min(requested, kTeamMax) : kTeamMax;
+    while (T > 1 && (long long)sub_count * T > resident) T /= 2;
+    return T;
+}
+
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     const size_t lds = solve_lds_bytes(a.m_cap);
     pam_status st = solve_check_capacity(a.m_cap, a.precision);
@@ -1588,16 +1846,28 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     double *H = wsp<double>(ctx, BUF_H);
     double *scr = wsp<double>(ctx, BUF_VEC);
     const int32_t *flags = wsp<int32_t>(ctx, BUF_FLAGS);
-    if (a.precision == PAM_PREC_F64) {
-        PAM_CHECK_HIP(hipFuncSetAttribute((const void *)k_solve<double>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_solve<double>, dim3(a.sub_count), dim3(kT), lds, ctx->stream, a,
-                           wsp<double>(ctx, BUF_G), H, scr, flags);
+    const int T = a.team > 1 ? a.team : 1;
+    unsigned long long *tctl = nullptr;
+    if (T > 1) {
+        // control words start at zero (no command posted) for every launch
+        const size_t bytes = (size_t)a.sub_count * kCtl * sizeof(unsigned long long);
+        if ((st = ensure(ctx, BUF_TEAM, bytes)) != PAM_OK) return st;
+        tctl = wsp<unsigned long long>(ctx, BUF_TEAM);
+        PAM_CHECK_HIP(hipMemsetAsync(tctl, 0, bytes, ctx->stream));
+    }
+    const bool f64 = a.precision == PAM_PREC_F64;
+    if ((st = f64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return st;
+    const void *fn = f64 ? (const void *)k_solve<double> : (const void *)k_solve<float>;
+    FitArgs ka = a;
+    void *G = f64 ? (void *)wsp<double>(ctx, BUF_G) : (void *)wsp<float>(ctx, BUF_G);
+    void *args[] = {&ka, &G, &H, &scr, (void *)&flags, &tctl};
+    if (T > 1) {
+        // every member of a team waits on the others: all workgroups must be
+        // resident at once, which the cooperative launch guarantees (or refuses)
+        PAM_CHECK_HIP(hipLaunchCooperativeKernel(fn, dim3(a.sub_count * T), dim3(kT), args, (unsigned)lds,
+                                                 ctx->stream));
     } else {
-        PAM_CHECK_HIP(hipFuncSetAttribute((const void *)k_solve<float>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_solve<float>, dim3(a.sub_count), dim3(kT), lds, ctx->stream, a,
-                           wsp<float>(ctx, BUF_G), H, scr, flags);
+        PAM_CHECK_HIP(hipLaunchKernel(fn, dim3(a.sub_count), dim3(kT), args, lds, ctx->stream));
     }
     PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;

@@ -185,16 +185,19 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
     a.stats = stats;
     a.active = active;
     a.basis = D->basis;
+    a.team = 1;
+    a.team_min = o->team_min > 0 ? o->team_min : 384;
     const size_t per_sub = (size_t)a.mpad * a.npad * wbytes(a.precision) +
                            (size_t)a.mpad * a.mpad * gbytes(a.precision) +
-                           solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad, a.precision) * 8;
+                           solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad, a.precision, 1) * 8;
     int batch = o->batched ? (int)std::max<size_t>(1, ws_budget() / std::max<size_t>(per_sub, 1)) : 1;
     batch = std::min(batch, a.n_sub);
+    if (o->batched) a.team = solve_team_size(batch, a.m_cap, a.precision, o->team);
     pam_status st;
     if ((st = ensure(ctx, BUF_WT, (size_t)batch * a.mpad * a.npad * wbytes(a.precision))) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_G, (size_t)batch * a.mpad * a.mpad * gbytes(a.precision))) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_H, (size_t)batch * solve_h_elems(a.m_cap) * 8)) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_VEC, (size_t)batch * solve_scratch_elems(a.m_cap, a.npad, a.precision) * 8)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_VEC, (size_t)batch * solve_scratch_elems(a.m_cap, a.npad, a.precision, a.team) * 8)) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_FLAGS, (size_t)a.n_sub * 4)) != PAM_OK) return st;
     PAM_CHECK_HIP(hipMemsetAsync(ctx->ws.ptr[BUF_FLAGS], 0, (size_t)a.n_sub * 4, ctx->stream));
     for (int b0 = 0; b0 < a.n_sub; b0 += batch) {
@@ -229,6 +232,8 @@ static pam_status check_fit_args(const pam_samples *S, const pam_dict *D, const 
     PAM_REQUIRE(o->lambda2_sub || o->lambda2 >= 0.0, "lambda2 must be >= 0");
     PAM_REQUIRE(o->precision >= PAM_PREC_F64 && o->precision <= PAM_PREC_BF16, "unknown precision");
     PAM_REQUIRE(o->cd_sweeps >= 0 && o->max_iter >= 1, "cd_sweeps >= 0 and max_iter >= 1 required");
+    PAM_REQUIRE(o->team == 0 || o->team == 1 || o->team == 2 || o->team == 4, "team must be 0, 1, 2 or 4");
+    PAM_REQUIRE(o->team_min >= 0, "team_min must be >= 0");
     int64_t nmax = 0;
     for (int s = 0; s < S->n_sub; ++s) {
         const int64_t n = S->off_host[s + 1] - S->off_host[s];

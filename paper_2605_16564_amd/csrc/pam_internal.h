@@ -43,6 +43,7 @@ enum Buf {
     BUF_EVAL,       // query binning workspace
     BUF_FLAGS,      // per-subdomain flags / counters
     BUF_CNN,        // network activations, packed weights, gradient partials
+    BUF_TEAM,       // control words of the solve's workgroup teams
     BUF_COUNT
 };
 
@@ -128,6 +129,8 @@ struct FitArgs {
     pam_fit_stats *stats;
     const int32_t *active;          // [n_sub] 1 = fit this subdomain (refinement), or NULL
     int32_t basis;                  // PAM_BASIS_SHEPARD or PAM_BASIS_PLAIN
+    int32_t team;                   // workgroups per subdomain in the solve (1, 2 or 4)
+    int32_t team_min;               // active-set size from which a team shares passes
 };
 
 pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);
@@ -135,7 +138,10 @@ pam_status launch_gram(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a);
 pam_status solve_check_capacity(int m_cap, int precision);   // LDS of the solve's vectors
 __host__ __device__ size_t solve_h_elems(int m_cap);
-__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision);
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team);
+// Workgroups per subdomain for a solve launch of sub_count subdomains: the
+// largest of requested (0: 4), 2 and 1 whose grid is resident at once.
+int solve_team_size(int sub_count, int m_cap, int precision, int requested);
 
 struct RefineArgs {
     int32_t n_sub, dim, m_cap, n_max;

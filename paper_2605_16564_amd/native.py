@@ -55,13 +55,13 @@ class PamEnetOpts(C.Structure):
                 ("lambda1_sub", C.c_void_p), ("lambda2_sub", C.c_void_p),
                 ("precision", C.c_int32), ("cd_sweeps", C.c_int32), ("max_iter", C.c_int32),
                 ("warm_start", C.c_int32), ("batched", C.c_int32),
-                ("support_hint", C.c_void_p)]
+                ("support_hint", C.c_void_p), ("team", C.c_int32), ("team_min", C.c_int32)]
 
 
 class PamFitStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("cd_sweeps", C.c_int32), ("iters", C.c_int32),
                 ("support", C.c_int32), ("kkt", C.c_double), ("stream_bytes", C.c_double),
-                ("polish", C.c_int32), ("reserved", C.c_int32)]
+                ("polish", C.c_int32), ("team", C.c_int32)]
 
 
 class PamRefineOpts(C.Structure):
