@@ -175,7 +175,7 @@ typedef struct {
                                     sums are taken in another order. Unbatched
                                     launches always use one.                  */
     int32_t team_min;            /* active-set size from which a team shares
-                                    those passes (0 = 384)                     */
+                                    those passes (0 = 128)                     */
 } pam_enet_opts;
 
 /* Per-subdomain results (device array of n_sub). */

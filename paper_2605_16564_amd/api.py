@@ -223,7 +223,7 @@ class EnetOpts:
     lambda2_sub: Optional[torch.Tensor] = None
     support_hint: Optional[torch.Tensor] = None
     team: int = 0          # workgroups per subdomain in the solve (0 auto, 1, 2, 4)
-    team_min: int = 0      # active-set size from which a team shares passes (0: 384)
+    team_min: int = 0      # active-set size from which a team shares passes (0: 128)
 
     def struct(self, warm_start: bool):
         o = N.PamEnetOpts()

@@ -1208,8 +1208,14 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __shared__ int frz[kFz];
     __shared__ double cri[kFz * kFz + 3 * kFz + 1];
     __shared__ unsigned tsh[5];
+    // Workgroups are dispatched to the 8 XCDs round robin (block b to XCD
+    // b mod 8): a team takes T blocks of one XCD (shared L2 for its partial
+    // results) and the leaders spread evenly over all XCDs. With T = 1 this
+    // is the identity; with T > 1 the grid is padded to whole groups of 8.
     const int T = a.team > 1 ? a.team : 1;
-    const int loc = (int)blockIdx.x / T, rank = (int)blockIdx.x - loc * T;
+    const int xcd = (int)blockIdx.x & 7, w = (int)blockIdx.x >> 3;
+    const int loc = xcd + 8 * (w / T), rank = w - (w / T) * T;
+    if (loc >= a.sub_count) return;
     const int s_id = a.sub_begin + loc;
     if (a.active && !a.active[s_id]) return;   // the whole team
     Sv<TG> v;
@@ -1835,7 +1841,7 @@ int solve_team_size(int sub_count, int m_cap, int precision, int requested) {
     if (!coop) return 1;
     const long long resident = (long long)per_cu * cus;
     int T = requested >= 2 ? std::min(requested, kTeamMax) : kTeamMax;
-    while (T > 1 && (long long)sub_count * T > resident) T /= 2;
+    while (T > 1 && round_up(sub_count, 8) * T > resident) T /= 2;
     return T;
 }
 
@@ -1864,8 +1870,8 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     if (T > 1) {
         // every member of a team waits on the others: all workgroups must be
         // resident at once, which the cooperative launch guarantees (or refuses)
-        PAM_CHECK_HIP(hipLaunchCooperativeKernel(fn, dim3(a.sub_count * T), dim3(kT), args, (unsigned)lds,
-                                                 ctx->stream));
+        PAM_CHECK_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)(round_up(a.sub_count, 8) * T)), dim3(kT), args,
+                                                 (unsigned)lds, ctx->stream));
     } else {
         PAM_CHECK_HIP(hipLaunchKernel(fn, dim3(a.sub_count), dim3(kT), args, lds, ctx->stream));
     }

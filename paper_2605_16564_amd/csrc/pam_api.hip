@@ -186,7 +186,7 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
     a.active = active;
     a.basis = D->basis;
     a.team = 1;
-    a.team_min = o->team_min > 0 ? o->team_min : 384;
+    a.team_min = o->team_min > 0 ? o->team_min : 128;
     const size_t per_sub = (size_t)a.mpad * a.npad * wbytes(a.precision) +
                            (size_t)a.mpad * a.mpad * gbytes(a.precision) +
                            solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad, a.precision, 1) * 8;
