@@ -168,6 +168,7 @@ struct Sv {
     int s;                 // active-set size (uniform)
     double bytes;          // algorithmic bytes streamed (Gram rows, H)
     int r;                 // frozen positions awaiting the batched downdate
+    int pend;              // rank of a deferred bordering update (rows [0, pend) of U, V)
     int *Rp;               // LDS [kFz] frozen positions
     double *Cri;           // LDS [kFz*kFz] inverse of H[R, R]
     // team (T > 1): see kTeamMax. The team scratch holds partial results
@@ -358,13 +359,19 @@ __device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *
 // H += V' U over all s rows (nq <= kB rank): shared by the team in row
 // slices once the block is large.
 template <typename TG>
+__device__ __forceinline__ void hupdate_rows(Sv<TG> &v, int s, int nq, double *tile, int r0, int r1) {
+    if (nq <= kB) hupdate<kB>(v, s, nq, v.V, v.U, tile, r0, r1);
+    else hupdate<kQ>(v, s, nq, v.V, v.U, tile, r0, r1);
+}
+
+template <typename TG>
 __device__ __forceinline__ void hupdate_all(Sv<TG> &v, int s, int nq, double *tile) {
     if (v.T > 1 && s >= v.team_min) {
         team_post(v, OP_UPDATE, s, nq);
-        hupdate<kB>(v, s, nq, v.V, v.U, tile, 0, team_row0(1, s, v.T));
+        hupdate_rows(v, s, nq, tile, 0, team_row0(1, s, v.T));
         team_join(v);
     } else {
-        hupdate<kB>(v, s, nq, v.V, v.U, tile, 0, s);
+        hupdate_rows(v, s, nq, tile, 0, s);
     }
 }
 
@@ -419,17 +426,24 @@ __device__ __forceinline__ void upass(Sv<TG> &v, int nb, int r0, int r1, double 
 // With upd_z, v.z holds H r_S for the current block (r = b - lambda1 theta)
 // on entry and the solution for the enlarged block on return:
 //   z_S <- z_S + V (U' r_S - r_B),  z_B = C^-1 (r_B - U' r_S).
+// With defer (and nothing pending), the update of the old block is left
+// pending: the border rows are written, V and U stay in rows [0, nb) of the
+// scratch (zero on the new positions) and v.pend = nb. The next block then
+// reads the stored H, corrects its U by the pending rank (U += Vp (Up' A))
+// and applies both updates in one rank-(pend + nb) pass, so a pair of blocks
+// streams H three times instead of four.
 template <typename TG>
 __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile,
-                                          bool upd_z = false) {
-    const int s = v.s;
-    v.bytes += 24.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
+                                          bool upd_z = false, bool defer = false) {
+    const int s = v.s, pend = v.pend;
+    double *Ub = v.U + (size_t)pend * v.m_cap, *Vb = v.V + (size_t)pend * v.m_cap;
+    v.bytes += 8.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
     for (int q = 0; q < nb; ++q)
         for (int i = threadIdx.x; i < s; i += kT) v.Ag[(size_t)q * v.m_cap + i] = Gat(v, ks[q], v.S[i]);
     __syncthreads();
     // U = H A_SB: one pass over H for all nb columns
     if (!team_on(v)) {
-        upass(v, nb, 0, s, v.U, tile);
+        upass(v, nb, 0, s, Ub, tile);
     } else {
         team_post(v, OP_UPASS, s, nb);
         upass(v, nb, 0, team_row0(1, s, v.T), v.part, tile);
@@ -440,7 +454,34 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
             const size_t o = (size_t)q * v.m_cap + i;
             double acc = v.part[o];
             for (int k = 1; k < v.T; ++k) acc += v.part[k * lp + o];
-            v.U[o] = acc;
+            Ub[o] = acc;
+        }
+        __syncthreads();
+    }
+    if (pend > 0) {
+        // the stored block lacks the pending V_p U_p' on the old positions:
+        // U += V_p (U_p' A_SB), with U_p' A_SB in tile[kB*kB ...)
+        for (int pair0 = 0; pair0 < kB * kB; pair0 += kT / 16) {
+            const int pair = pair0 + (threadIdx.x >> 4), l16 = threadIdx.x & 15;
+            const int p = pair / kB, q = pair % kB;
+            double acc = 0.0;
+            if (pair < kB * kB && p < pend && q < nb)
+                for (int i = l16; i < s; i += 16) acc += v.U[(size_t)p * v.m_cap + i] * v.Ag[(size_t)q * v.m_cap + i];
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+            if (l16 == 0 && pair < kB * kB) tile[kB * kB + pair] = acc;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < s; i += kT) {
+            double vp[kB];
+#pragma unroll
+            for (int p = 0; p < kB; ++p) vp[p] = p < pend ? v.V[(size_t)p * v.m_cap + i] : 0.0;
+            for (int q = 0; q < nb; ++q) {
+                double acc = Ub[(size_t)q * v.m_cap + i];
+#pragma unroll
+                for (int p = 0; p < kB; ++p) acc += vp[p] * (p < pend ? tile[kB * kB + p * kB + q] : 0.0);
+                Ub[(size_t)q * v.m_cap + i] = acc;
+            }
         }
         __syncthreads();
     }
@@ -450,7 +491,7 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         const int p = pair / kB, q = pair % kB;
         double acc = 0.0;
         if (pair < kB * kB && p < nb && q < nb)
-            for (int i = l16; i < s; i += 16) acc += v.Ag[(size_t)p * v.m_cap + i] * v.U[(size_t)q * v.m_cap + i];
+            for (int i = l16; i < s; i += 16) acc += v.Ag[(size_t)p * v.m_cap + i] * Ub[(size_t)q * v.m_cap + i];
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
         if (l16 == 0 && pair < kB * kB) tile[pair] = acc;
@@ -498,12 +539,12 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
     for (int i = threadIdx.x; i < s; i += kT) {
         double uu[kB];
 #pragma unroll
-        for (int p = 0; p < kB; ++p) uu[p] = p < nb ? v.U[(size_t)p * v.m_cap + i] : 0.0;
+        for (int p = 0; p < kB; ++p) uu[p] = p < nb ? Ub[(size_t)p * v.m_cap + i] : 0.0;
         for (int q = 0; q < nb; ++q) {
             double val = 0.0;
 #pragma unroll
             for (int p = 0; p < kB; ++p) val += uu[p] * (p < nb ? cinv[p * kB + q] : 0.0);
-            v.V[(size_t)q * v.m_cap + i] = val;
+            Vb[(size_t)q * v.m_cap + i] = val;
         }
     }
     __syncthreads();
@@ -515,7 +556,7 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
             const int k = v.S[i];
             const double ri = v.b[k] - v.l1 * (double)v.th[k];
 #pragma unroll
-            for (int q = 0; q < kB; ++q) ur[q] += q < nb ? v.U[(size_t)q * v.m_cap + i] * ri : 0.0;
+            for (int q = 0; q < kB; ++q) ur[q] += q < nb ? Ub[(size_t)q * v.m_cap + i] * ri : 0.0;
         }
         bsum_vec<kB>(ur, red);
         double w[kB];   // U' r_S - r_B
@@ -525,7 +566,7 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         for (int i = threadIdx.x; i < s; i += kT) {
             double acc = v.z[i];
 #pragma unroll
-            for (int q = 0; q < kB; ++q) acc += q < nb ? v.V[(size_t)q * v.m_cap + i] * w[q] : 0.0;
+            for (int q = 0; q < kB; ++q) acc += q < nb ? Vb[(size_t)q * v.m_cap + i] * w[q] : 0.0;
             v.z[i] = acc;
         }
         if ((int)threadIdx.x < nb) {
@@ -535,11 +576,16 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         }
         __syncthreads();
     }
-    // H[i][j] += sum_q V[q][i] U[q][j] over the old block
-    hupdate_all(v, s, nb, tile);
+    // H[i][j] += sum_q V[q][i] U[q][j] over the old block (with the pending
+    // rows, which are zero on the pending block's own positions)
+    const bool keep = defer && pend == 0;
+    if (!keep) {
+        v.bytes += 16.0 * (double)s * (double)s;
+        hupdate_all(v, s, pend + nb, tile);
+    }
     for (int j = threadIdx.x; j < s; j += kT)
         for (int q = 0; q < nb; ++q) {
-            const double val = -v.V[(size_t)q * v.m_cap + j];
+            const double val = -Vb[(size_t)q * v.m_cap + j];
             v.H[(size_t)(s + q) * v.ldh + j] = val;
             v.H[(size_t)j * v.ldh + s + q] = val;
         }
@@ -551,9 +597,27 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         v.S[s + threadIdx.x] = ks[threadIdx.x];
         v.pos[ks[threadIdx.x]] = s + threadIdx.x;
     }
+    if (keep) {
+        // the pending factors vanish on the new positions
+        for (int e = threadIdx.x; e < nb * nb; e += kT) {
+            const int q = e / nb, i = s + e % nb;
+            v.U[(size_t)q * v.m_cap + i] = 0.0;
+            v.V[(size_t)q * v.m_cap + i] = 0.0;
+        }
+    }
     __syncthreads();
+    v.pend = keep ? nb : 0;
     v.s = s + nb;
     return true;
+}
+
+// Apply a deferred bordering update (rank v.pend) to the stored block.
+template <typename TG>
+__device__ __forceinline__ void flush_pending(Sv<TG> &v, double *tile) {
+    if (v.pend == 0) return;
+    v.bytes += 16.0 * (double)v.s * (double)v.s;
+    hupdate_all(v, v.s, v.pend, tile);
+    v.pend = 0;
 }
 
 // Drop active position p (no update of H): the last position moves into p.
@@ -830,7 +894,8 @@ __device__ __forceinline__ bool activate(Sv<TG> &v, int *list, int n, Red &red, 
         const int nb = min(kB, n - b0);
         if (threadIdx.x < nb) blk[threadIdx.x] = list[b0 + threadIdx.x];
         __syncthreads();
-        if (add_block(v, blk, nb, red, cinv, tile, upd_z)) {
+        // a block followed by another defers its update to the pair's end
+        if (add_block(v, blk, nb, red, cinv, tile, upd_z, b0 + nb < n)) {
             any = true;
             continue;
         }
@@ -847,6 +912,7 @@ __device__ __forceinline__ bool activate(Sv<TG> &v, int *list, int n, Red &red, 
             __syncthreads();
         }
     }
+    flush_pending(v, tile);
     return any;
 }
 
@@ -866,8 +932,8 @@ __device__ __forceinline__ void rebuild(Sv<TG> &v, int *list, Red &red, double *
     for (int i = threadIdx.x; i < s; i += kT) v.pos[v.S[i]] = -1;
     __syncthreads();
     v.s = 0;
-    for (int b0 = 0; b0 < s; b0 += kB) {
-        const int nb = min(kB, s - b0);
+    for (int b0 = 0; b0 < s; b0 += kAdd) {
+        const int nb = min(kAdd, s - b0);
         if (threadIdx.x < nb) list[threadIdx.x] = (int)v.rhs[b0 + threadIdx.x];
         __syncthreads();
         activate(v, list, nb, red, cinv, blk, tile);
@@ -1181,7 +1247,7 @@ __device__ __forceinline__ void team_serve(Sv<TG> &v, int rank, double *tile) {
         const int r0 = team_row0(rank, s, v.T), r1 = team_row0(rank + 1, s, v.T);
         if (op == OP_GEMV) hgemv_rows(v, v.xin(), mine, r0, r1);
         else if (op == OP_UPASS) upass(v, n, r0, r1, mine, tile);
-        else if (op == OP_UPDATE) hupdate<kB>(v, s, n, v.V, v.U, tile, r0, r1);
+        else if (op == OP_UPDATE) hupdate_rows(v, s, n, tile, r0, r1);
         else grad_rows<true>(v, v.Sg(), v.bco(), r0, r1, mine);
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         __syncthreads();
@@ -1245,6 +1311,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.s = 0;
     v.bytes = 0.0;
     v.r = 0;
+    v.pend = 0;
     v.Rp = frz;
     v.Cri = cri;
     v.T = T;
@@ -1348,7 +1415,7 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
         v.th[m] = (signed char)t;
     }
     __syncthreads();
-    // initial active block, ascending coordinate order, kB at a time
+    // initial active block, ascending coordinate order, kAdd at a time
     for (int m0 = 0; m0 < M; m0 += kT) {
         const int m = m0 + threadIdx.x;
         const bool on = m < M && v.th[m] != 0;
@@ -1366,8 +1433,8 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
         __syncthreads();
         if (on) v.rhs[wbase + pre] = (double)m;   // rhs is free here
         __syncthreads();
-        for (int b0 = 0; b0 < tot; b0 += kB) {
-            const int nb = min(kB, tot - b0);
+        for (int b0 = 0; b0 < tot; b0 += kAdd) {
+            const int nb = min(kAdd, tot - b0);
             if (threadIdx.x < nb) list[threadIdx.x] = (int)v.rhs[b0 + threadIdx.x];
             __syncthreads();
             activate(v, list, nb, red, cinv, blk, tile);
