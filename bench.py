@@ -57,7 +57,7 @@ SLOTS_F64 = 78.6e12 / 2.0
 # HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB device copy), valid only for the
 # kernel source they were taken on (sha256 prefix of its source files).
-TRAFFIC = {("k_solve<float>", "facies256"): {"src": "c18c9cd8f8f9988c", "bytes_per_launch": 66.15e9}}
+TRAFFIC = {("k_solve<float, true>", "facies256"): {"src": "c18c9cd8f8f9988c", "bytes_per_launch": 66.15e9}}
 TRAFFIC_SOURCES = ["paper_2605_16564_amd/csrc/k_solve.hip", "paper_2605_16564_amd/csrc/pam_internal.h"]
 
 
@@ -702,7 +702,8 @@ def main():
             # the active block; algorithmic bytes counted by the kernel itself
             per_launch = solve_bytes / launches
             ach = per_launch / avg_s / 1e9
-            kname = "k_solve<" + ("double" if prec == "f64" else "float") + ">"
+            team = int(st["team"].max()) > 1   # the instance with workgroup teams ran
+            kname = "k_solve<" + ("double" if prec == "f64" else "float") + (", true>" if team else ", false>")
             tr = measured_traffic(kname, args.workload)
             return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": ach / PEAK_HBM_GBS,

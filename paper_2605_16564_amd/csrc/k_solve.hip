@@ -54,9 +54,11 @@ static constexpr long long kTeamWait = 1000000000LL;   // 10 s of the 100 MHz co
 static constexpr unsigned kWaitVm0 = 0x0F70;           // s_waitcnt vmcnt(0) (gfx9 encoding)
 enum TeamOp { OP_QUIT = 0, OP_GEMV = 1, OP_UPASS = 2, OP_UPDATE = 3, OP_GRAD = 4 };
 
-__host__ __device__ size_t solve_ldh(int m_cap) { return (size_t)round_up(m_cap, kPass); }
-__host__ __device__ size_t solve_h_elems(int m_cap) { return (size_t)(m_cap + 1) * solve_ldh(m_cap); }
-__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team) {
+// (force-inlined bodies: a call from the kernel would make it a non-leaf
+// function with the calling convention's register cost)
+__host__ __device__ __forceinline__ size_t ldh_of(int m_cap) { return (size_t)round_up(m_cap, kPass); }
+__host__ __device__ __forceinline__ size_t h_elems_of(int m_cap) { return (size_t)(m_cap + 1) * ldh_of(m_cap); }
+__host__ __device__ __forceinline__ size_t scratch_elems_of(int m_cap, int npad, int precision, int team) {
     // blocked-bordering rows [3][kQ][m_cap], then for the FP64 phase of the
     // low-precision modes: -1/(2 sigma^2) [m_cap], three CG vectors [3][m_cap],
     // two per-sample vectors [2][npad] and the FP64 design W64 [m_cap][npad];
@@ -65,6 +67,11 @@ __host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precisio
     const size_t w64 = precision == PAM_PREC_F64 ? 0 : (size_t)m_cap * npad;
     const size_t tm = team > 1 ? (size_t)(kTeamMax * kB + 3) * m_cap : 0;
     return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad + w64 + tm;
+}
+__host__ __device__ size_t solve_ldh(int m_cap) { return ldh_of(m_cap); }
+__host__ __device__ size_t solve_h_elems(int m_cap) { return h_elems_of(m_cap); }
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team) {
+    return scratch_elems_of(m_cap, npad, precision, team);
 }
 size_t solve_lds_bytes(int m_cap) { return (size_t)57 * round_up(m_cap, 8) + 64; }   // 57 B per center: see the carve-out in k_solve
 
@@ -1261,7 +1268,9 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
                                           const int32_t *__restrict__ flags, Red &red, double *cinv, int *blk,
                                           int *list, double *tile);
 
-template <typename TG>
+// kTeam = false: one workgroup per subdomain, no team code compiled in
+// (T is the constant 1, every team branch folds away).
+template <typename TG, bool kTeam>
 __global__ void __launch_bounds__(kT)
 k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         double *__restrict__ scratch, const int32_t *__restrict__ flags, unsigned long long *__restrict__ tctl) {
@@ -1278,7 +1287,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     // b mod 8): a team takes T blocks of one XCD (shared L2 for its partial
     // results) and the leaders spread evenly over all XCDs. With T = 1 this
     // is the identity; with T > 1 the grid is padded to whole groups of 8.
-    const int T = a.team > 1 ? a.team : 1;
+    const int T = (kTeam && a.team > 1) ? a.team : 1;
     const int xcd = (int)blockIdx.x & 7, w = (int)blockIdx.x >> 3;
     const int loc = xcd + 8 * (w / T), rank = w - (w / T) * T;
     if (loc >= a.sub_count) return;
@@ -1289,11 +1298,11 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.mpad = a.mpad;
     v.M = max(0, min(a.m[s_id], a.m_cap));
     v.m_cap = a.m_cap;
-    v.ldh = solve_ldh(a.m_cap);
+    v.ldh = ldh_of(a.m_cap);
     v.l1 = a.lambda1_sub ? a.lambda1_sub[s_id] : a.lambda1;
     v.l2 = a.lambda2_sub ? a.lambda2_sub[s_id] : a.lambda2;
-    v.H = Hall + (size_t)loc * solve_h_elems(a.m_cap);
-    double *sc = scratch + (size_t)loc * solve_scratch_elems(a.m_cap, a.npad, a.precision, T);
+    v.H = Hall + (size_t)loc * h_elems_of(a.m_cap);
+    double *sc = scratch + (size_t)loc * scratch_elems_of(a.m_cap, a.npad, a.precision, T);
     v.Ag = sc;
     v.U = sc + (size_t)kQ * a.m_cap;
     v.V = sc + (size_t)2 * kQ * a.m_cap;
@@ -1323,7 +1332,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __syncthreads();
     if (T > 1) {
         v.ctl = tctl + (size_t)loc * kCtl;
-        v.part = sc + solve_scratch_elems(a.m_cap, a.npad, a.precision, 1);
+        v.part = sc + scratch_elems_of(a.m_cap, a.npad, a.precision, 1);
         if (rank > 0) {
             team_serve(v, rank, tile);
             return;
@@ -1870,9 +1879,14 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
 // LDS of one workgroup on gfx950 (static + dynamic)
 static constexpr size_t kLdsPerWorkgroup = 160 * 1024;
 
+template <typename TG>
+static const void *solve_fn(bool team) {
+    return team ? (const void *)k_solve<TG, true> : (const void *)k_solve<TG, false>;
+}
+
 pam_status solve_check_capacity(int m_cap, int precision) {
-    hipFuncAttributes attr;
-    const void *fn = precision == PAM_PREC_F64 ? (const void *)k_solve<double> : (const void *)k_solve<float>;
+    hipFuncAttributes attr;   // the team instance's static LDS includes the other's
+    const void *fn = precision == PAM_PREC_F64 ? solve_fn<double>(true) : solve_fn<float>(true);
     PAM_CHECK_HIP(hipFuncGetAttributes(&attr, fn));
     const size_t fixed = attr.sharedSizeBytes;
     if (solve_lds_bytes(m_cap) + fixed > kLdsPerWorkgroup) {
@@ -1887,15 +1901,15 @@ pam_status solve_check_capacity(int m_cap, int precision) {
 
 template <typename TG>
 static pam_status solve_set_lds(size_t lds) {
-    PAM_CHECK_HIP(hipFuncSetAttribute((const void *)k_solve<TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)lds));
+    for (bool team : {false, true})
+        PAM_CHECK_HIP(hipFuncSetAttribute(solve_fn<TG>(team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     return PAM_OK;
 }
 
 int solve_team_size(int sub_count, int m_cap, int precision, int requested) {
     if (requested == 1 || sub_count < 1) return 1;
     const size_t lds = solve_lds_bytes(m_cap);
-    const void *fn = precision == PAM_PREC_F64 ? (const void *)k_solve<double> : (const void *)k_solve<float>;
+    const void *fn = precision == PAM_PREC_F64 ? solve_fn<double>(true) : solve_fn<float>(true);
     if ((precision == PAM_PREC_F64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return 1;
     int dev = 0, coop = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1930,7 +1944,7 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     }
     const bool f64 = a.precision == PAM_PREC_F64;
     if ((st = f64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return st;
-    const void *fn = f64 ? (const void *)k_solve<double> : (const void *)k_solve<float>;
+    const void *fn = f64 ? solve_fn<double>(T > 1) : solve_fn<float>(T > 1);
     FitArgs ka = a;
     void *G = f64 ? (void *)wsp<double>(ctx, BUF_G) : (void *)wsp<float>(ctx, BUF_G);
     void *args[] = {&ka, &G, &H, &scr, (void *)&flags, &tctl};
