@@ -176,6 +176,10 @@ typedef struct {
                                     launches always use one.                  */
     int32_t team_min;            /* active-set size from which a team shares
                                     those passes (0 = 128)                     */
+    int32_t team_idle_us;        /* how long (us, <= 1e7) a team member waits
+                                    for the next pass before it leaves (0 =
+                                    10 s); the leader then does that member's
+                                    rows itself, with the same result          */
 } pam_enet_opts;
 
 /* Per-subdomain results (device array of n_sub). */

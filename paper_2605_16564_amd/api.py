@@ -224,6 +224,7 @@ class EnetOpts:
     support_hint: Optional[torch.Tensor] = None
     team: int = 0          # workgroups per subdomain in the solve (0 auto, 1, 2, 4)
     team_min: int = 0      # active-set size from which a team shares passes (0: 128)
+    team_idle_us: int = 0  # a member's wait for the next pass before it leaves (0: 10 s)
 
     def struct(self, warm_start: bool):
         o = N.PamEnetOpts()
@@ -234,7 +235,7 @@ class EnetOpts:
         o.warm_start = 1 if warm_start else 0
         o.batched = 1 if self.batched else 0
         o.support_hint = _p(self.support_hint)
-        o.team, o.team_min = int(self.team), int(self.team_min)
+        o.team, o.team_min, o.team_idle_us = int(self.team), int(self.team_min), int(self.team_idle_us)
         return o
 
 

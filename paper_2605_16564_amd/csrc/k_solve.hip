@@ -183,6 +183,7 @@ struct Sv {
     // [m_cap] and the active list [m_cap]; T drops to 1 when a member did
     // not answer in time (tsh[3] then records the failure).
     int T, team_min;
+    long long idle;            // constant-clock ticks a member waits for a command before leaving
     unsigned long long *ctl;   // [kCtl] command, arguments, completion words
     double *part;              // team scratch
     unsigned *tsh;             // LDS [5]: command broadcast, commands posted, failure
@@ -216,25 +217,45 @@ __device__ __forceinline__ void team_post(Sv<TG> &v, int op, int s, int n) {
     }
 }
 
-// Leader: wait for every member's completion of the last command (bounded);
-// an unanswered command leaves the leader alone for the rest of the solve.
+// A member that waited kTeamWait for a command without one arriving leaves
+// and marks its completion word kGone; it never started the pending command.
+static constexpr unsigned long long kGone = ~0ull;
+
 template <typename TG>
-__device__ __forceinline__ void team_join(Sv<TG> &v) {
+__device__ __forceinline__ void team_slice(Sv<TG> &v, int op, int s, int n, int k, double *tile);
+
+// Leader: wait for every member's completion of the last command (bounded).
+// The slices of members that have left are done here; a member that neither
+// completes nor leaves in time leaves the leader alone for the rest of the
+// solve (the result is then reported as not certified).
+template <typename TG>
+__device__ __forceinline__ void team_join(Sv<TG> &v, int op, int s, int n, double *tile) {
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned long long seq = v.tsh[4];
         const long long t0 = wall_clock64();
         bool ok = true;
-        for (int k = 1; k < v.T && ok; ++k)
-            while (ld_relaxed(&v.ctl[16 * k]) != seq) {
+        unsigned gone = 0;
+        for (int k = 1; k < v.T && ok; ++k) {
+            unsigned long long d;
+            while ((d = ld_relaxed(&v.ctl[16 * k])) != seq && d != kGone) {
                 if (wall_clock64() - t0 > kTeamWait) { ok = false; break; }
                 __builtin_amdgcn_s_sleep(2);
             }
+            if (d == kGone) gone |= 1u << k;
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (!ok) v.tsh[3] = 1;
+        v.tsh[0] = gone;
     }
     __syncthreads();
-    if (v.tsh[3]) v.T = 1;   // uniform: the leader goes on alone
+    const unsigned gone = v.tsh[0];
+    if (v.tsh[3]) {
+        v.T = 1;   // uniform: the leader goes on alone
+        return;
+    }
+    for (int k = 1; k < v.T; ++k)
+        if (gone & (1u << k)) team_slice(v, op, s, n, k, tile);
 }
 
 template <typename TG>
@@ -303,8 +324,8 @@ __device__ __forceinline__ void hgemv(Sv<TG> &v, const double *in, double *out) 
     double *xin = v.xin();
     for (int i = threadIdx.x; i < s; i += kT) xin[i] = in[i];
     team_post(v, OP_GEMV, s, 0);
-    hgemv_rows(v, in, v.part, 0, team_row0(1, s, v.T));
-    team_join(v);
+    team_slice(v, OP_GEMV, s, 0, 0, nullptr);
+    team_join(v, OP_GEMV, s, 0, nullptr);
     const size_t lp = (size_t)kB * v.m_cap;
     for (int i = threadIdx.x; i < s; i += kT) {
         double acc = v.part[i];
@@ -375,8 +396,8 @@ template <typename TG>
 __device__ __forceinline__ void hupdate_all(Sv<TG> &v, int s, int nq, double *tile) {
     if (v.T > 1 && s >= v.team_min) {
         team_post(v, OP_UPDATE, s, nq);
-        hupdate_rows(v, s, nq, tile, 0, team_row0(1, s, v.T));
-        team_join(v);
+        team_slice(v, OP_UPDATE, s, nq, 0, tile);
+        team_join(v, OP_UPDATE, s, nq, tile);
     } else {
         hupdate_rows(v, s, nq, tile, 0, s);
     }
@@ -453,8 +474,8 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         upass(v, nb, 0, s, Ub, tile);
     } else {
         team_post(v, OP_UPASS, s, nb);
-        upass(v, nb, 0, team_row0(1, s, v.T), v.part, tile);
-        team_join(v);
+        team_slice(v, OP_UPASS, s, nb, 0, tile);
+        team_join(v, OP_UPASS, s, nb, tile);
         const size_t lp = (size_t)kB * v.m_cap;
         for (int e = threadIdx.x; e < nb * s; e += kT) {
             const int q = e / s, i = e - q * s;
@@ -879,8 +900,8 @@ __device__ __forceinline__ void full_gradient(Sv<TG> &v) {
     for (int i = threadIdx.x; i < s; i += kT) Sg[i] = v.S[i];
     for (int m = threadIdx.x; m < M; m += kT) bco[m] = v.beta[m];
     team_post(v, OP_GRAD, s, M);
-    grad_rows<true>(v, v.S, v.beta, 0, team_row0(1, s, v.T), v.part);
-    team_join(v);
+    team_slice(v, OP_GRAD, s, M, 0, nullptr);
+    team_join(v, OP_GRAD, s, M, nullptr);
     const size_t lp = (size_t)kB * v.m_cap;
     for (int m = threadIdx.x; m < M; m += kT) {
         double acc = v.part[m];
@@ -1226,36 +1247,49 @@ __device__ __forceinline__ int cg64(Sv<TG> &v, const Pol &P, Red &red, double to
     return it;
 }
 
+// Member k's rows of a posted pass: inputs from the team buffers and the
+// bordering rows, results to its partial block (or to its rows of H).
+template <typename TG>
+__device__ __forceinline__ void team_slice(Sv<TG> &v, int op, int s, int n, int k, double *tile) {
+    const int r0 = team_row0(k, s, v.T), r1 = team_row0(k + 1, s, v.T);
+    double *mine = v.part + (size_t)k * kB * v.m_cap;
+    if (op == OP_GEMV) hgemv_rows(v, v.xin(), mine, r0, r1);
+    else if (op == OP_UPASS) upass(v, n, r0, r1, mine, tile);
+    else if (op == OP_UPDATE) hupdate_rows(v, s, n, tile, r0, r1);
+    else if (op == OP_GRAD) grad_rows<true>(v, v.Sg(), v.bco(), r0, r1, mine);
+}
+
 // Members other than the leader: take row slices of the leader's passes
-// until it quits (or a bounded wait for the next command runs out).
+// until it quits, or leave (marked kGone) after a bounded wait for the next
+// command.
 template <typename TG>
 __device__ __forceinline__ void team_serve(Sv<TG> &v, int rank, double *tile) {
     unsigned long long seen = 0;   // meaningful in thread 0
-    double *mine = v.part + (size_t)rank * kB * v.m_cap;
     for (;;) {
         if (threadIdx.x == 0) {
             const long long t0 = wall_clock64();
             unsigned long long c;
             while ((c = ld_relaxed(&v.ctl[0])) == seen) {
-                if (wall_clock64() - t0 > kTeamWait) break;
+                if (wall_clock64() - t0 > v.idle) break;
                 __builtin_amdgcn_s_sleep(2);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            v.tsh[0] = c == seen ? (int)OP_QUIT : (int)v.ctl[1];
-            v.tsh[1] = (int)v.ctl[2];
-            v.tsh[2] = (int)v.ctl[3];
+            if (c == seen) {
+                __hip_atomic_store(&v.ctl[16 * rank], kGone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                v.tsh[0] = (unsigned)OP_QUIT;
+            } else {
+                v.tsh[0] = (unsigned)v.ctl[1];
+            }
+            v.tsh[1] = (unsigned)v.ctl[2];
+            v.tsh[2] = (unsigned)v.ctl[3];
             seen = c;
         }
         __syncthreads();
-        const int op = v.tsh[0], s = v.tsh[1], n = v.tsh[2];
+        const int op = (int)v.tsh[0], s = (int)v.tsh[1], n = (int)v.tsh[2];
         __syncthreads();
         if (op < OP_GEMV || op > OP_GRAD) return;
         v.s = s;
-        const int r0 = team_row0(rank, s, v.T), r1 = team_row0(rank + 1, s, v.T);
-        if (op == OP_GEMV) hgemv_rows(v, v.xin(), mine, r0, r1);
-        else if (op == OP_UPASS) upass(v, n, r0, r1, mine, tile);
-        else if (op == OP_UPDATE) hupdate_rows(v, s, n, tile, r0, r1);
-        else grad_rows<true>(v, v.Sg(), v.bco(), r0, r1, mine);
+        team_slice(v, op, s, n, rank, tile);
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         __syncthreads();
         if (threadIdx.x == 0)
@@ -1325,6 +1359,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.Cri = cri;
     v.T = T;
     v.team_min = a.team_min;
+    v.idle = a.team_idle_us > 0 ? (long long)a.team_idle_us * 100 : kTeamWait;   // 100 MHz clock
     v.tsh = tsh;
     v.ctl = nullptr;
     v.part = nullptr;

@@ -187,6 +187,7 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
     a.basis = D->basis;
     a.team = 1;
     a.team_min = o->team_min > 0 ? o->team_min : 128;
+    a.team_idle_us = o->team_idle_us;
     const size_t per_sub = (size_t)a.mpad * a.npad * wbytes(a.precision) +
                            (size_t)a.mpad * a.mpad * gbytes(a.precision) +
                            solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad, a.precision, 1) * 8;
@@ -234,6 +235,7 @@ static pam_status check_fit_args(const pam_samples *S, const pam_dict *D, const 
     PAM_REQUIRE(o->cd_sweeps >= 0 && o->max_iter >= 1, "cd_sweeps >= 0 and max_iter >= 1 required");
     PAM_REQUIRE(o->team == 0 || o->team == 1 || o->team == 2 || o->team == 4, "team must be 0, 1, 2 or 4");
     PAM_REQUIRE(o->team_min >= 0, "team_min must be >= 0");
+    PAM_REQUIRE(o->team_idle_us >= 0 && o->team_idle_us <= 10000000, "team_idle_us must be in [0, 1e7]");
     int64_t nmax = 0;
     for (int s = 0; s < S->n_sub; ++s) {
         const int64_t n = S->off_host[s + 1] - S->off_host[s];

@@ -131,6 +131,7 @@ struct FitArgs {
     int32_t basis;                  // PAM_BASIS_SHEPARD or PAM_BASIS_PLAIN
     int32_t team;                   // workgroups per subdomain in the solve (1, 2 or 4)
     int32_t team_min;               // active-set size from which a team shares passes
+    int32_t team_idle_us;           // a member's wait for a command before it leaves (0: 10 s)
 };
 
 pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);

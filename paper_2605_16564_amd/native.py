@@ -55,7 +55,8 @@ class PamEnetOpts(C.Structure):
                 ("lambda1_sub", C.c_void_p), ("lambda2_sub", C.c_void_p),
                 ("precision", C.c_int32), ("cd_sweeps", C.c_int32), ("max_iter", C.c_int32),
                 ("warm_start", C.c_int32), ("batched", C.c_int32),
-                ("support_hint", C.c_void_p), ("team", C.c_int32), ("team_min", C.c_int32)]
+                ("support_hint", C.c_void_p), ("team", C.c_int32), ("team_min", C.c_int32),
+                ("team_idle_us", C.c_int32)]
 
 
 class PamFitStats(C.Structure):

@@ -11,7 +11,9 @@ same; only summation order differs. Checked here:
   - a three-round refinement makes the same enrichment decisions with and
     without teams;
   - the team size reported per subdomain follows the grid that fits on the
-    device (4, 2, 1), unbatched launches use one, bad values are errors.
+    device (4, 2, 1), unbatched launches use one, bad values are errors;
+  - members that leave early (a 1 us idle bound set from the host) have
+    their rows done by the leader: the same coefficients, status OK.
 """
 import numpy as np
 import pytest
@@ -127,6 +129,22 @@ def test_team_size_follows_the_resident_grid(ctx):
     D = api.init_lattice(ctx, g, [8, 8], 64)
     beta, st = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64", batched=False))
     assert np.all(api.stats_to_numpy(st)["team"] == 1)
-    for bad in (dict(team=3), dict(team=-1), dict(team_min=-2)):
+    for bad in (dict(team=3), dict(team=-1), dict(team_min=-2), dict(team_idle_us=-1),
+                dict(team_idle_us=10_000_001)):
         with pytest.raises(api.N.PamError):
             api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64", **bad))
+
+
+def test_members_that_leave_are_replaced_by_the_leader(ctx):
+    g = _grid()
+    S = api.partition(ctx, g)
+    D = api.init_lattice(ctx, g, [16, 16], 256)
+    ref, st1 = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64", team=1))
+    out, st4 = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64", team=4, team_min=16, team_idle_us=1))
+    torch.cuda.synchronize()
+    s1, s4 = api.stats_to_numpy(st1), api.stats_to_numpy(st4)
+    assert np.all(s4["status"] == 0) and np.all(s4["team"] == 4)
+    assert s4["kkt"].max() <= 1e-9
+    err = _rel(_t(out), _t(ref), _t(D.m))
+    print("members left early: coefficients vs one workgroup", err)
+    assert err <= 1e-9
