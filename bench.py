@@ -57,7 +57,7 @@ SLOTS_F64 = 78.6e12 / 2.0
 # HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB device copy), valid only for the
 # kernel source they were taken on (sha256 prefix of its source files).
-TRAFFIC = {("k_solve<float, true>", "facies256"): {"src": "81b27958b66c7593", "bytes_per_launch": 66.07e9}}
+TRAFFIC = {("k_solve<float, true>", "facies256"): {"src": "bc19a27042e93647", "bytes_per_launch": 66.07e9}}
 TRAFFIC_SOURCES = ["paper_2605_16564_amd/csrc/k_solve.hip", "paper_2605_16564_amd/csrc/pam_internal.h"]
 
 

@@ -43,11 +43,15 @@ static_assert(kFz <= kB && kB <= kQ, "the low-rank passes are instantiated for k
 
 // A team of up to kTeamMax workgroups, co-resident by a cooperative launch,
 // may serve one subdomain: its first workgroup (the leader) runs the whole
-// iteration; the others only take row slices of the passes that stream the
-// active-block inverse H and the Gram once the active set reaches team_min
-// coordinates. Commands and completions go through a per-team control block
-// (one 128-byte line each) with agent-scope release/acquire; every wait is
-// bounded, after which the leader finishes alone and reports NOCONV.
+// iteration; once the active set reaches team_min coordinates, every pass
+// that streams the active-block inverse H or the Gram is split into row
+// slices, one per member (the leader's included), and the leader sums the
+// members' partial results in member order. Commands and completions go
+// through a per-team control block (one 128-byte line each) with agent-scope
+// release/acquire. Every wait is bounded: a member idle for longer than its
+// bound leaves, and the leader does its rows from then on; a member that
+// neither answers nor leaves within kTeamWait leaves the leader alone, and
+// that subdomain's result is reported NOCONV.
 static constexpr int kTeamMax = 4;
 static constexpr int kCtl = 16 * (kTeamMax + 1);       // u64 control words per team
 static constexpr long long kTeamWait = 1000000000LL;   // 10 s of the 100 MHz constant clock
@@ -217,8 +221,8 @@ __device__ __forceinline__ void team_post(Sv<TG> &v, int op, int s, int n) {
     }
 }
 
-// A member that waited kTeamWait for a command without one arriving leaves
-// and marks its completion word kGone; it never started the pending command.
+// A member whose wait for a command ran past its idle bound leaves and marks
+// its completion word kGone; it never started the pending command, if any.
 static constexpr unsigned long long kGone = ~0ull;
 
 template <typename TG>
