@@ -751,6 +751,7 @@ def main():
         "field_l1_log10": l1,
         "kkt_max": float(st["kkt"].max()),
         "fit_status_ok": bool(np.all(st["status"] == 0)),
+        "solve_team": int(st["team"].max()),   # workgroups per subdomain in the solve
         "centers_final_mean": float(m_final.mean()),
         "kernels": per_kernel,
         "dominant_kernel": dominant,
