@@ -8,6 +8,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
@@ -46,13 +47,20 @@ def build(verbose: bool = False, out: Path = OUT, defines=()) -> Path:
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", str(ROOT / "include"), "-I", str(CSRC), "-Wall", "-Wno-unused-function",
              *[f"-D{d}" for d in defines]]
+    cmds = []
     for src in SOURCES:
         obj = out.parent / (Path(src).stem + ".o")
-        cmd = [hipcc(), *flags, "-c", str(CSRC / src), "-o", str(obj)]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        _run(cmd)
+        cmds.append([hipcc(), *flags, "-c", str(CSRC / src), "-o", str(obj)])
         objs.append(str(obj))
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    # one hipcc per source, the longest (the solve: four kernel instances) first
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    order = sorted(cmds, key=lambda c: "k_solve" not in c[-3])
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        for f in [pool.submit(_run, cmd) for cmd in order]:
+            f.result()
     tmp = out.with_suffix(".so.tmp")
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", str(tmp), *objs]
     _run(cmd)
