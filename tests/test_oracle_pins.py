@@ -428,3 +428,136 @@ def test_refinement_reduces_error_on_facies_subdomain():
     assert [int(v) for v in rs[:, 0]] == [64, 217, 370, 523]
     err = rs[:, 4]
     assert np.all(np.diff(err) < 0)
+
+
+# ---------------------------------------------------------------- d = 1 and d = 3 branches
+def test_enrichment_geometry_3d_hand_computed():
+    """Sec. 3.4 in three dimensions (the Gaussian, Shepard and enrichment
+    definitions are dimension-free; the theorem of Sec. 4 is stated in d
+    dimensions): a marked element adds 2^3 - 1 = 7 centers at
+    x_T + (h_T / 2^(l+1)) o, o in {0,1}^3 without 0, axis-0 bit lowest, width
+    sigma0 * eta^(l+1). Values written out by hand; every one is a dyadic
+    rational, so equality is exact."""
+    lib = O.lib()
+    x = np.array([0.5, 0.25, 0.75, 0.125, 0.5, 0.5])          # two elements
+    h = np.array([0.125, 0.0625, 0.25, 0.25, 0.125, 0.5])
+    cap = 24
+    c = np.zeros(cap * 3); s = np.zeros(cap); lv = np.zeros(cap, np.int32)
+    el = np.zeros(2, np.int32)
+    m = lib.ora_enrich(3, 0, cap, x, h, 1, np.array([0], np.int32), 0.2, 0.5, el, c, s, lv)
+    assert m == 7 and list(el) == [1, 0]
+    first = [[0.5625, 0.25, 0.75], [0.5, 0.28125, 0.75], [0.5625, 0.28125, 0.75],
+             [0.5, 0.25, 0.875], [0.5625, 0.25, 0.875], [0.5, 0.28125, 0.875],
+             [0.5625, 0.28125, 0.875]]
+    assert np.array_equal(c[:21].reshape(7, 3), first)
+    assert np.array_equal(s[:7], [0.1] * 7) and np.array_equal(lv[:7], [1] * 7)
+    # rank order: element 1 (never marked) first, then element 0 at level 1
+    m = lib.ora_enrich(3, m, cap, x, h, 2, np.array([1, 0], np.int32), 0.2, 0.5, el, c, s, lv)
+    assert m == 21 and list(el) == [2, 1]
+    second_e1 = [[0.25, 0.5, 0.5], [0.125, 0.5625, 0.5], [0.25, 0.5625, 0.5],
+                 [0.125, 0.5, 0.75], [0.25, 0.5, 0.75], [0.125, 0.5625, 0.75],
+                 [0.25, 0.5625, 0.75]]
+    second_e0 = [[0.53125, 0.25, 0.75], [0.5, 0.265625, 0.75], [0.53125, 0.265625, 0.75],
+                 [0.5, 0.25, 0.8125], [0.53125, 0.25, 0.8125], [0.5, 0.265625, 0.8125],
+                 [0.53125, 0.265625, 0.8125]]
+    assert np.array_equal(c[21:42].reshape(7, 3), second_e1)
+    assert np.array_equal(c[42:63].reshape(7, 3), second_e0)
+    assert np.array_equal(s[7:14], [0.1] * 7) and np.array_equal(s[14:21], [0.05] * 7)
+    assert np.array_equal(lv[7:14], [1] * 7) and np.array_equal(lv[14:21], [2] * 7)
+    # capacity: 21 + 7 > 24, the group is not added and no level changes
+    assert lib.ora_enrich(3, 21, cap, x, h, 1, np.array([0], np.int32), 0.2, 0.5, el, c, s,
+                          lv) == 21
+    assert list(el) == [2, 1]
+
+
+def test_enrichment_geometry_1d_hand_computed():
+    """Sec. 3.4 in one dimension (Example 3's setting): one new center per
+    marked element at x_T + h_T / 2^(l+1), width sigma0 * eta^(l+1)."""
+    lib = O.lib()
+    x = np.array([0.375]); h = np.array([0.25])
+    c = np.zeros(4); s = np.zeros(4); lv = np.zeros(4, np.int32); el = np.zeros(1, np.int32)
+    m = 0
+    for _ in range(3):
+        m = lib.ora_enrich(1, m, 4, x, h, 1, np.array([0], np.int32), 0.3, 0.5, el, c, s, lv)
+    assert m == 3 and el[0] == 3
+    assert np.array_equal(c[:3], [0.5, 0.4375, 0.40625])
+    assert np.array_equal(s[:3], [0.15, 0.075, 0.0375]) and np.array_equal(lv[:3], [1, 2, 3])
+
+
+def _logistic_surrogate_3d(v, cdist, sig):
+    """Sec. 4: two centers +-c v with equal widths and beta = (1, 0) give the
+    normalized expansion 1 / (1 + exp(-2 c <x, v> / sigma^2)) exactly."""
+    cen = np.array([cdist * v, -cdist * v])
+    k = 2.0 * cdist / sig ** 2
+    return cen, lambda p: 1.0 / (1.0 + np.exp(-k * (p @ v)))
+
+
+@pytest.mark.parametrize("space", [0, 1])
+def test_indicator_3d_direct_eight_point(space):
+    """Sec. 2 Step 3 in three dimensions: R_T = sum over the 2x2x2
+    Gauss-Legendre points x_T + (+-1, +-1, +-1) h_T / (2 sqrt 3) of
+    (|T| / 8) (F(K*) - F(y_T))^2. K* is the closed-form logistic of the
+    two-center construction (not the oracle's Gaussian sums), elements have
+    different extents per axis and the direction has three distinct
+    components, so a wrong weight, offset or axis fails."""
+    v = np.array([2.0, 3.0, 6.0]) / 7.0
+    cdist, sig = 0.02, 0.015
+    cen, f = _logistic_surrogate_3d(v, cdist, sig)
+    rng = np.random.default_rng(31)
+    n = 25
+    x = rng.uniform(-0.05, 0.05, size=(n, 3))
+    h = rng.uniform(0.005, 0.03, size=(n, 3))
+    y = (x @ v > 0).astype(float)
+    R = O.indicator(x, y, h, cen, np.array([sig, sig]), np.array([1.0, 0.0]), space=space)
+    F = (lambda u: u) if space == 0 else (lambda u: 10.0 ** u)
+    ref = np.zeros(n)
+    for sg in itertools.product((-1.0, 1.0), repeat=3):
+        p = x + np.array(sg) * h / (2.0 * math.sqrt(3.0))
+        ref += np.prod(h, axis=1) / 8.0 * (F(f(p)) - F(y)) ** 2
+    assert np.allclose(R, ref, rtol=1e-11, atol=1e-14 * ref.max())
+    assert np.all(ref > 0)
+
+
+def test_refinement_counts_3d():
+    """The Table 2 count rule in three dimensions: one center per element of
+    an 8x8x8 subdomain, K_top = 64 marked per round, five rounds without a
+    stop -> 512 + 7 * 64 per round, no basis function added twice, and 7
+    centers per marking."""
+    g = synth.layered3d(nx=8, ny=8, nz=8, sub=(1, 1, 1))
+    S = O.partition(g)
+    D = O.init_dictionary(g, [8, 8, 8], 512 + 5 * 7 * 64)
+    D2, beta, lvl, info = O.refine_batch(S, D, 1e3, 1e-3, k_top=64, max_rounds=5,
+                                         m_max=100000, eps_tol=0.0, cd_sweeps=2)
+    counts = [int(v) for v in info["round_stats"][0, :, 0]]
+    assert counts == [512 + 448 * r for r in range(6)]
+    M = int(D2.m[0])
+    cs = D2.c[: M * 3].reshape(M, 3)
+    key = {(a, b, c, s) for (a, b, c), s in zip(map(tuple, cs), D2.sigma[:M])}
+    assert len(key) == M
+    assert lvl.sum() * 7 == M - 512
+    assert np.all(beta == 0.0)   # lambda1 above ||b||_inf: the fits are exactly zero
+
+
+def test_kkt_residual_hand_computed():
+    """KKT residual of the elastic net (convex optimality conditions of Eq.
+    (elastic)): with A = G + lambda2 I and g = b - A beta, an active
+    coordinate contributes |g_m - lambda1 sign(beta_m)|, an inactive one
+    (|g_m| - lambda1)_+. Values worked out by hand on a 2x2 problem with
+    lambda1 = 1, lambda2 = 0.5, G = [[2, 0.5], [0.5, 3]]; the lambda2 term
+    changes every active residual below."""
+    G = np.array([[2.0, 0.5], [0.5, 3.0]])
+    l1, l2 = 1.0, 0.5
+    b = np.array([5.0, 0.1])
+    # the minimizer: beta_0 = (5 - 1) / 2.5, beta_1 = 0 with |0.1 - 0.8| <= 1
+    assert O.kkt(G, b, l1, l2, np.array([1.6, 0.0])) < 1e-15
+    # active coordinate moved by 0.1: g = (0.75, -0.75), residual |0.75 - 1|
+    assert abs(O.kkt(G, b, l1, l2, np.array([1.7, 0.0])) - 0.25) < 1e-14
+    # inactive violation: b_1 = 1.9 gives g_1 = 1.1, residual 0.1
+    assert abs(O.kkt(G, np.array([5.0, 1.9]), l1, l2, np.array([1.6, 0.0])) - 0.1) < 1e-14
+    # wrong sign: g_0 = 5 + 2.5 * 0.1 = 5.25, residual |5.25 + 1|
+    assert abs(O.kkt(G, b, l1, l2, np.array([-0.1, 0.0])) - 6.25) < 1e-14
+    # both active, off-diagonal coupling: beta = (1, 1): g = (5 - 3, 0.1 - 4) = (2, -3.9);
+    # residuals |2 - 1| = 1 and |-3.9 - 1| = 4.9
+    assert abs(O.kkt(G, b, l1, l2, np.array([1.0, 1.0])) - 4.9) < 1e-14
+    # without the lambda2 term the first perturbed case would read |5 - 3.4 - 1| = 0.6
+    assert abs(O.kkt(G, b, l1, 0.0, np.array([1.7, 0.0])) - 0.6) < 1e-14
