@@ -306,7 +306,7 @@ def darcy(ctx, api, grid, D, beta, blend):
     if grid.dim != 2:
         return None
     o = api.DarcyOpts(grid.n_cells[0], grid.n_cells[1], grid.lo[:2], grid.hi[:2], tol=1e-10)
-    k_true = api.darcy_k_from_cells(grid, o, "cuda")
+    k_true = api.darcy_k_from_cells(ctx, grid, o)
     k_own = api.darcy_k_from_reconstruction(ctx, grid, D, beta, o)
     k_blend = api.darcy_k_from_reconstruction(ctx, grid, D, beta, o, blend=blend)
     torch.cuda.synchronize()

@@ -36,6 +36,10 @@ typedef enum {
     PAM_OK = 0,
     PAM_ERR_ARG = -1,       /* invalid argument (shape, range, NULL)          */
     PAM_ERR_CAPACITY = -2,  /* a capacity (m_cap, workspace cap) is too small */
+    PAM_ERR_NONFINITE = -3, /* pam_sync only: since the previous pam_sync a fit
+                               met a sample point, data value, center or width
+                               that is NaN or infinite (or a width <= 0); the
+                               subdomains concerned carry PAM_ST_NONFINITE   */
     PAM_ERR_HIP = -5,       /* a HIP runtime call failed                      */
     PAM_ERR_NOMEM = -6,     /* workspace allocation failed                    */
     PAM_ERR_STATE = -7      /* context not usable (destroyed, wrong device)   */
@@ -46,7 +50,14 @@ enum {
     PAM_ST_OK = 0,
     PAM_ST_NOCONV = 1,     /* active-set iteration cap reached / singular block */
     PAM_ST_UNDERFLOW = 2,  /* a Shepard denominator was not a positive normal   */
-    PAM_ST_EMPTY = 3       /* subdomain without samples or centers              */
+    PAM_ST_EMPTY = 3,      /* subdomain without samples or centers              */
+    PAM_ST_NONFINITE = 4   /* a sample point, data value, element extent (refine),
+                              center or width of the subdomain is NaN or
+                              infinite, or a width is <= 0: the subdomain is not
+                              fitted (beta = 0) and, in pam_refine, not refined.
+                              The paper's data are positive coefficients whose
+                              logarithm is fitted (remark after Sec. 3.3), so a
+                              non-finite value has no meaning for the method  */
 };
 
 /* Precision of the normalized design and of its Gram products. The
@@ -66,7 +77,10 @@ pam_status pam_create(pam_ctx **out, int device);
 pam_status pam_destroy(pam_ctx *ctx);
 /* Stream used for all later calls (a hipStream_t; NULL = the null stream). */
 pam_status pam_set_stream(pam_ctx *ctx, void *stream);
-/* Block until all work enqueued by the context has finished. */
+/* Block until all work enqueued by the context has finished. Returns
+ * PAM_ERR_NONFINITE if any fit enqueued since the previous pam_sync met
+ * non-finite input (a sticky device flag, cleared by this call; the
+ * per-subdomain status says which subdomains), else PAM_OK or PAM_ERR_HIP. */
 pam_status pam_sync(pam_ctx *ctx);
 /* [host] Message of the last failing call on this thread ("" if none). */
 const char *pam_last_error(void);
@@ -402,6 +416,26 @@ pam_status pam_darcy_solve(pam_ctx *ctx, const pam_darcy_opts *opts, const doubl
  * output (0 if ||p_ref|| = 0). Synchronizes the context's stream. */
 pam_status pam_darcy_error(pam_ctx *ctx, const pam_darcy_opts *opts, const double *p_ref,
                            const double *p, double *e_rel);
+
+/* Coefficient of the pressure problem from the reconstruction (Sec. 5: the
+ * permeability of Eq. (darcy_model) is the surrogate K* of the fitted field;
+ * the experiment of Exp. 1 solves with it on the mesh): k_tri
+ * [n[1]][n[0]][2] (triangle order as above) = 10^K* at the centroid of every
+ * triangle of the mesh of opts, K* the field's owner reconstruction (blend <
+ * 0, as pam_eval) or its continuous reconstruction with band blend in
+ * [0, 1/2] (as pam_eval_blend), in FP64. field: one 2-D field (its query
+ * range is ignored). Workspace: the 2 n[0] n[1] centroids and the
+ * evaluation's own, from the context. */
+pam_status pam_darcy_coefficient(pam_ctx *ctx, const pam_darcy_opts *opts, const pam_field *field,
+                                 const pam_dict *dict, const double *beta, double blend,
+                                 double *k_tri);
+
+/* The data's own coefficient on a mesh whose squares are the data cells:
+ * both triangles of square (i, j) get 10^cell_y[i + n[0] j] (cell_y: device
+ * double [n[0] n[1]], log10 values, axis 0 fastest). The reference pressure
+ * of the relative error of Exp. 1 is solved with it. */
+pam_status pam_darcy_coefficient_cells(pam_ctx *ctx, const pam_darcy_opts *opts,
+                                       const double *cell_y, double *k_tri);
 
 /* ------------------------------------------------------------------------
  * Learned warm start (not part of the paper's method: a support prior for

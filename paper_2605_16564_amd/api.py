@@ -470,39 +470,33 @@ class DarcyOpts:
         return o
 
 
-def triangle_centroids(o: DarcyOpts) -> np.ndarray:
-    """Centroids [n1, n0, 2 (lower-right, upper-left), 2] of the P1 mesh."""
-    xs = o.lo[0] + (o.hi[0] - o.lo[0]) * np.arange(o.n0 + 1) / o.n0
-    ys = o.lo[1] + (o.hi[1] - o.lo[1]) * np.arange(o.n1 + 1) / o.n1
-    x0, x1 = xs[None, :-1], xs[None, 1:]
-    y0, y1 = ys[:-1, None], ys[1:, None]
-    out = np.empty((o.n1, o.n0, 2, 2))
-    out[:, :, 0, 0] = (x0 + 2.0 * x1) / 3.0 + 0.0 * y0
-    out[:, :, 0, 1] = (2.0 * y0 + y1) / 3.0 + 0.0 * x0
-    out[:, :, 1, 0] = (2.0 * x0 + x1) / 3.0 + 0.0 * y0
-    out[:, :, 1, 1] = (y0 + 2.0 * y1) / 3.0 + 0.0 * x0
-    return out
-
-
 def darcy_k_from_reconstruction(ctx: Context, grid, D: Dictionary, beta: torch.Tensor,
                                 o: DarcyOpts, blend: Optional[float] = None) -> torch.Tensor:
     """K = 10^K* at the triangle centroids (owner reconstruction, or the
     continuous one with the given band), float64 [n1, n0, 2] on the device."""
-    xq = torch.as_tensor(triangle_centroids(o).reshape(-1, 2), device=beta.device)
-    if blend is None:
-        k = evaluate(ctx, grid, D, beta, xq, space=1)
-    else:
-        k = evaluate_blend(ctx, grid, D, beta, xq, blend, space=1)
-    return k.reshape(o.n1, o.n0, 2)
+    k = torch.empty((o.n1, o.n0, 2), dtype=torch.float64, device=beta.device)
+    fields, keep = _field_table([grid], 0, None, None)
+    os_, ds = o.struct(), D.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_darcy_coefficient(ctx.h, C.byref(os_), fields, C.byref(ds), _p(beta),
+                                          -1.0 if blend is None else float(blend), _p(k)),
+            "pam_darcy_coefficient")
+    del keep
+    return k
 
 
-def darcy_k_from_cells(grid, o: DarcyOpts, device) -> torch.Tensor:
+def darcy_k_from_cells(ctx: Context, grid, o: DarcyOpts) -> torch.Tensor:
     """The data's own coefficient 10^y on a mesh whose squares are the data
     cells (n0, n1 = the grid's cells): both triangles of a square take it."""
     if (o.n0, o.n1) != (grid.n_cells[0], grid.n_cells[1]):
         raise N.PamError("the mesh must be the data grid")
-    y = torch.as_tensor(grid.y, dtype=torch.float64, device=device).reshape(o.n1, o.n0)
-    return torch.pow(10.0, y)[:, :, None].expand(o.n1, o.n0, 2).contiguous()
+    y = torch.as_tensor(grid.y, dtype=torch.float64, device="cuda")
+    k = torch.empty((o.n1, o.n0, 2), dtype=torch.float64, device=y.device)
+    os_ = o.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_darcy_coefficient_cells(ctx.h, C.byref(os_), _p(y), _p(k)),
+            "pam_darcy_coefficient_cells")
+    return k
 
 
 def darcy_solve(ctx: Context, o: DarcyOpts, k_tri: torch.Tensor, p: Optional[torch.Tensor] = None):

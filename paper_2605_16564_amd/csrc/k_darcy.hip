@@ -410,4 +410,63 @@ pam_status launch_darcy_error(pam_ctx *ctx, const pam_darcy_opts *o, const doubl
     return PAM_OK;
 }
 
+// ---------------------------------------------------------------- coefficient
+// Centroids of the two triangles of every square of the mesh, [n1][n0][2][2]:
+// lower-right (i,j),(i+1,j),(i+1,j+1) at ((x_i + 2 x_{i+1}) / 3, (2 y_j + y_{j+1}) / 3),
+// upper-left (i,j),(i+1,j+1),(i,j+1) at ((2 x_i + x_{i+1}) / 3, (y_j + 2 y_{j+1}) / 3),
+// with x_i = lo_0 + (hi_0 - lo_0) i / n0 and y_j likewise.
+__global__ void __launch_bounds__(kD)
+k_darcy_centroids(int n0, int n1, double lo0, double w0, double lo1, double w1,
+                  double *__restrict__ xq) {
+    const int64_t t = (int64_t)blockIdx.x * kD + threadIdx.x;
+    if (t >= (int64_t)n0 * n1) return;
+    const int i = (int)(t % n0), j = (int)(t / n0);
+    const double x0 = lo0 + w0 * i / n0, x1 = lo0 + w0 * (i + 1) / n0;
+    const double y0 = lo1 + w1 * j / n1, y1 = lo1 + w1 * (j + 1) / n1;
+    double *q = xq + t * 4;
+    q[0] = (x0 + 2.0 * x1) / 3.0;
+    q[1] = (2.0 * y0 + y1) / 3.0;
+    q[2] = (2.0 * x0 + x1) / 3.0;
+    q[3] = (y0 + 2.0 * y1) / 3.0;
+}
+
+// The data's own coefficient: both triangles of square (i, j) take 10^y of
+// data cell (i, j).
+__global__ void __launch_bounds__(kD)
+k_darcy_cells(int n0, int n1, const double *__restrict__ cell_y, double *__restrict__ k) {
+    const int64_t t = (int64_t)blockIdx.x * kD + threadIdx.x;
+    if (t >= (int64_t)n0 * n1) return;
+    const double v = exp10(cell_y[t]);
+    k[2 * t] = v;
+    k[2 * t + 1] = v;
+}
+
+pam_status launch_darcy_coefficient(pam_ctx *ctx, const pam_darcy_opts *o, const pam_field *field,
+                                    const pam_dict *dict, const double *beta, double blend,
+                                    double *k_tri) {
+    const int64_t nsq = (int64_t)o->n[0] * o->n[1];
+    pam_status st = ensure(ctx, BUF_AUX, (size_t)nsq * 4 * sizeof(double));
+    if (st != PAM_OK) return st;
+    double *xq = wsp<double>(ctx, BUF_AUX);
+    hipLaunchKernelGGL(k_darcy_centroids, dim3((unsigned)((nsq + kD - 1) / kD)), dim3(kD), 0,
+                       ctx->stream, o->n[0], o->n[1], o->lo[0], o->hi[0] - o->lo[0], o->lo[1],
+                       o->hi[1] - o->lo[1], xq);
+    PAM_CHECK_HIP(hipGetLastError());
+    pam_field f = *field;
+    f.q_begin = 0;
+    f.q_end = 2 * nsq;
+    if (blend < 0.0)
+        return launch_eval(ctx, 1, &f, dict, beta, 1, xq, 2 * nsq, k_tri, 1, nullptr);
+    return launch_eval_blend(ctx, 1, &f, dict, beta, blend, 1, xq, 2 * nsq, k_tri, 1, nullptr);
+}
+
+pam_status launch_darcy_cells(pam_ctx *ctx, const pam_darcy_opts *o, const double *cell_y,
+                              double *k_tri) {
+    const int64_t nsq = (int64_t)o->n[0] * o->n[1];
+    hipLaunchKernelGGL(k_darcy_cells, dim3((unsigned)((nsq + kD - 1) / kD)), dim3(kD), 0,
+                       ctx->stream, o->n[0], o->n[1], cell_y, k_tri);
+    PAM_CHECK_HIP(hipGetLastError());
+    return PAM_OK;
+}
+
 }  // namespace pam

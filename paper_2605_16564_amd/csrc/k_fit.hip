@@ -29,11 +29,48 @@ template <> __device__ __forceinline__ __hip_bfloat16 to_w<__hip_bfloat16>(doubl
     return __float2bfloat16((float)v);
 }
 
+// Input check (one block per subdomain): every sample coordinate, data value
+// and element extent, and the first m[s] centers and widths must be finite,
+// the widths positive. A failing subdomain is flagged (bit 2) so that the
+// assembly, the solve and the marking skip it, and counted in the context's
+// sticky word that pam_sync reports.
+__global__ void __launch_bounds__(kThreads)
+k_check_finite(FitArgs a, const double *__restrict__ h, int32_t *__restrict__ flags,
+               int32_t *__restrict__ sticky) {
+    const int s = blockIdx.x;
+    if (a.active && !a.active[s]) return;
+    const int64_t j0 = a.off[s];
+    const int64_t nd = (a.off[s + 1] - j0) * a.dim;
+    const int M = max(0, min(a.m[s], a.m_cap));
+    int bad = 0;
+    for (int64_t t = threadIdx.x; t < nd; t += kThreads) {
+        bad |= !isfinite(a.x[j0 * a.dim + t]);
+        if (h) bad |= !isfinite(h[j0 * a.dim + t]);
+    }
+    for (int64_t t = threadIdx.x; t < nd / a.dim; t += kThreads) bad |= !isfinite(a.y[j0 + t]);
+    const double *cs = a.c + (size_t)s * a.m_cap * a.dim;
+    const double *ss = a.sigma + (size_t)s * a.m_cap;
+    for (int t = threadIdx.x; t < M * a.dim; t += kThreads) bad |= !isfinite(cs[t]);
+    for (int t = threadIdx.x; t < M; t += kThreads) bad |= !(isfinite(ss[t]) && ss[t] > 0.0);
+    if (__syncthreads_or(bad) && threadIdx.x == 0) {
+        atomicOr(&flags[s], 2);
+        atomicAdd(sticky, 1);
+    }
+}
+
+pam_status launch_check_finite(pam_ctx *ctx, const FitArgs &a, const double *h) {
+    hipLaunchKernelGGL(k_check_finite, dim3(a.n_sub), dim3(kThreads), 0, ctx->stream, a, h,
+                       wsp<int32_t>(ctx, BUF_FLAGS), ctx->sticky);
+    PAM_CHECK_HIP(hipGetLastError());
+    return PAM_OK;
+}
+
 template <typename TW, bool kF64>
 __global__ void __launch_bounds__(kThreads)
 k_assemble(FitArgs a, TW *__restrict__ Wt, int32_t *__restrict__ flags) {
     const int s = a.sub_begin + blockIdx.y;
     if (a.active && !a.active[s]) return;
+    if (flags[s] & 2) return;   // non-finite input: not fitted
     const int64_t j0 = a.off[s];
     const int N = (int)(a.off[s + 1] - j0);
     const int M = max(0, min(a.m[s], a.m_cap));

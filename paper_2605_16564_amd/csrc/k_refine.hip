@@ -22,6 +22,10 @@ k_indicator(RefineArgs a, double *__restrict__ R) {
     const int64_t j0 = a.off[s];
     const int N = (int)(a.off[s + 1] - j0);
     const int j = blockIdx.x * kT + threadIdx.x;
+    if (a.flags[s] & 2) {   // non-finite input: no indicator
+        if (j < N) R[j0 + j] = __builtin_nan("");
+        return;
+    }
     const int M = max(0, min(a.m[s], a.m_cap));
     const int dim = a.dim;
     const int nq = 1 << dim;
@@ -150,7 +154,7 @@ k_mark_enrich(RefineArgs a, const double *__restrict__ R) {
     }
     const int limit = min(a.m0[s] + a.m_max, a.m_cap);
     const int per = (1 << dim) - 1;
-    const bool failed = a.stats && a.stats[s].status != PAM_ST_OK;
+    const bool failed = (a.stats && a.stats[s].status != PAM_ST_OK) || (a.flags[s] & 2);
     const bool stop = failed || !(rmax >= a.eps_tol) || a.round >= a.max_rounds || M >= limit;
     int nm = 0;
     if (!stop) {
@@ -224,11 +228,17 @@ k_mark_enrich(RefineArgs a, const double *__restrict__ R) {
     }
 }
 
-pam_status launch_mark_enrich(pam_ctx *ctx, const RefineArgs &a) {
-    if (a.n_max > kSortMax) {
+pam_status mark_check_capacity(int n_max) {
+    if (n_max > kSortMax) {
         set_error("pam_refine: subdomains with more than 4096 samples are not supported");
         return PAM_ERR_CAPACITY;
     }
+    return PAM_OK;
+}
+
+pam_status launch_mark_enrich(pam_ctx *ctx, const RefineArgs &a) {
+    pam_status st = mark_check_capacity(a.n_max);
+    if (st != PAM_OK) return st;
     hipLaunchKernelGGL(k_mark_enrich, dim3(a.n_sub), dim3(kT), 0, ctx->stream, a,
                        wsp<double>(ctx, BUF_R));
     PAM_CHECK_HIP(hipGetLastError());

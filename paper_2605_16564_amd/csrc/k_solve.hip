@@ -1395,12 +1395,13 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
     double *beta_out = a.beta + (size_t)s_id * a.m_cap;
     pam_fit_stats *st = a.stats ? a.stats + s_id : nullptr;
 
-    if ((flags[s_id] & 1) || M <= 0 || a.off[s_id + 1] <= a.off[s_id]) {
+    if ((flags[s_id] & 3) || M <= 0 || a.off[s_id + 1] <= a.off[s_id]) {
         for (int m = threadIdx.x; m < a.m_cap; m += kT) beta_out[m] = 0.0;
         if (st && threadIdx.x == 0) {
-            // no centers or no samples is EMPTY (the empty design also flags underflow)
+            // non-finite input first; then no centers or no samples is EMPTY
+            // (the empty design also flags underflow)
             const bool empty = M <= 0 || a.off[s_id + 1] <= a.off[s_id];
-            st->status = empty ? PAM_ST_EMPTY : PAM_ST_UNDERFLOW;
+            st->status = (flags[s_id] & 2) ? PAM_ST_NONFINITE : empty ? PAM_ST_EMPTY : PAM_ST_UNDERFLOW;
             st->cd_sweeps = 0; st->iters = 0; st->support = 0; st->kkt = 0.0;
             st->stream_bytes = 0.0; st->polish = 0; st->team = 1;
         }

@@ -97,19 +97,17 @@ size_t lattice_table_bytes(int n_sub);
 void build_gather_table(const pam_grid *g, void *host_tab);
 void build_lattice_table(const pam_grid *g, const int32_t *gl, double sigma_factor, void *host_tab);
 void axis_range(int n_cells, int n_sub, const int32_t *brk, int k, double overlap, int *first, int *last);
-// eval (k_eval.hip)
-pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, const pam_dict *dict,
-                       const double *beta, int dtype, const void *xq, int64_t Q, void *out,
-                       int space, int64_t *n_outside);
-pam_status launch_eval_blend(pam_ctx *ctx, int n_fields, const pam_field *fields,
-                             const pam_dict *dict, const double *beta, double blend, int dtype,
-                             const void *xq, int64_t Q, void *out, int space, int64_t *n_outside);
 int64_t interface_count(int n_fields, const pam_field *fields);
 // Darcy consumer (k_darcy.hip)
 pam_status launch_darcy_solve(pam_ctx *ctx, const pam_darcy_opts *o, const double *k_tri,
                               double *p, int warm, int32_t *iters, double *rel_res);
 pam_status launch_darcy_error(pam_ctx *ctx, const pam_darcy_opts *o, const double *p_ref,
                               const double *p, double *e_rel);
+pam_status launch_darcy_coefficient(pam_ctx *ctx, const pam_darcy_opts *o, const pam_field *field,
+                                    const pam_dict *dict, const double *beta, double blend,
+                                    double *k_tri);
+pam_status launch_darcy_cells(pam_ctx *ctx, const pam_darcy_opts *o, const double *cell_y,
+                              double *k_tri);
 // lambda selection (k_select.hip)
 pam_status launch_cv_setup(pam_ctx *ctx, const pam_samples *S, const pam_dict *D, int K,
                            const int64_t *off_v, double *xv, double *yv, int32_t *mv, double *cv,
@@ -157,7 +155,7 @@ static size_t gbytes(int prec) { return prec == PAM_PREC_F64 ? 8 : 4; }
 // workspace budget (batched = 0: one subdomain per launch).
 static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
                           const pam_enet_opts *o, double *beta, pam_fit_stats *stats,
-                          const int32_t *active, int warm_start) {
+                          const int32_t *active, int warm_start, const double *h = nullptr) {
     FitArgs a;
     memset(&a, 0, sizeof(a));
     a.n_sub = S->n_sub;
@@ -201,6 +199,7 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
     if ((st = ensure(ctx, BUF_VEC, (size_t)batch * solve_scratch_elems(a.m_cap, a.npad, a.precision, a.team) * 8)) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_FLAGS, (size_t)a.n_sub * 4)) != PAM_OK) return st;
     PAM_CHECK_HIP(hipMemsetAsync(ctx->ws.ptr[BUF_FLAGS], 0, (size_t)a.n_sub * 4, ctx->stream));
+    if ((st = launch_check_finite(ctx, a, h)) != PAM_OK) return st;
     for (int b0 = 0; b0 < a.n_sub; b0 += batch) {
         a.sub_begin = b0;
         a.sub_count = std::min(batch, a.n_sub - b0);
@@ -276,8 +275,16 @@ pam_status pam_create(pam_ctx **out, int device) {
         return PAM_ERR_ARG;
     }
     PAM_CHECK_HIP(hipSetDevice(device));
+    int32_t *sticky = nullptr;
+    PAM_CHECK_HIP(hipMalloc(&sticky, 4 * sizeof(int32_t)));
+    if (hipMemset(sticky, 0, 4 * sizeof(int32_t)) != hipSuccess) {
+        (void)hipFree(sticky);
+        set_error("pam_create: hipMemset failed");
+        return PAM_ERR_HIP;
+    }
     pam_ctx *c = new pam_ctx();
     c->device = device;
+    c->sticky = sticky;
     *out = c;
     return PAM_OK;
 }
@@ -295,6 +302,7 @@ pam_status pam_destroy(pam_ctx *ctx) {
     for (hipEvent_t e : ctx->timing.pool) (void)hipEventDestroy(e);
     if (ctx->staging.host) (void)hipHostFree(ctx->staging.host);
     if (ctx->staging.done) (void)hipEventDestroy(ctx->staging.done);
+    if (ctx->sticky) (void)hipFree(ctx->sticky);
     ctx->alive = false;
     delete ctx;
     return PAM_OK;
@@ -311,6 +319,15 @@ pam_status pam_sync(pam_ctx *ctx) {
     pam_status st = check_ctx(ctx);
     if (st != PAM_OK) return st;
     PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+    int32_t bad = 0;
+    PAM_CHECK_HIP(hipMemcpy(&bad, ctx->sticky, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (bad) {
+        PAM_CHECK_HIP(hipMemsetAsync(ctx->sticky, 0, sizeof(int32_t), ctx->stream));
+        PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+        set_error("non-finite input (or a width <= 0) in " + std::to_string(bad) +
+                  " subdomain fit(s) since the previous pam_sync; see the per-subdomain status");
+        return PAM_ERR_NONFINITE;
+    }
     return PAM_OK;
 }
 
@@ -427,6 +444,7 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     PAM_REQUIRE(r->eta > 0.0 && r->eta < 1.0, "eta must be in (0, 1)");
     PAM_REQUIRE(r->k_top >= 0 || r->k_top_sub, "k_top must be >= 0");
     PAM_REQUIRE(r->space == 0 || r->space == 1, "space must be 0 or 1");
+    if ((st = mark_check_capacity(samples->n_max)) != PAM_OK) return st;
     const int n = samples->n_sub;
     // per-subdomain int tables: active, m0, k_top
     std::vector<int32_t> tab((size_t)3 * n);
@@ -471,7 +489,9 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     ra.basis = dict->basis;
     for (int round = 0; round <= r->max_rounds; ++round) {
         const int warm = round == 0 ? opts->warm_start : (r->cold_rounds ? 0 : 1);
-        if ((st = run_fit(ctx, samples, dict, opts, beta, stats, active, warm)) != PAM_OK) return st;
+        if ((st = run_fit(ctx, samples, dict, opts, beta, stats, active, warm, samples->h)) != PAM_OK)
+            return st;
+        ra.flags = wsp<int32_t>(ctx, BUF_FLAGS);
         ra.round = round;
         {
             KernelTimer kt(ctx, PAM_TK_INDICATOR);
@@ -667,6 +687,32 @@ pam_status pam_eval_blend(pam_ctx *ctx, int32_t n_fields, const pam_field *field
     PAM_REQUIRE(Q <= ((int64_t)1 << 59), "too many queries");
     return launch_eval_blend(ctx, n_fields, fields, dict, beta, blend, dtype, xq, Q, out, space,
                              n_outside);
+}
+
+pam_status pam_darcy_coefficient(pam_ctx *ctx, const pam_darcy_opts *opts, const pam_field *field,
+                                 const pam_dict *dict, const double *beta, double blend,
+                                 double *k_tri) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    if ((st = check_darcy(opts)) != PAM_OK) return st;
+    PAM_REQUIRE(field && dict && beta && k_tri, "NULL argument");
+    PAM_REQUIRE(field->dim == 2, "the Darcy mesh is two-dimensional");
+    PAM_REQUIRE(blend < 0.0 || blend <= 0.5, "blend must be < 0 (owner) or in [0, 1/2]");
+    pam_field f = *field;
+    const int64_t Q = 2 * (int64_t)opts->n[0] * opts->n[1];
+    f.q_begin = 0;
+    f.q_end = Q;
+    if ((st = check_fields(1, &f, dict, Q)) != PAM_OK) return st;
+    return launch_darcy_coefficient(ctx, opts, &f, dict, beta, blend, k_tri);
+}
+
+pam_status pam_darcy_coefficient_cells(pam_ctx *ctx, const pam_darcy_opts *opts,
+                                       const double *cell_y, double *k_tri) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    if ((st = check_darcy(opts)) != PAM_OK) return st;
+    PAM_REQUIRE(cell_y && k_tri, "NULL argument");
+    return launch_darcy_cells(ctx, opts, cell_y, k_tri);
 }
 
 int64_t pam_interface_count(int32_t n_fields, const pam_field *fields) {

@@ -44,6 +44,7 @@ enum Buf {
     BUF_FLAGS,      // per-subdomain flags / counters
     BUF_CNN,        // network activations, packed weights, gradient partials
     BUF_TEAM,       // control words of the solve's workgroup teams
+    BUF_AUX,        // staging of generated query points (Darcy coefficient)
     BUF_COUNT
 };
 
@@ -77,6 +78,7 @@ struct pam_ctx {
     pam::Workspace ws;
     pam::Staging staging;
     pam::Timing timing;
+    int32_t *sticky = nullptr;   // device [4]: [0] subdomains met with non-finite input
     bool alive = true;
 };
 
@@ -134,6 +136,11 @@ struct FitArgs {
     int32_t team_idle_us;           // a member's wait for a command before it leaves (0: 10 s)
 };
 
+// Non-finite input check of a fit call: for every subdomain, its sample
+// points, data values, element extents (h, may be NULL), centers and widths;
+// a subdomain with a NaN / infinite value or a width <= 0 gets bit 2 in the
+// per-subdomain flags (BUF_FLAGS) and is counted in ctx->sticky[0].
+pam_status launch_check_finite(pam_ctx *ctx, const FitArgs &a, const double *h);
 pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_gram(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a);
@@ -162,9 +169,20 @@ struct RefineArgs {
     double *round_stats;
     pam_fit_stats *stats;
     int32_t basis;
+    const int32_t *flags;           // [n_sub] per-subdomain flags of the round's fit
 };
 
 pam_status launch_indicator(pam_ctx *ctx, const RefineArgs &a);
+
+// evaluation (k_eval.hip), also used by the Darcy coefficient
+pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, const pam_dict *dict,
+                       const double *beta, int dtype, const void *xq, int64_t Q, void *out,
+                       int space, int64_t *n_outside);
+pam_status launch_eval_blend(pam_ctx *ctx, int n_fields, const pam_field *fields,
+                             const pam_dict *dict, const double *beta, double blend, int dtype,
+                             const void *xq, int64_t Q, void *out, int space, int64_t *n_outside);
 pam_status launch_mark_enrich(pam_ctx *ctx, const RefineArgs &a);
+// PAM_ERR_CAPACITY when the marking cannot rank n_max samples per subdomain.
+pam_status mark_check_capacity(int n_max);
 
 }  // namespace pam

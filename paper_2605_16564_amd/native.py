@@ -14,7 +14,8 @@ LIB_PATH = Path(os.environ.get("PAM_LIB", str(Path(__file__).resolve().parent / 
 
 PAM_OK = 0
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
-ST_OK, ST_NOCONV, ST_UNDERFLOW, ST_EMPTY = 0, 1, 2, 3
+ST_OK, ST_NOCONV, ST_UNDERFLOW, ST_EMPTY, ST_NONFINITE = 0, 1, 2, 3, 4
+ERR_NONFINITE = -3
 
 EXPORTS = [
     "pam_create", "pam_destroy", "pam_set_stream", "pam_sync", "pam_last_error", "pam_version",
@@ -23,7 +24,7 @@ EXPORTS = [
     "pam_cnn_param_count", "pam_cnn_forward", "pam_cnn_loss_grad", "pam_cnn_adam",
     "pam_grid_patches", "pam_support_hint", "pam_cnn_labels",
     "pam_eval_blend", "pam_interface_count", "pam_interface_jump", "pam_select_lambda",
-    "pam_darcy_solve", "pam_darcy_error",
+    "pam_darcy_solve", "pam_darcy_error", "pam_darcy_coefficient", "pam_darcy_coefficient_cells",
 ]
 TIMING_KINDS = ["gather", "lattice", "assemble", "gram", "solve", "indicator", "mark",
                 "eval_bin", "eval", "cnn", "blend", "jump",
@@ -94,7 +95,9 @@ _lib = None
 
 
 class PamError(RuntimeError):
-    pass
+    def __init__(self, msg, status=None):
+        super().__init__(msg)
+        self.status = status
 
 
 def lib():
@@ -132,6 +135,9 @@ def lib():
                                         P, P, P]
         L.pam_darcy_solve.argtypes = [P, C.POINTER(PamDarcyOpts), P, P, C.c_int32, P, P]
         L.pam_darcy_error.argtypes = [P, C.POINTER(PamDarcyOpts), P, P, P]
+        L.pam_darcy_coefficient.argtypes = [P, C.POINTER(PamDarcyOpts), C.POINTER(PamField),
+                                            C.POINTER(PamDict), P, C.c_double, P]
+        L.pam_darcy_coefficient_cells.argtypes = [P, C.POINTER(PamDarcyOpts), P, P]
         L.pam_timing_enable.argtypes = [P, C.c_int32]
         L.pam_timing_read.argtypes = [P, P, P, C.c_int32]
         L.pam_cnn_param_count.argtypes = []
@@ -155,4 +161,4 @@ def lib():
 def check(status: int, what: str):
     if status != PAM_OK:
         msg = lib().pam_last_error().decode(errors="replace")
-        raise PamError(f"{what} failed with status {status}: {msg}")
+        raise PamError(f"{what} failed with status {status}: {msg}", status)

@@ -94,7 +94,7 @@ def test_reconstruction_to_pressure_error(ctx):
     beta, _ = api.fit(ctx, S, D, api.EnetOpts(synth.LAMBDA1, synth.LAMBDA2, "f64"))
     o = _opts(64, 64)
     k_star = api.darcy_k_from_reconstruction(ctx, g, D, beta, o)
-    k_true = api.darcy_k_from_cells(g, o, "cuda")
+    k_true = api.darcy_k_from_cells(ctx, g, o)
     p_star, it1, _ = api.darcy_solve(ctx, o, k_star)
     p_true, it2, _ = api.darcy_solve(ctx, o, k_true)
     e_gpu = api.darcy_error(ctx, o, p_true, p_star)

@@ -93,3 +93,56 @@ def test_largest_dictionary_and_capacity_error(ctx):
     Dbig = api.init_lattice(ctx, g, [48, 48], 2720)
     with pytest.raises(native.PamError, match="m_cap too large"):
         api.fit(ctx, S, Dbig, api.EnetOpts(L1, L2, "f32"))
+
+
+def test_nonfinite_input_detected(ctx):
+    """A NaN data value, an infinite sample point, an infinite center or a
+    zero width leaves that subdomain unfitted with status NONFINITE (beta
+    zero) while the others are fitted as usual; pam_sync then reports
+    PAM_ERR_NONFINITE once (the flag is sticky until read)."""
+    g = synth.circle64()
+    S = api.partition(ctx, g)
+    od = O.init_dictionary(g, [16, 16], 256)
+    bo, _, _ = O.fit_batch(O.partition(g), od, L1, L2)
+    ctx.sync()                                   # clears any earlier flag
+    for case in ("nan_y", "inf_x", "inf_c", "zero_sigma", "inf_y_refine"):
+        print("case", case, flush=True)
+        S2 = api.Samples(S.dim, S.n_sub, S.n_max, S.off, S.off_host, S.x.clone(), S.y.clone(),
+                         S.h.clone())
+        D = _dict_from(od if case != "inf_y_refine" else O.init_dictionary(g, [16, 16], 556))
+        j = int(S.off_host[1]) + 17              # an element of subdomain 1
+        if case == "nan_y":
+            S2.y[j] = float("nan")
+        elif case == "inf_x":
+            S2.x[j, 0] = float("inf")
+        elif case == "inf_c":
+            D.c[1, 5, 1] = float("-inf")
+        elif case == "zero_sigma":
+            D.sigma[1, 9] = 0.0
+        else:
+            S2.y[j] = float("inf")
+        if case == "inf_y_refine":
+            beta, lvl, rounds, rs, st = api.refine(ctx, S2, D, api.EnetOpts(L1, L2, "f64"),
+                                                   api.RefineOpts(k_top=50, max_rounds=2,
+                                                                  eps_tol=1e-9))
+        else:
+            beta = torch.full((4, 256), 7.0, dtype=torch.float64, device="cuda")
+            beta, st = api.fit(ctx, S2, D, api.EnetOpts(L1, L2, "f64"))
+        with pytest.raises(native.PamError) as ei:
+            ctx.sync()
+        assert ei.value.status == native.ERR_NONFINITE
+        ctx.sync()                               # read once: cleared
+        stn = api.stats_to_numpy(st)
+        assert stn["status"][1] == native.ST_NONFINITE
+        assert np.all(np.delete(stn["status"], 1) == 0)
+        b = _t(beta)
+        assert np.all(b[1] == 0.0)
+        if case == "inf_y_refine":
+            assert int(_t(D.m).min()) == 256 and int(_t(D.m).max()) > 256
+            r = _t(rounds)
+            assert r[1] == 1 and np.all(np.delete(r, 1) >= 2)
+            assert int(_t(D.m)[1]) == 256        # not enriched
+            continue
+        for s in (0, 2, 3):
+            ref = bo[s * 256:(s + 1) * 256]
+            assert np.abs(b[s] - ref).max() <= 1e-9 * np.abs(ref).max()

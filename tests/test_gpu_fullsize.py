@@ -173,7 +173,7 @@ def test_c2_darcy_on_the_data_coefficient(ctx):
     from oracle import darcy_oracle as DO
     g = synth.facies256()
     o = api.DarcyOpts(256, 256, tol=1e-12)
-    p, it, rel = api.darcy_solve(ctx, o, api.darcy_k_from_cells(g, o, "cuda"))
+    p, it, rel = api.darcy_solve(ctx, o, api.darcy_k_from_cells(ctx, g, o))
     lo, hi = np.zeros(2), np.ones(2)
     ref = DO.solve(256, 256, lo, hi, DO.k_from_cells(256, 256, lo, hi, g.y, 256, 256))
     err = np.abs(_t(p) - ref).max()
