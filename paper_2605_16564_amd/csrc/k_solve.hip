@@ -41,8 +41,10 @@ static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the p
 static constexpr int kIncMax = 48;     // incremental solution updates between full solves
 static_assert(kFz <= kB && kB <= kQ, "the low-rank passes are instantiated for kB rows");
 
-// A team of up to kTeamMax workgroups, co-resident by a cooperative launch,
-// may serve one subdomain: its first workgroup (the leader) runs the whole
+// A team of up to kTeamMax workgroups may serve one subdomain (the launch is
+// sized so that the device holds all of its workgroups at once, by the
+// occupancy query; residency is needed for speed only, never for progress,
+// since every wait below is bounded): its first workgroup (the leader) runs the whole
 // iteration; once the active set reaches team_min coordinates, every pass
 // that streams the active-block inverse H or the Gram is split into row
 // slices, one per member (the leader's included), and the leader sums the
@@ -1951,15 +1953,13 @@ int solve_team_size(int sub_count, int m_cap, int precision, int requested) {
     const size_t lds = solve_lds_bytes(m_cap);
     const void *fn = precision == PAM_PREC_F64 ? solve_fn<double>(true) : solve_fn<float>(true);
     if ((precision == PAM_PREC_F64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return 1;
-    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kT, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
-    if (!coop) return 1;
     const long long resident = (long long)per_cu * cus;
     int T = requested >= 2 ? std::min(requested, kTeamMax) : kTeamMax;
     while (T > 1 && round_up(sub_count, 8) * T > resident) T /= 2;
@@ -1988,14 +1988,11 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     FitArgs ka = a;
     void *G = f64 ? (void *)wsp<double>(ctx, BUF_G) : (void *)wsp<float>(ctx, BUF_G);
     void *args[] = {&ka, &G, &H, &scr, (void *)&flags, &tctl};
-    if (T > 1) {
-        // every member of a team waits on the others: all workgroups must be
-        // resident at once, which the cooperative launch guarantees (or refuses)
-        PAM_CHECK_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)(round_up(a.sub_count, 8) * T)), dim3(kT), args,
-                                                 (unsigned)lds, ctx->stream));
-    } else {
-        PAM_CHECK_HIP(hipLaunchKernel(fn, dim3(a.sub_count), dim3(kT), args, lds, ctx->stream));
-    }
+    // A team grid is no larger than what the device holds at once
+    // (solve_team_size), so its workgroups run together on an idle device; an
+    // ordinary launch suffices because no wait depends on residency to end.
+    const unsigned blocks = T > 1 ? (unsigned)(round_up(a.sub_count, 8) * T) : (unsigned)a.sub_count;
+    PAM_CHECK_HIP(hipLaunchKernel(fn, dim3(blocks), dim3(kT), args, lds, ctx->stream));
     PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;
 }
