@@ -285,6 +285,25 @@ pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
                     const pam_dict *dict, const double *beta, int32_t dtype, const void *xq,
                     int64_t Q, void *out, int32_t space, int64_t *n_outside);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): pam_eval with the same
+ * arguments, result and kernels, allocating nothing. The binning workspace
+ * is a fixed 64 MiB device array of the library (one per GPU, set up by
+ * pam_create and held until the process ends) instead of the context's
+ * workspace, and the field tables travel as a kernel argument instead of a
+ * staged upload. Limits, checked on the host before anything is enqueued
+ * (PAM_ERR_CAPACITY beyond them): n_fields <= 8, at most 240 breakpoints over
+ * all fields and axes, and at most 64 MiB of binning workspace (about 12 B
+ * per query plus 24 B per subdomain, 256-byte aligned pieces: up to about 5e6
+ * queries per call). Kernel timing is not recorded. Every call on a GPU
+ * shares that GPU's array and leaves its last contents there (each call
+ * clears what it needs): calls that overlap in time on one GPU (other
+ * streams, other threads) race, and the caller must order them. */
+pam_status pam_eval_noalloc(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
+                            const pam_dict *dict, const double *beta, int32_t dtype,
+                            const void *xq, int64_t Q, void *out, int32_t space,
+                            int64_t *n_outside);
+
 /* ------------------------------------------------------------------------
  * Per-subdomain elastic-net parameters (Sec. 2 after Eq. (elastic): they may
  * differ between subdomains; Exp. 1.2 chooses them independently per

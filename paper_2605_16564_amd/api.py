@@ -400,6 +400,27 @@ def evaluate(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.T
     return out
 
 
+def evaluate_noalloc(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.Tensor,
+                     out: torch.Tensor, q_counts: Optional[Sequence[int]] = None,
+                     sub_bases: Optional[Sequence[int]] = None, space: int = 0,
+                     n_outside: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """evaluate() through pam_eval_noalloc: the library allocates nothing
+    (fixed per-device scratch); the caller passes the output buffer."""
+    if not isinstance(grids, (list, tuple)):
+        grids = [grids]
+    dtype = _query_dtype(xq)
+    Q = int(xq.shape[0])
+    if out.dtype != xq.dtype or out.numel() < Q or not out.is_cuda:
+        raise N.PamError("out must be a device tensor of the query dtype with Q entries")
+    fields, keep = _field_table(grids, Q, q_counts, sub_bases)
+    ds = D.struct()
+    ctx.use_current_stream()
+    N.check(N.lib().pam_eval_noalloc(ctx.h, len(grids), fields, C.byref(ds), _p(beta), dtype,
+                                     _p(xq.contiguous()), Q, _p(out), int(space), _p(n_outside)),
+            "pam_eval_noalloc")
+    return out
+
+
 def evaluate_blend(ctx: Context, grids, D: Dictionary, beta: torch.Tensor, xq: torch.Tensor,
                    blend: float, q_counts: Optional[Sequence[int]] = None,
                    sub_bases: Optional[Sequence[int]] = None, space: int = 0,

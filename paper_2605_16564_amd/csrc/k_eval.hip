@@ -21,6 +21,8 @@
 
 #include <algorithm>
 
+#include <mutex>
+
 #include "pam_internal.h"
 
 namespace pam {
@@ -584,13 +586,75 @@ int field_tables(int n_fields, const pam_field *fields, std::vector<FieldDev> &f
     return n_sub_total;
 }
 
+// The no-alloc evaluation passes its small tables by value (one kernel
+// argument) and clears the histogram in the same kernel.
+static constexpr int kNaFields = 8, kNaAxis = 240;
+struct TablesArg {
+    FieldDev f[kNaFields];
+    double axis[kNaAxis];
+    int32_t n_fields, n_axis, n_sub;
+};
+
+__global__ void __launch_bounds__(kE)
+k_put_tables(TablesArg t, FieldDev *__restrict__ fd, double *__restrict__ ax, int32_t *__restrict__ hist) {
+    const int i = blockIdx.x * kE + threadIdx.x;
+    const int stride = gridDim.x * kE;
+    for (int k = i; k < t.n_fields; k += stride) fd[k] = t.f[k];
+    for (int k = i; k < t.n_axis; k += stride) ax[k] = t.axis[k];
+    for (int k = i; k < t.n_sub; k += stride) hist[k] = 0;
+}
+
+// The same tables in the fixed arrays of TablesArg (no host containers);
+// returns the number of subdomains, or -1 beyond kNaFields / kNaAxis.
+int field_tables_fixed(int n_fields, const pam_field *fields, TablesArg &t) {
+    memset(&t, 0, sizeof(t));
+    if (n_fields > kNaFields) return -1;
+    int n_sub_total = 0, na = 0;
+    for (int f = 0; f < n_fields; ++f) {
+        const pam_field &F = fields[f];
+        FieldDev &d = t.f[f];
+        d.dim = F.dim;
+        int nsub = 1, pos = 0;
+        for (int a = 0; a < 3; ++a) d.n_sub_axis[a] = a < F.dim ? F.n_sub_axis[a] : 1;
+        d.axis_off = na;
+        for (int a = 0; a < F.dim; ++a) {
+            if (na + F.n_sub_axis[a] + 1 > kNaAxis) return -1;
+            for (int i = 0; i <= F.n_sub_axis[a]; ++i) t.axis[na++] = F.axis_x[pos + i];
+            pos += F.n_sub_axis[a] + 1;
+            nsub *= F.n_sub_axis[a];
+        }
+        d.sub_base = F.sub_base;
+        d.q_begin = F.q_begin;
+        d.q_end = F.q_end;
+        n_sub_total = std::max(n_sub_total, F.sub_base + nsub);
+    }
+    t.n_fields = n_fields;
+    t.n_axis = na;
+    t.n_sub = n_sub_total;
+    return n_sub_total;
+}
+
 template <typename TQ>
 pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const pam_dict *dict,
                       const double *beta, bool blended, double blend, const TQ *xq, int64_t Q,
-                      TQ *out, int space, int64_t *n_outside) {
+                      TQ *out, int space, int64_t *n_outside, char *ext_ws = nullptr,
+                      size_t ext_cap = 0) {
     std::vector<FieldDev> fd;
     std::vector<double> axis;
-    const int n_sub_total = field_tables(n_fields, fields, fd, axis);
+    TablesArg ta;   // the no-alloc path's tables (no host containers either)
+    int n_sub_total = 0;
+    size_t n_axis = 0;
+    if (ext_ws) {
+        n_sub_total = field_tables_fixed(n_fields, fields, ta);
+        if (n_sub_total < 0) {
+            set_error("pam_eval_noalloc: more than 8 fields or 240 breakpoints");
+            return PAM_ERR_CAPACITY;
+        }
+        n_axis = (size_t)ta.n_axis;
+    } else {
+        n_sub_total = field_tables(n_fields, fields, fd, axis);
+        n_axis = axis.size();
+    }
     int dim_max = 1;
     for (int f = 0; f < n_fields; ++f) dim_max = std::max(dim_max, fields[f].dim);
     // binned items: queries, or term slots (2^dim per query) in the continuous variant
@@ -599,7 +663,7 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
     const size_t o_fields = take(sizeof(FieldDev) * n_fields);
-    const size_t o_axis = take(sizeof(double) * axis.size());
+    const size_t o_axis = take(sizeof(double) * n_axis);
     const size_t o_owner = take(blended ? 0 : sizeof(int32_t) * Q);
     const size_t o_hist = take(sizeof(int32_t) * n_sub_total);
     const size_t o_base = take(sizeof(int64_t) * n_sub_total);
@@ -611,20 +675,35 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
     const size_t o_chstart = take(sizeof(int64_t) * max_chunks);
     const size_t o_chlen = take(sizeof(int32_t) * max_chunks);
     const size_t o_tval = take(blended ? sizeof(TQ) * slots : 0);
-    pam_status st = ensure(ctx, BUF_EVAL, o);
-    if (st != PAM_OK) return st;
-    char *w = wsp<char>(ctx, BUF_EVAL);
-    // both tables in one staged upload
-    std::vector<char> host(o_owner);
-    memcpy(host.data() + o_fields, fd.data(), sizeof(FieldDev) * n_fields);
-    memcpy(host.data() + o_axis, axis.data(), sizeof(double) * axis.size());
-    if ((st = upload_to(ctx, w, host.data(), o_owner)) != PAM_OK) return st;
-    PAM_CHECK_HIP(hipMemsetAsync(w + o_hist, 0, sizeof(int32_t) * n_sub_total, ctx->stream));
+    pam_status st;
+    char *w;
+    const bool timed = ext_ws == nullptr;   // the no-alloc path creates no timing events
+    if (ext_ws) {
+        if (o > ext_cap) {
+            set_error("pam_eval_noalloc: the binning workspace of this call exceeds the fixed 64 MiB "
+                      "(about 12 B per query plus 24 B per subdomain)");
+            return PAM_ERR_CAPACITY;
+        }
+        w = ext_ws;
+        const int nb = (int)std::min<int64_t>(64, (std::max<int64_t>(n_sub_total, kNaAxis) + kE - 1) / kE);
+        hipLaunchKernelGGL(k_put_tables, dim3(nb), dim3(kE), 0, ctx->stream, ta, (FieldDev *)(w + o_fields),
+                           (double *)(w + o_axis), (int32_t *)(w + o_hist));
+        PAM_CHECK_HIP(hipGetLastError());
+    } else {
+        if ((st = ensure(ctx, BUF_EVAL, o)) != PAM_OK) return st;
+        w = wsp<char>(ctx, BUF_EVAL);
+        // both tables in one staged upload
+        std::vector<char> host(o_owner);
+        memcpy(host.data() + o_fields, fd.data(), sizeof(FieldDev) * n_fields);
+        memcpy(host.data() + o_axis, axis.data(), sizeof(double) * axis.size());
+        if ((st = upload_to(ctx, w, host.data(), o_owner)) != PAM_OK) return st;
+        PAM_CHECK_HIP(hipMemsetAsync(w + o_hist, 0, sizeof(int32_t) * n_sub_total, ctx->stream));
+    }
     EvalTables t;
     t.fields = (const FieldDev *)(w + o_fields);
     t.axis = (const double *)(w + o_axis);
     t.n_fields = n_fields;
-    t.n_axis = (int32_t)axis.size();
+    t.n_axis = (int32_t)n_axis;
     int32_t *owner = (int32_t *)(w + o_owner);
     int32_t *hist = (int32_t *)(w + o_hist);
     int64_t *base = (int64_t *)(w + o_base);
@@ -643,7 +722,7 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
     // contention on the few bins that spatially coherent queries touch
     const int grid_o = (int)std::max<int64_t>(1, std::min<int64_t>((Q + kE - 1) / kE, 512));
     {
-        KernelTimer kt_bin(ctx, PAM_TK_EVAL_BIN);
+        KernelTimer kt_bin(ctx, timed ? PAM_TK_EVAL_BIN : -1);
         if (Q > 0) {
             if (blended) {
                 auto kt = dim_max == 1 ? k_terms<TQ, 1> : dim_max == 2 ? k_terms<TQ, 2> : k_terms<TQ, 3>;
@@ -679,7 +758,7 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
     }
     if (Q == 0) return PAM_OK;
     {
-        KernelTimer kt_eval(ctx, blended ? PAM_TK_BLEND : PAM_TK_EVAL);
+        KernelTimer kt_eval(ctx, !timed ? -1 : blended ? PAM_TK_BLEND : PAM_TK_EVAL);
         if (blended)
             hipLaunchKernelGGL((k_eval_chunks<TQ, true>), dim3((unsigned)max_chunks), dim3(kE), 0,
                                ctx->stream, dict->dim, dict->m_cap, nch, chsub, chstart, chlen,
@@ -694,7 +773,7 @@ pam_status eval_typed(pam_ctx *ctx, int n_fields, const pam_field *fields, const
     }
     if (blended) {
         // the weighted sum is bookkeeping like the binning: timed with it
-        KernelTimer kt_comb(ctx, PAM_TK_EVAL_BIN);
+        KernelTimer kt_comb(ctx, timed ? PAM_TK_EVAL_BIN : -1);
         auto kc = dim_max == 1 ? k_combine<TQ, 1> : dim_max == 2 ? k_combine<TQ, 2> : k_combine<TQ, 3>;
         hipLaunchKernelGGL(kc, dim3(grid_o), dim3(kE), 0, ctx->stream, t, xq, Q, blend,
                            (const TQ *)tval, out, space);
@@ -713,6 +792,57 @@ pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, cons
                           (float *)out, space, n_outside);
     return eval_typed(ctx, n_fields, fields, dict, beta, false, 0.0, (const double *)xq, Q,
                       (double *)out, space, n_outside);
+}
+
+// ---------------------------------------------------------------- no-alloc evaluation
+// The binning workspace of pam_eval_noalloc: one fixed array per GPU, held
+// until the process ends. Host code never uses this name as an address: the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current (eval_scratch_init, called from
+// pam_create) and kept in g_scratch.
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices] = {};
+
+pam_status eval_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("device index beyond the scratch table");
+        return PAM_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device]) return PAM_OK;
+    int cur = -1;
+    PAM_CHECK_HIP(hipGetDevice(&cur));
+    if (cur != device) {
+        set_error("eval_scratch_init: the device is not current");
+        return PAM_ERR_STATE;
+    }
+    void *ptr = nullptr;
+    PAM_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch[device] = ptr;
+    return PAM_OK;
+}
+
+pam_status launch_eval_noalloc(pam_ctx *ctx, int n_fields, const pam_field *fields,
+                               const pam_dict *dict, const double *beta, int dtype, const void *xq,
+                               int64_t Q, void *out, int space, int64_t *n_outside) {
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ws = ctx->device >= 0 && ctx->device < kMaxDevices ? g_scratch[ctx->device] : nullptr;
+    }
+    if (!ws) {
+        set_error("pam_eval_noalloc: the scratch array of this device was not set up");
+        return PAM_ERR_STATE;
+    }
+    if (dtype == 0)
+        return eval_typed(ctx, n_fields, fields, dict, beta, false, 0.0, (const float *)xq, Q,
+                          (float *)out, space, n_outside, (char *)ws, kScratchBytes);
+    return eval_typed(ctx, n_fields, fields, dict, beta, false, 0.0, (const double *)xq, Q,
+                      (double *)out, space, n_outside, (char *)ws, kScratchBytes);
 }
 
 pam_status launch_eval_blend(pam_ctx *ctx, int n_fields, const pam_field *fields,

@@ -73,7 +73,7 @@ static hipEvent_t timing_event(pam_ctx *ctx) {
 }
 
 KernelTimer::KernelTimer(pam_ctx *ctx, int kind) : ctx_(ctx), kind_(kind) {
-    if (!ctx_->timing.on) return;
+    if (!ctx_->timing.on || kind_ < 0) return;
     start_ = timing_event(ctx_);
     if (start_) (void)hipEventRecord(start_, ctx_->stream);
 }
@@ -281,6 +281,11 @@ pam_status pam_create(pam_ctx **out, int device) {
         (void)hipFree(sticky);
         set_error("pam_create: hipMemset failed");
         return PAM_ERR_HIP;
+    }
+    pam_status sst = eval_scratch_init(device);   // once per device: pam_eval_noalloc's array
+    if (sst != PAM_OK) {
+        (void)hipFree(sticky);
+        return sst;
     }
     pam_ctx *c = new pam_ctx();
     c->device = device;
@@ -670,6 +675,19 @@ pam_status pam_eval(pam_ctx *ctx, int32_t n_fields, const pam_field *fields, con
     PAM_REQUIRE(space == 0 || space == 1, "space must be 0 or 1");
     if ((st = check_fields(n_fields, fields, dict, Q)) != PAM_OK) return st;
     return launch_eval(ctx, n_fields, fields, dict, beta, dtype, xq, Q, out, space, n_outside);
+}
+
+pam_status pam_eval_noalloc(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,
+                            const pam_dict *dict, const double *beta, int32_t dtype, const void *xq,
+                            int64_t Q, void *out, int32_t space, int64_t *n_outside) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(beta, "NULL argument");
+    PAM_REQUIRE(Q >= 0 && (Q == 0 || (xq && out)), "query arrays are NULL");
+    PAM_REQUIRE(dtype == 0 || dtype == 1, "dtype must be 0 (f32) or 1 (f64)");
+    PAM_REQUIRE(space == 0 || space == 1, "space must be 0 or 1");
+    if ((st = check_fields(n_fields, fields, dict, Q)) != PAM_OK) return st;
+    return launch_eval_noalloc(ctx, n_fields, fields, dict, beta, dtype, xq, Q, out, space, n_outside);
 }
 
 pam_status pam_eval_blend(pam_ctx *ctx, int32_t n_fields, const pam_field *fields,

@@ -102,7 +102,7 @@ inline int32_t mpad_of(int32_t m_cap) { return (int32_t)round_up((int64_t)m_cap 
 inline int32_t npad_of(int32_t n_max) { return (int32_t)round_up(n_max > 0 ? n_max : 1, 32); }
 
 // Brackets the launches made during its lifetime with timing events of
-// kind `kind` when timing is enabled on the context.
+// kind `kind` when timing is enabled on the context (kind < 0: no events).
 class KernelTimer {
   public:
     KernelTimer(pam_ctx *ctx, int kind);
@@ -181,6 +181,13 @@ pam_status launch_eval(pam_ctx *ctx, int n_fields, const pam_field *fields, cons
 pam_status launch_eval_blend(pam_ctx *ctx, int n_fields, const pam_field *fields,
                              const pam_dict *dict, const double *beta, double blend, int dtype,
                              const void *xq, int64_t Q, void *out, int space, int64_t *n_outside);
+// No-alloc evaluation (pam_eval_noalloc): the scratch array's device address
+// is looked up once per device (with the device current) by
+// eval_scratch_init; launch_eval_noalloc then runs pam_eval's kernels on it.
+pam_status eval_scratch_init(int device);
+pam_status launch_eval_noalloc(pam_ctx *ctx, int n_fields, const pam_field *fields,
+                               const pam_dict *dict, const double *beta, int dtype, const void *xq,
+                               int64_t Q, void *out, int space, int64_t *n_outside);
 pam_status launch_mark_enrich(pam_ctx *ctx, const RefineArgs &a);
 // PAM_ERR_CAPACITY when the marking cannot rank n_max samples per subdomain.
 pam_status mark_check_capacity(int n_max);

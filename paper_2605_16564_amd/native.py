@@ -25,6 +25,7 @@ EXPORTS = [
     "pam_grid_patches", "pam_support_hint", "pam_cnn_labels",
     "pam_eval_blend", "pam_interface_count", "pam_interface_jump", "pam_select_lambda",
     "pam_darcy_solve", "pam_darcy_error", "pam_darcy_coefficient", "pam_darcy_coefficient_cells",
+    "pam_eval_noalloc",
 ]
 TIMING_KINDS = ["gather", "lattice", "assemble", "gram", "solve", "indicator", "mark",
                 "eval_bin", "eval", "cnn", "blend", "jump",
@@ -125,6 +126,8 @@ def lib():
                                  C.POINTER(PamEnetOpts), C.POINTER(PamRefineOpts), P]
         L.pam_eval.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P, C.c_int32,
                                P, C.c_int64, P, C.c_int32, P]
+        L.pam_eval_noalloc.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P,
+                                       C.c_int32, P, C.c_int64, P, C.c_int32, P]
         L.pam_eval_blend.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P,
                                      C.c_double, C.c_int32, P, C.c_int64, P, C.c_int32, P]
         L.pam_interface_count.argtypes = [C.c_int32, C.POINTER(PamField)]
