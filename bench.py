@@ -57,7 +57,7 @@ SLOTS_F64 = 78.6e12 / 2.0
 # HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB device copy), valid only for the
 # kernel source they were taken on (sha256 prefix of its source files).
-TRAFFIC = {("k_solve<float, true>", "facies256"): {"src": "bc19a27042e93647", "bytes_per_launch": 66.07e9}}
+TRAFFIC = {("k_solve<float, false>", "layered3d"): {"src": "d5eae32ff73a90a6", "bytes_per_launch": 1660.3e9}}
 TRAFFIC_SOURCES = ["paper_2605_16564_amd/csrc/k_solve.hip", "paper_2605_16564_amd/csrc/pam_internal.h"]
 
 
@@ -77,12 +77,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="facies256")
+    ap.add_argument("--workload", default="layered3d")
     ap.add_argument("--precision", default=None, help="Gram precision override (f64|f32|bf16)")
     ap.add_argument("--cd-sweeps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-subdomains", type=int, default=8)
-    ap.add_argument("--cpu-sample-rounds", type=int, default=1)
+    ap.add_argument("--cpu-sample-subdomains", type=int, default=12,
+                    help="subdomains of the oracle sample (every round of Alg. 1 on each)")
+    ap.add_argument("--cpu-workers", type=int, default=12,
+                    help="oracle worker processes (one thread each) running beside the GPU extras")
     ap.add_argument("--no-learned", action="store_true", help="no learned warm start")
     ap.add_argument("--train-mosaics", type=int, default=12,
                     help="training fields: mosaics of 8x8 facies256 fields (16384 patches each)")
@@ -110,83 +112,11 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(grid, wl, n_sub_sample: int, rounds: int):
-    """Time the FP64 CPU oracle on a bounded sample of the same workload:
-    Alg. 1 with `rounds` enrichment rounds on `n_sub_sample` interior
-    subdomains, one OpenMP thread per subdomain (the full three rounds take
-    about 290 s per subdomain on one core). Returns the JSON record and the
-    oracle's results (first subdomain, dictionary, coefficients)."""
-    from oracle import oracle as O
-    S = O.partition(grid)
-    n = min(n_sub_sample, len(S["off"]) - 1)
-    # an interior band of subdomains (row 3 of the 8x8 grid) with all facies
-    first = min(3 * grid.n_sub[0], len(S["off"]) - 1 - n)
-    j0, j1 = S["off"][first], S["off"][first + n]
-    sub = dict(off=S["off"][first:first + n + 1] - j0, x=S["x"][j0:j1], y=S["y"][j0:j1],
-               h=S["h"][j0:j1])
-    D = O.init_dictionary(grid, wl.g, wl.m0 + wl.max_rounds * wl.k_top * (2 ** grid.dim - 1))
-    Ds = O.Dictionary(n, D.m_cap, grid.dim)
-    Ds.m = D.m[first:first + n].copy()
-    Ds.c = D.c[first * D.m_cap * grid.dim:(first + n) * D.m_cap * grid.dim].copy()
-    Ds.sigma = D.sigma[first * D.m_cap:(first + n) * D.m_cap].copy()
-    Ds.level = D.level[first * D.m_cap:(first + n) * D.m_cap].copy()
-    eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t0 = time.perf_counter()
-    Do, bo, _, info = O.refine_batch(sub, Ds, wl.lambda1, wl.lambda2, k_top=wl.k_top,
-                                     max_rounds=rounds, m_max=1 << 30, eps_tol=eps)
-    dt = time.perf_counter() - t0
-    fits = int(info["rounds"].sum())
-    rec = {"value": fits / dt, "unit": "subdomain fits/s", "cores": min(threads, n),
-           "kind": "oracle",
-           "sample": f"Alg. 1 with {rounds} of the {wl.max_rounds} enrichment rounds on {n} of "
-                     f"{len(S['off']) - 1} subdomains ({fits} fits up to "
-                     f"M={wl.m0 + rounds * wl.k_top * (2 ** grid.dim - 1)}, {dt:.1f} s, FP64, "
-                     f"one OpenMP thread per subdomain); later rounds are slower per fit"}
-    return rec, (first, n, sub, Do, bo, rounds)
-
-
 def local_field(c, sigma, beta, x):
     """Normalized expansion sum_m beta_m phi_m(x) / sum_m phi_m(x) (FP64)."""
     d2 = ((x[:, None, :] - c[None, :, :]) ** 2).sum(-1)
     phi = np.exp(-d2 / (2.0 * sigma[None, :] ** 2))
     return (phi @ beta) / phi.sum(1)
-
-
-def oracle_check(ctx, api, grid, wl, prec, opts, sample):
-    """Same rounds on the GPU: dictionaries, coefficients and the field's L1
-    error on the sample's owned cells against the oracle's."""
-    import torch
-    first, n, sub, Do, bo, rounds = sample
-    S = api.partition(ctx, grid)
-    D = api.init_lattice(ctx, grid, wl.g, Do.m_cap, wl.sigma_factor)
-    eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
-    beta, _, _, _, _ = api.refine(ctx, S, D, opts, api.RefineOpts(k_top=wl.k_top, max_rounds=rounds,
-                                                                  eps_tol=eps, eta=wl.eta))
-    torch.cuda.synchronize()
-    m = D.m.cpu().numpy()[first:first + n]
-    c = D.c.cpu().numpy()[first:first + n]
-    sg = D.sigma.cpu().numpy()[first:first + n]
-    b = beta.cpu().numpy()[first:first + n]
-    same_dict = bool(np.array_equal(m, Do.m))
-    err, l1g, l1o = 0.0, 0.0, 0.0
-    cell = float(np.prod(grid.cell_size))
-    for s in range(n):
-        M = int(Do.m[s])
-        ref = bo[s * Do.m_cap:s * Do.m_cap + M]
-        co = Do.c[s * Do.m_cap * grid.dim:(s * Do.m_cap + M) * grid.dim].reshape(M, grid.dim)
-        so = Do.sigma[s * Do.m_cap:s * Do.m_cap + M]
-        same_dict &= bool(np.array_equal(c[s, :M], co) and np.array_equal(sg[s, :M], so))
-        err = max(err, float(np.abs(b[s, :M] - ref).max() / np.abs(ref).max()))
-        xs = sub["x"][sub["off"][s]:sub["off"][s + 1]]
-        ys = sub["y"][sub["off"][s]:sub["off"][s + 1]]
-        l1g += float(np.abs(local_field(c[s, :M], sg[s, :M], b[s, :M], xs) - ys).sum()) * cell
-        l1o += float(np.abs(local_field(co, so, ref, xs) - ys).sum()) * cell
-    return {"coef_rel_err_max": err, "gate_coef": 1e-5 if prec == "f32" else None,
-            "field_l1_gpu": l1g, "field_l1_oracle": l1o, "gate_l1": 1e-3,
-            "dictionaries_equal": same_dict,
-            "sample": f"{n} subdomains from {first}, {rounds} enrichment round(s), "
-                      "L1 over their samples' cells"}
 
 
 def train_learned(ctx, api, wl, prec, n_mosaics):
@@ -347,11 +277,10 @@ def sub_problem(api, S, D, lo, hi):
     return Ss, Ds
 
 
-def other_configs(ctx, api, synth, progress):
+def other_configs(ctx, api, synth, args, progress, skip=None):
     """The other configurations as single timed runs (wall clock around
     synchronized calls, kernel split from HIP events): circle64 as 1,024
-    replicas (4,096 FP64 fits), layered3d (1,188 subdomains, FP32 Gram + FP64
-    pass, three enrichment rounds; the same with the BF16 Gram beside it),
+    replicas (4,096 FP64 fits), layered3d (when it is not the headline),
     multifield (5,820 FP32 fits, then 6.4e7 FP32 query evaluations)."""
     import torch
     L1, L2 = synth.LAMBDA1, synth.LAMBDA2
@@ -382,25 +311,25 @@ def other_configs(ctx, api, synth, progress):
                              "kkt_max": float(stn["kkt"].max()), "kernel_ms": tk}
     progress("circle64 replicas done")
 
-    g3 = synth.layered3d()
-    S3 = api.partition(ctx, g3)
-    ktop = np.floor(0.05 * np.diff(S3.off_host)).astype(np.int32)
-    m_cap = 512 + 3 * int(ktop.max()) * 7
+    if skip != "layered3d":
+        g3 = synth.layered3d()
+        S3 = api.partition(ctx, g3)
+        ktop = np.floor(0.05 * np.diff(S3.off_host)).astype(np.int32)
+        m_cap = 512 + 3 * int(ktop.max()) * 7
 
-    def run3(prec):
-        D3 = api.init_lattice(ctx, g3, [8, 8, 8], m_cap)
-        r = api.refine(ctx, S3, D3, api.EnetOpts(L1, L2, prec),
-                       api.RefineOpts(k_top=0, k_top_sub=ktop, max_rounds=3, eps_tol=1e-4))
-        return D3, r
-    for key, prec in (("layered3d", "f32"), ("layered3d_bf16", "bf16")):
-        (D3, (b3, lvl3, rounds3, rs3, st3)), dt, tk = timed(lambda: run3(prec))
+        def run3(prec):
+            D3 = api.init_lattice(ctx, g3, [8, 8, 8], m_cap)
+            r = api.refine(ctx, S3, D3, api.EnetOpts(L1, L2, prec),
+                           api.RefineOpts(k_top=0, k_top_sub=ktop, max_rounds=3, eps_tol=1e-4))
+            return D3, r
+        (D3, (b3, lvl3, rounds3, rs3, st3)), dt, tk = timed(lambda: run3("f32"))
         stn = api.stats_to_numpy(st3)
         fits = int(rounds3.sum().item())
-        out[key] = {"subdomains": D3.n_sub, "fits": fits, "s": dt, "fits_per_s": fits / dt,
-                    "dtype": prec, "centers_final_mean": float(D3.m.double().mean().item()),
-                    "status_ok": bool(np.all(stn["status"] == 0)),
-                    "kkt_max": float(stn["kkt"].max()), "kernel_ms": tk}
-        progress(key + " done")
+        out["layered3d"] = {"subdomains": D3.n_sub, "fits": fits, "s": dt, "fits_per_s": fits / dt,
+                            "dtype": "f32", "centers_final_mean": float(D3.m.double().mean().item()),
+                            "status_ok": bool(np.all(stn["status"] == 0)),
+                            "kkt_max": float(stn["kkt"].max()), "kernel_ms": tk}
+        progress("layered3d done")
 
     grids = synth.multifield()
     parts = [api.partition(ctx, gg) for gg in grids]
@@ -419,6 +348,67 @@ def other_configs(ctx, api, synth, progress):
                          "kkt_max": float(stn["kkt"].max()), "fit_kernel_ms": tk,
                          "eval_kernel_ms": tke}
     progress("multifield done")
+    return out
+
+
+def facies_section(ctx, api, synth, args, progress, headline=None):
+    """The 2-D facies256 workload (8 x 8 subdomains, three rounds, FP32 +
+    FP64 pass) with the parts that exist in two dimensions only: the learned
+    warm start (training, hinted timed steps, gain), per-subdomain parameter
+    selection, the Darcy consumer and the paper's own comparisons. headline:
+    (record, state, context, params, learned record) of an already timed
+    facies256 headline."""
+    import torch
+    prec = synth.workload("facies256").precision
+    use_learned = not args.no_learned
+    params, learned_rec = None, None
+    if headline is None:
+        if use_learned:
+            params, learned_rec = train_learned(ctx, api, synth.workload("facies256"), prec,
+                                                args.train_mosaics)
+            progress("learned warm start trained")
+        rec, res, cs = run_workload(ctx, api, synth, args, "facies256", prec, use_learned, params,
+                                    3, 1, progress)
+        progress(f"facies256 timed: {rec['value']:.1f} fits/s")
+        out = {k: rec[k] for k in ("value", "unit", "ms_per_step", "dtype", "config", "query_evals_per_s",
+                                   "field_l1_log10", "kkt_max", "fit_status_ok", "solve_team",
+                                   "centers_final_mean", "kernels", "roofline", "gram_roofline")}
+        if not args.no_ablations:
+            abl = {}
+            for vname, kw in (("no_learned", dict(hinted=False)), ("fp64", dict(precision="f64")),
+                              ("plain_basis", dict(basis="plain", hinted=False))):
+                if vname == "no_learned" and not use_learned:
+                    continue
+                cs["step"](**kw)
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                ra = cs["step"](**kw)
+                torch.cuda.synchronize()
+                va = int(ra["rounds"].sum().item()) / (time.perf_counter() - ta)
+                l1a = float((cs["w_d"] * (ra["out"].double() - cs["ycell"]).abs()).sum().item()) / cs["area"]
+                abl[vname] = {"value": va, "unit": "fits/s", "ratio_to_facies256": rec["value"] / va,
+                              "field_l1_log10": l1a}
+            out["ablations"] = abl
+            progress("facies256 ablations done")
+    else:
+        rec, res, cs, params, learned_rec = headline
+        out = {}
+    grid, wl = cs["grid"], cs["wl"]
+    if not args.no_select:
+        out["lambda_selection"] = lambda_selection(ctx, api, grid, wl, prec, cs["m_cap"], cs["eps"],
+                                                   cs["xq"], cs["w_d"], cs["ycell"], cs["area"],
+                                                   args.select_alphas, args.select_folds, args.select_ratio)
+        progress("lambda selection done")
+    if not args.no_darcy:
+        out["darcy"] = darcy(ctx, api, grid, res["D"], res["beta"], args.blend)
+        progress("Darcy consumer done")
+    if not args.no_ablations and not args.no_paper_ablations:
+        out["paper_ablations"] = paper_ablations(ctx, api, grid, wl, prec, cs["m_cap"], cs["eps"],
+                                                 cs["xq"], cs["w_d"], cs["ycell"], cs["area"], progress)
+    if use_learned and params is not None:
+        learned_rec["gain_first_fit"] = learned_gain(ctx, api, grid, wl, prec, params)
+        out["learned"] = learned_rec
+        progress("learned gain done")
     return out
 
 
@@ -570,6 +560,221 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def sample_subdomains(n_sub: int, k: int):
+    """k subdomains spread evenly over the numbering (both ends included)."""
+    k = max(1, min(k, n_sub))
+    return sorted({int(round(v)) for v in np.linspace(0, n_sub - 1, k)})
+
+
+def oracle_gate(grid, wl, res, state):
+    """The metric's gate on the sampled subdomains of the timed run: the
+    GPU's dictionaries, element levels and per-round counts against the FP64
+    oracle's (bit-exact), coefficients within 1e-5 of max|beta| (the FP32 /
+    BF16 gate after the FP64 pass; FP64 1e-9), and each subdomain's L1 error
+    over its samples' cells within 1e-3 of the oracle's."""
+    S, D, beta, lvl, rs = state["S"], state["D"], state["beta"], state["lvl"], state["rs"]
+    c, sg, lv = D.c.cpu().numpy(), D.sigma.cpu().numpy(), D.level.cpu().numpy()
+    b, m, el, grs = beta.cpu().numpy(), D.m.cpu().numpy(), lvl.cpu().numpy(), rs.cpu().numpy()
+    cell = float(np.prod(grid.cell_size))
+    coef_tol = 1e-9 if state["prec"] == "f64" else 1e-5
+    out = {"subdomains": [], "coef_rel_err_max": 0.0, "l1_diff_max": 0.0, "dictionaries_equal": True,
+           "gate_coef": coef_tol, "gate_l1": 1e-3}
+    for r in res:
+        s, M = r["sub"], r["m"]
+        n = r["fits"]
+        same = (int(m[s]) == M and np.array_equal(c[s, :M].ravel(), r["c"]) and
+                np.array_equal(sg[s, :M], r["sigma"]) and np.array_equal(lv[s, :M], r["level"]) and
+                np.array_equal(el[S.off_host[s]:S.off_host[s + 1]], r["elem_level"]) and
+                np.array_equal(grs[s, :n, 0], r["round_stats"][:n, 0]) and
+                np.array_equal(grs[s, :n, 3], r["round_stats"][:n, 3]))
+        out["dictionaries_equal"] &= bool(same)
+        err = float("inf")
+        l1g = l1o = float("nan")
+        if same:
+            scale = float(np.abs(r["beta"]).max())
+            err = float(np.abs(b[s, :M] - r["beta"]).max() / scale) if scale > 0 else \
+                float(np.abs(b[s, :M]).max())
+            xs = S.x[S.off_host[s]:S.off_host[s + 1]].cpu().numpy()
+            ys = S.y[S.off_host[s]:S.off_host[s + 1]].cpu().numpy()
+            cs = r["c"].reshape(M, grid.dim)
+            l1g = float(np.abs(local_field(cs, r["sigma"], b[s, :M], xs) - ys).sum()) * cell
+            l1o = float(np.abs(local_field(cs, r["sigma"], r["beta"], xs) - ys).sum()) * cell
+            out["l1_diff_max"] = max(out["l1_diff_max"], abs(l1g - l1o))
+        out["coef_rel_err_max"] = max(out["coef_rel_err_max"], err)
+        out["subdomains"].append({"sub": s, "fits": n, "centers": M, "dictionary_equal": bool(same),
+                                  "coef_rel_err": err, "l1_gpu": l1g, "l1_oracle": l1o})
+    out["gates_pass"] = bool(out["dictionaries_equal"] and out["coef_rel_err_max"] <= coef_tol and
+                             out["l1_diff_max"] <= 1e-3)
+    return out
+
+
+def comparator(ctx, api, grid, wl, prec, m_cap, eps, ktop, subs, cd_sweeps, progress):
+    """The plain GPU fit on sampled subdomains: one launch per subdomain and
+    kernel (batching off, one workgroup), no hint, the workload's precision
+    mode; once with Alg. 1's warm restarts between rounds (the same algorithm
+    unbatched) and once with every refit from zero. fits/s is a rate, so the
+    sample's rate stands for the whole workload's."""
+    import torch
+    S = api.partition(ctx, grid)
+    out = {"subdomains": len(subs)}
+    for name, cold in (("unbatched", False), ("unbatched_cold_refits", True)):
+        fits, secs = 0, 0.0
+        for s in subs:
+            Ss, Ds = sub_problem(api, S, api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor), s, s + 1)
+            o = api.EnetOpts(wl.lambda1, wl.lambda2, prec, cd_sweeps=cd_sweeps, batched=False)
+            ro = api.RefineOpts(k_top=wl.k_top, k_top_sub=None if ktop is None else ktop[s:s + 1],
+                                max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta, cold_rounds=cold)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, r, _, _ = api.refine(ctx, Ss, Ds, o, ro)
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t0
+            fits += int(r.sum().item())
+        out[name] = {"value": fits / secs, "unit": "fits/s", "fits": fits, "s": secs}
+        progress(f"comparator {name} done")
+    return out
+
+
+def solve_roofline(per_kernel, rs_h, rounds_h, st, prec, workload):
+    """Roofline of the solve from the method's own work (the FP64 Cholesky of
+    each round's final support, s^3/3 flops, plus the 2 M s flops of its
+    gradient, per subdomain-round) against the FP64 dense peak; the bytes the
+    kernel streams (its own count of Gram rows, active-block inverse and FP64
+    design passes) against HBM are reported beside it as the streaming
+    efficiency."""
+    ms = per_kernel["solve"]["ms_per_step"]
+    launches = per_kernel["solve"]["launches_per_step"]
+    avg_s = ms / 1e3 / launches
+    flops = 0.0
+    for s in range(rs_h.shape[0]):
+        for r in range(int(rounds_h[s])):
+            M, sup = float(rs_h[s, r, 0]), float(rs_h[s, r, 1])
+            flops += sup ** 3 / 3.0 + 2.0 * M * sup
+    per_launch = flops / launches
+    ach = per_launch / avg_s / 1e12
+    peak = PEAK_MFMA["f64"]
+    team = int(st["team"].max()) > 1
+    kname = "k_solve<" + ("double" if prec == "f64" else "float") + (", true>" if team else ", false>")
+    bytes_launch = float(rs_h[..., 5].sum()) / launches
+    tr = measured_traffic(kname, workload)
+    return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "traffic": None if tr is None else tr / 1e9, "traffic_unit": "GB per launch",
+            "kernel": kname, "launches_per_step": launches, "avg_launch_ms": avg_s * 1e3,
+            "algorithmic_flops_per_launch": per_launch,
+            "work": "sum over the launch's subdomains of s^3/3 + 2 M s (s = the round's final support, "
+                    "M = its centers), FP64",
+            "streaming_efficiency": {"bytes_per_launch": bytes_launch,
+                                     "achieved_gbs": bytes_launch / avg_s / 1e9,
+                                     "frac_of_hbm_peak": bytes_launch / avg_s / 1e9 / PEAK_HBM_GBS}}
+
+
+def run_workload(ctx, api, synth, args, name, prec, use_learned, params, steps, warmup, progress):
+    """Timed steps of one workload: partition, lattice, (hint,) Alg. 1 over
+    every subdomain and round, evaluation at the metric points. Returns the
+    record and the last step's state."""
+    import torch
+    wl = synth.workload(name)
+    grid = wl.grids[0]
+    dev = torch.device("cuda", 0)
+    cell_y = torch.as_tensor(grid.y, dtype=torch.float64, device=dev)
+    per = 2 ** grid.dim - 1
+    S0 = api.partition(ctx, grid, cell_y)
+    ktop = None
+    if not wl.k_top and wl.k_top_frac:
+        ktop = np.floor(wl.k_top_frac * np.diff(S0.off_host)).astype(np.int32)
+    k_max = wl.k_top if wl.k_top else (int(ktop.max()) if ktop is not None else 0)
+    m_cap = wl.m0 + wl.max_rounds * k_max * per
+    pts, wts, cell_of = synth.metric_points(grid, 4 if grid.dim < 3 else 2)
+    xq = torch.as_tensor(pts, dtype=torch.float32, device=dev)
+    w_d = torch.as_tensor(wts, dtype=torch.float64, device=dev)
+    ycell = cell_y[torch.as_tensor(cell_of, device=dev)]
+    Q = xq.shape[0]
+    eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
+    area = float(np.prod([grid.hi[a] - grid.lo[a] for a in range(grid.dim)]))
+
+    def step(batched=True, cold=False, hinted=use_learned, precision=prec, basis="shepard"):
+        from paper_2605_16564_amd import learned
+        S = api.partition(ctx, grid, cell_y)
+        D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor, basis=basis)
+        hint = learned.hint(ctx, params, grid, D, precision="bf16") if hinted else None
+        o = api.EnetOpts(wl.lambda1, wl.lambda2, precision, cd_sweeps=args.cd_sweeps, batched=batched,
+                         support_hint=hint)
+        ro = api.RefineOpts(k_top=wl.k_top, k_top_sub=ktop, max_rounds=wl.max_rounds, eps_tol=eps,
+                            eta=wl.eta, cold_rounds=cold)
+        beta, lvl, rounds, rs, stats = api.refine(ctx, S, D, o, ro)
+        out = api.evaluate(ctx, grid, D, beta, xq)
+        return dict(S=S, D=D, beta=beta, lvl=lvl, rounds=rounds, rs=rs, stats=stats, out=out, prec=precision)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tk = ctx.timing_read(reset=True)
+    ctx.timing(False)
+    elapsed = t1 - t0
+    rounds_h = res["rounds"].cpu().numpy()
+    rs_h = res["rs"].cpu().numpy()
+    st = api.stats_to_numpy(res["stats"])
+    fits_step = int(rounds_h.sum())
+    value = fits_step * steps / elapsed
+    l1 = float((w_d * (res["out"].double() - ycell).abs()).sum().item()) / area
+    n_of = np.diff(res["S"].off_host)
+    gram_flops = 0.0
+    for s in range(res["D"].n_sub):
+        for r in range(int(rounds_h[s])):
+            M = float(rs_h[s, r, 0])
+            gram_flops += float(n_of[s]) * (M + 1.0) * (M + 2.0)   # symmetric (M+1)^2 product
+    per_kernel = {k: {"ms_per_step": v[0] / steps, "launches_per_step": v[1] / steps}
+                  for k, v in tk.items() if v[1] > 0}
+    dominant = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
+    gram = per_kernel["gram"]
+    gram_ach = gram_flops / (gram["ms_per_step"] / 1e3) / 1e12
+    gram_peak = PEAK_MFMA[prec]
+    eval_ms = per_kernel.get("eval", {}).get("ms_per_step", float("nan")) + \
+        per_kernel.get("eval_bin", {}).get("ms_per_step", 0.0)
+    rec = {
+        "metric": "subdomain fits/s",
+        "value": value,
+        "unit": "fits/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": name, "n_subdomains": int(res["D"].n_sub),
+                   "fits_per_step": fits_step, "initial_centers": int(wl.m0),
+                   "max_rounds": wl.max_rounds,
+                   "k_top": wl.k_top if wl.k_top else f"floor({wl.k_top_frac} N_i)",
+                   "queries_per_step": int(Q), "learned_warm_start": bool(use_learned),
+                   "parallelism": "single GPU"},
+        "query_evals_per_s": float(Q) / (eval_ms / 1e3) if eval_ms == eval_ms else None,
+        "field_l1_log10": l1,
+        "kkt_max": float(st["kkt"].max()),
+        "fit_status_ok": bool(np.all(st["status"] == 0)),
+        "solve_team": int(st["team"].max()),
+        "centers_final_mean": float(res["D"].m.double().mean().item()),
+        "kernels": per_kernel,
+        "dominant_kernel": dominant,
+        "roofline": solve_roofline(per_kernel, rs_h, rounds_h, st, prec, name),
+        "gram_roofline": {"bound": "mfma", "achieved": gram_ach, "peak": gram_peak, "unit": "TFLOP/s",
+                          "frac": gram_ach / gram_peak, "kernel": "k_gram_" + prec},
+    }
+    ctx_state = dict(wl=wl, grid=grid, step=step, m_cap=m_cap, eps=eps, ktop=ktop, xq=xq, w_d=w_d,
+                     ycell=ycell, area=area, cell_y=cell_y)
+    return rec, res, ctx_state
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -591,254 +796,85 @@ def main():
         return
     from paper_2605_16564_amd import api, synth
 
+    # the FP64 oracle's worker processes are spawned before anything touches
+    # the GPU; they run the CPU sample later, beside the GPU extras
+    cpu_pool = None
+    if not args.no_cpu_baseline:
+        from oracle import timing
+        cpu_pool = timing.pool(args.cpu_workers)
+    ctx = api.Context(0)
     wl = synth.workload(args.workload)
     prec = args.precision or wl.precision
-    grid = wl.grids[0]
-    ctx = api.Context(0)
-    dev = torch.device("cuda", 0)
-    cell_y = torch.as_tensor(grid.y, dtype=torch.float64, device=dev)
-    per = 2 ** grid.dim - 1
-    m_cap = wl.m0 + wl.max_rounds * wl.k_top * per
-    pts, wts, cell_of = synth.metric_points(grid, 4 if grid.dim < 3 else 2)
-    xq = torch.as_tensor(pts, dtype=torch.float32, device=dev)
-    w_d = torch.as_tensor(wts, dtype=torch.float64, device=dev)
-    ycell = cell_y[torch.as_tensor(cell_of, device=dev)]
-    Q = xq.shape[0]
-    eps = wl.eps_tol_rel * float(np.prod(grid.cell_size))
-    use_learned = not args.no_learned and grid.dim == 2
+    use_learned = not args.no_learned and wl.grids[0].dim == 2
     params, learned_rec = None, None
     if use_learned:
-        from paper_2605_16564_amd import learned
         params, learned_rec = train_learned(ctx, api, wl, prec, args.train_mosaics)
-
-    def step(batched=True, cold=False, hinted=use_learned, precision=prec, basis="shepard"):
-        S = api.partition(ctx, grid, cell_y)
-        D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor, basis=basis)
-        hint = learned.hint(ctx, params, grid, D, precision="bf16") if hinted else None
-        o = api.EnetOpts(wl.lambda1, wl.lambda2, precision, cd_sweeps=args.cd_sweeps, batched=batched,
-                         support_hint=hint)
-        ro = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta,
-                            cold_rounds=cold)
-        beta, lvl, rounds, rs, stats = api.refine(ctx, S, D, o, ro)
-        out = api.evaluate(ctx, grid, D, beta, xq)
-        return S, D, beta, rounds, rs, stats, out
-
-    progress("start" if not use_learned else "learned warm start trained")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    ctx.timing_read(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tk = ctx.timing_read(reset=True)
-    ctx.timing(False)
-    S, D, beta, rounds, rs, stats, out = res
-    elapsed = t1 - t0
-    ms_step = 1e3 * elapsed / args.steps
-    rounds_h = rounds.cpu().numpy()
-    rs_h = rs.cpu().numpy()
-    st = api.stats_to_numpy(stats)
-    fits_step = int(rounds_h.sum())
-    value = fits_step * args.steps / elapsed
-    # field error of the GPU reconstruction (log10 units), metric quadrature
-    area = float(np.prod([grid.hi[a] - grid.lo[a] for a in range(grid.dim)]))
-    l1 = float((w_d * (out.double() - ycell).abs()).sum().item()) / area
-
-    # algorithmic work of the timed steps (per step, from the per-round counts)
-    n_of = np.diff(S.off_host)
-    solve_bytes = float(rs_h[..., 5].sum())
-    gram_flops = 0.0
-    pairs_design = 0.0
-    pairs_ind = 0.0
-    for s in range(D.n_sub):
-        for r in range(int(rounds_h[s])):
-            M = float(rs_h[s, r, 0])
-            gram_flops += float(n_of[s]) * (M + 1.0) * (M + 2.0)   # symmetric (M+1)^2 product
-            pairs_design += 2.0 * n_of[s] * M                      # two exp passes
-            pairs_ind += (2 ** grid.dim) * n_of[s] * M
-    m_final = D.m.cpu().numpy().astype(np.float64)
-    # queries are the metric points (the same count in every cell), so each
-    # subdomain receives its owned cells' share of them
-    owned = np.ones(D.n_sub)
-    ns = list(grid.n_sub[: grid.dim]) + [1] * (3 - grid.dim)
-    s_id = 0
-    for k2 in range(ns[2]):
-        for k1 in range(ns[1]):
-            for k0 in range(ns[0]):
-                kk = (k0, k1, k2)
-                owned[s_id] = np.prod([grid.breaks[a][kk[a] + 1] - grid.breaks[a][kk[a]]
-                                       for a in range(grid.dim)])
-                s_id += 1
-    eval_pairs = float(np.sum(owned / owned.sum() * Q * m_final))
-    per_kernel = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
-                  for k, v in tk.items() if v[1] > 0}
-    dominant = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
-
-    def roofline_for(kind):
-        ms = per_kernel[kind]["ms_per_step"]
-        launches = per_kernel[kind]["launches_per_step"]
-        avg_s = ms / 1e3 / launches
-        if kind == "gram":
-            per_launch = gram_flops / launches
-            ach = per_launch / avg_s / 1e12
-            peak = PEAK_MFMA[prec]
-            return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                    "frac": ach / peak, "traffic": None, "kernel": "k_gram_" + prec}
-        if kind == "eval":
-            # FP32 pair = 7 VALU slots + one exp (4 slots)
-            peak_pairs = SLOTS_F32 / 11.0
-            per_launch = eval_pairs / launches
-            ach = per_launch / avg_s
-            return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
-                    "unit": "Tpair/s", "frac": ach / peak_pairs, "traffic": None,
-                    "kernel": "k_eval_chunks<float>"}
-        if kind == "solve":
-            # the active-set iteration streams the Gram rows and the inverse of
-            # the active block; algorithmic bytes counted by the kernel itself
-            per_launch = solve_bytes / launches
-            ach = per_launch / avg_s / 1e9
-            team = int(st["team"].max()) > 1   # the instance with workgroup teams ran
-            kname = "k_solve<" + ("double" if prec == "f64" else "float") + (", true>" if team else ", false>")
-            tr = measured_traffic(kname, args.workload)
-            return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": ach / PEAK_HBM_GBS,
-                    "traffic": None if tr is None else tr / 1e9,
-                    "traffic_unit": "GB per launch",
-                    "algorithmic": per_launch / 1e9, "kernel": kname}
-        if kind == "indicator":
-            # FP64 pair: software exp (about 20 FP64 slots) + 12 others
-            peak_pairs = SLOTS_F64 / 32.0
-            per_launch = pairs_ind / launches
-            ach = per_launch / avg_s
-            return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
-                    "unit": "Tpair/s", "frac": ach / peak_pairs, "traffic": None,
-                    "kernel": "k_indicator"}
-        if kind == "assemble":
-            peak_pairs = SLOTS_F64 / 32.0 if prec == "f64" else SLOTS_F32 / 11.0
-            per_launch = pairs_design / launches
-            ach = per_launch / avg_s
-            return {"bound": "alu", "achieved": ach / 1e12, "peak": peak_pairs / 1e12,
-                    "unit": "Tpair/s", "frac": ach / peak_pairs, "traffic": None,
-                    "kernel": "k_assemble"}
-        return None
-
-    roof = roofline_for(dominant) or roofline_for("gram")
-    eval_ms = per_kernel.get("eval", {}).get("ms_per_step", float("nan")) + \
-        per_kernel.get("eval_bin", {}).get("ms_per_step", 0.0)
-    rec = {
-        "metric": "subdomain fits/s",
-        "value": value,
-        "unit": "fits/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": prec,
-        "data": "synthetic",
-        "config": {"workload": args.workload, "n_subdomains": int(D.n_sub),
-                   "fits_per_step": fits_step, "initial_centers": int(wl.m0),
-                   "max_rounds": wl.max_rounds, "k_top": wl.k_top, "queries_per_step": int(Q),
-                   "parallelism": "single GPU"},
-        "query_evals_per_s": float(Q) / (eval_ms / 1e3) if eval_ms == eval_ms else None,
-        "field_l1_log10": l1,
-        "kkt_max": float(st["kkt"].max()),
-        "fit_status_ok": bool(np.all(st["status"] == 0)),
-        "solve_team": int(st["team"].max()),   # workgroups per subdomain in the solve
-        "centers_final_mean": float(m_final.mean()),
-        "kernels": per_kernel,
-        "dominant_kernel": dominant,
-        "roofline": roof,
-    }
-    rec["config"]["learned_warm_start"] = bool(use_learned)
+        progress("learned warm start trained")
+    rec, res, cs = run_workload(ctx, api, synth, args, args.workload, prec, use_learned, params,
+                                args.steps, args.warmup, progress)
+    grid, step = cs["grid"], cs["step"]
+    value = rec["value"]
     progress(f"timed steps done: {value:.1f} fits/s")
-    if not args.no_select:
-        rec["lambda_selection"] = lambda_selection(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d,
-                                                   ycell, area, args.select_alphas,
-                                                   args.select_folds, args.select_ratio)
-    progress("lambda selection done")
-    if not args.no_configs:
-        rec["other_configs"] = other_configs(ctx, api, synth, progress)
-    if not args.no_darcy:
-        rec["darcy"] = darcy(ctx, api, grid, D, beta, args.blend)
-    progress("Darcy consumer done")
-    if not args.no_continuity:
-        rec["continuity"] = continuity(ctx, api, grid, D, beta, xq, w_d, ycell, area, args.blend)
-    if use_learned:
-        learned_rec["gain_first_fit"] = learned_gain(ctx, api, grid, wl, prec, params)
-        rec["learned"] = learned_rec
-    progress("continuity done")
+    # the FP64 oracle on sampled subdomains runs in spawned worker processes
+    # (CPU only) while the GPU extras below run
+    subs = sample_subdomains(int(res["D"].n_sub), args.cpu_sample_subdomains)
+    cpu_h = None
+    if cpu_pool is not None:
+        cpu_h = timing.start(cpu_pool, args.workload, subs, args.cpu_workers)
+        progress(f"oracle sample started: {len(subs)} subdomains on {args.cpu_workers} workers")
     if not args.no_ablations:
-        # each pattern switched off alone (one untimed and one timed step; the
-        # unbatched run is one timed step): fits/s and the ratio it costs
+        # the precision pattern switched at a time (one untimed, one timed step)
         abl = {}
-        variants = [("no_learned", dict(hinted=False), 1), ("fp64", dict(precision="f64"), 1),
-                    ("unbatched", dict(batched=False), 0),
-                    ("plain_basis", dict(basis="plain", hinted=False), 1)]
-        for name, kw, warm in variants:
-            if name == "no_learned" and not use_learned:
-                continue
-            for _ in range(warm):
-                step(**kw)
+        alts = [p_ for p_ in ("f64", "f32", "bf16") if p_ != prec]
+        variants = [(p_, dict(precision=p_)) for p_ in alts]
+        if use_learned:
+            variants.insert(0, ("no_learned", dict(hinted=False)))
+        if grid.dim == 2:
+            variants.append(("plain_basis", dict(basis="plain", hinted=False)))
+        for vname, kw in variants:
+            step(**kw)
             torch.cuda.synchronize()
             ta = time.perf_counter()
             ra = step(**kw)
             torch.cuda.synchronize()
-            va = int(ra[3].sum().item()) / (time.perf_counter() - ta)
-            l1a = float((w_d * (ra[6].double() - ycell).abs()).sum().item()) / area
-            abl[name] = {"value": va, "unit": "fits/s", "speedup_of_pattern": value / va,
-                         "field_l1_log10": l1a}
+            va = int(ra["rounds"].sum().item()) / (time.perf_counter() - ta)
+            l1a = float((cs["w_d"] * (ra["out"].double() - cs["ycell"]).abs()).sum().item()) / cs["area"]
+            abl[vname] = {"value": va, "unit": "fits/s", "ratio_to_headline": value / va,
+                          "field_l1_log10": l1a,
+                          "kkt_max": float(api.stats_to_numpy(ra["stats"])["kkt"].max())}
+            progress(f"ablation {vname} done")
         rec["ablations"] = abl
-    progress("ablations done")
-    if not args.no_ablations and not args.no_paper_ablations and grid.dim == 2:
-        rec["paper_ablations"] = paper_ablations(ctx, api, grid, wl, prec, m_cap, eps, xq, w_d, ycell,
-                                                 area, progress)
     if not args.no_comparator:
-        # plain GPU fit: one launch per subdomain and kernel, every refit from
-        # zero, no hint; same path otherwise. The per-subdomain launches are
-        # serial, so the subdomains are run in two halves (the same work) with
-        # a progress line between them
-        torch.cuda.synchronize()
-        tc0 = time.perf_counter()
-        S = api.partition(ctx, grid, cell_y)
-        D = api.init_lattice(ctx, grid, wl.g, m_cap, wl.sigma_factor)
-        o = api.EnetOpts(wl.lambda1, wl.lambda2, prec, cd_sweeps=args.cd_sweeps, batched=False)
-        ro = api.RefineOpts(k_top=wl.k_top, max_rounds=wl.max_rounds, eps_tol=eps, eta=wl.eta,
-                            cold_rounds=True)
-        half = D.n_sub // 2
-        parts = []
-        for lo, hi in ((0, half), (half, D.n_sub)):
-            Sh, Dh = sub_problem(api, S, D, lo, hi)
-            bh, _, rh, _, _ = api.refine(ctx, Sh, Dh, o, ro)
-            torch.cuda.synchronize()
-            parts.append((Dh, bh, rh))
-            progress(f"comparator subdomains {lo}..{hi - 1} done")
-        Dc = api.concat_dicts([p_[0] for p_ in parts])
-        bc = torch.cat([p_[1] for p_ in parts])
-        oc = api.evaluate(ctx, grid, Dc, bc, xq)
-        torch.cuda.synchronize()
-        tc = time.perf_counter() - tc0
-        fits_c = int(sum(int(p_[2].sum().item()) for p_ in parts))
-        l1c = float((w_d * (oc.double() - ycell).abs()).sum().item()) / area
-        rec["comparator"] = {"kind": "plain GPU fit (per-subdomain launches, cold refits, no hint)",
-                             "value": fits_c / tc, "unit": "fits/s", "field_l1_log10": l1c,
-                             "speedup": value / (fits_c / tc)}
-    progress("comparator done")
-    if not args.no_cpu_baseline:
-        base, sample = cpu_baseline(grid, wl, args.cpu_sample_subdomains,
-                                    min(args.cpu_sample_rounds, wl.max_rounds))
+        comp = comparator(ctx, api, grid, cs["wl"], prec, cs["m_cap"], cs["eps"], cs["ktop"], subs,
+                          args.cd_sweeps, progress)
+        comp["speedup_batched_vs_unbatched"] = value / comp["unbatched"]["value"]
+        comp["speedup_vs_cold_unbatched"] = value / comp["unbatched_cold_refits"]["value"]
+        rec["comparator"] = comp
+    if not args.no_continuity:
+        rec["continuity"] = continuity(ctx, api, grid, res["D"], res["beta"], cs["xq"], cs["w_d"],
+                                       cs["ycell"], cs["area"], args.blend)
+        progress("continuity done")
+    if not args.no_configs or args.workload == "facies256":
+        head = (rec, res, cs, params, learned_rec) if args.workload == "facies256" else None
+        fac = facies_section(ctx, api, synth, args, progress, headline=head)
+        if args.workload == "facies256":
+            rec.update(fac)
+        else:
+            rec["facies256"] = fac
+    if not args.no_configs:
+        rec["other_configs"] = other_configs(ctx, api, synth, args, progress, skip=args.workload)
+    if cpu_h is not None:
+        progress("waiting for the oracle sample")
+        base, ores = timing.finish(cpu_h)
         rec["cpu_baseline"] = base
-        rec["oracle_check"] = oracle_check(ctx, api, grid, wl, prec,
-                                           api.EnetOpts(wl.lambda1, wl.lambda2, prec), sample)
+        rec["oracle_check"] = oracle_gate(grid, cs["wl"], ores, res)
+        progress("oracle sample done")
     print(json.dumps(rec))
     ctx.close()
+    if "oracle_check" in rec and not rec["oracle_check"]["gates_pass"]:
+        print("bench.py: the GPU result failed the oracle gate on the sampled subdomains",
+              file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

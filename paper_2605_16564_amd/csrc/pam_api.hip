@@ -142,10 +142,18 @@ static pam_status check_grid(const pam_grid *g, int *n_sub_total) {
     return PAM_OK;
 }
 
+// Workspace of one batched fit launch: PAM_WS_BYTES if set, else 60 % of the
+// device memory free at the call, at most 160 GiB (288 GB of HBM3E per GPU:
+// the 1,188 three-round layered subdomains, ~55 MB each, fit in one launch).
 static size_t ws_budget() {
     const char *e = getenv("PAM_WS_BYTES");
     if (e) return (size_t)strtoull(e, nullptr, 10);
-    return (size_t)48 << 30;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+        (void)hipGetLastError();
+        return (size_t)48 << 30;
+    }
+    return std::min<size_t>((size_t)160 << 30, free_b / 10 * 6);
 }
 
 static size_t wbytes(int prec) { return prec == PAM_PREC_F64 ? 8 : (prec == PAM_PREC_F32 ? 4 : 2); }
