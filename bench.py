@@ -815,6 +815,22 @@ def main():
     grid, step = cs["grid"], cs["step"]
     value = rec["value"]
     progress(f"timed steps done: {value:.1f} fits/s")
+    # the same step without kernel timing: refinement as replays of its
+    # cached graph, then with the graph off (the same launches enqueued
+    # directly), two steps each
+    gr = {}
+    for gname, on in (("graph_replay", True), ("direct_launches", False)):
+        ctx.graphs(on)
+        step()
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(2):
+            rg = step()
+        torch.cuda.synchronize()
+        gr[gname] = {"value": 2 * int(rg["rounds"].sum().item()) / (time.perf_counter() - tg), "unit": "fits/s"}
+    ctx.graphs(True)
+    rec["graph"] = gr
+    progress("graph on/off done")
     # the FP64 oracle on sampled subdomains runs in spawned worker processes
     # (CPU only) while the GPU extras below run
     subs = sample_subdomains(int(res["D"].n_sub), args.cpu_sample_subdomains)

@@ -82,6 +82,16 @@ pam_status pam_set_stream(pam_ctx *ctx, void *stream);
  * non-finite input (a sticky device flag, cleared by this call; the
  * per-subdomain status says which subdomains), else PAM_OK or PAM_ERR_HIP. */
 pam_status pam_sync(pam_ctx *ctx);
+/* Batched launches as HIP graphs (default on): pam_fit_subdomains and
+ * pam_refine capture all of their launches (every round of a refinement,
+ * with the per-subdomain active flags the kernels read on the device: a
+ * subdomain that stops is skipped by every later launch) into one graph on a
+ * private stream, instantiate it once per call shape (pointers, sizes,
+ * options and workspace addresses) and replay it with one hipGraphLaunch on
+ * the context's stream. While kernel timing is on (pam_timing_enable), and
+ * with on = 0, the same launches are enqueued directly. Results are
+ * identical either way. */
+pam_status pam_graph_enable(pam_ctx *ctx, int32_t on);
 /* [host] Message of the last failing call on this thread ("" if none). */
 const char *pam_last_error(void);
 /* [host] Library version string. */

@@ -40,6 +40,10 @@ class Context:
     def sync(self):
         N.check(N.lib().pam_sync(self.h), "pam_sync")
 
+    def graphs(self, on: bool = True):
+        """Fits and refinements as one HIP graph launch each (default on)."""
+        N.check(N.lib().pam_graph_enable(self.h, 1 if on else 0), "pam_graph_enable")
+
     def timing(self, on: bool = True):
         N.check(N.lib().pam_timing_enable(self.h, 1 if on else 0), "pam_timing_enable")
 
@@ -255,9 +259,11 @@ def stats_to_numpy(stats: torch.Tensor) -> np.ndarray:
 
 
 def fit(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts,
-        beta: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None):
-    """a3-a6 for every subdomain; returns (beta [n_sub, m_cap] f64, stats tensor)."""
-    warm = beta is not None
+        beta: Optional[torch.Tensor] = None, stats: Optional[torch.Tensor] = None,
+        warm: Optional[bool] = None):
+    """a3-a6 for every subdomain; returns (beta [n_sub, m_cap] f64, stats tensor).
+    warm: beta holds the starting point (default: when beta is given)."""
+    warm = (beta is not None) if warm is None else warm
     if beta is None:
         beta = torch.zeros((D.n_sub, D.m_cap), dtype=torch.float64, device=D.m.device)
     if stats is None:
@@ -309,18 +315,29 @@ class RefineOpts:
 
 
 def refine(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, ropts: RefineOpts,
-           beta: Optional[torch.Tensor] = None, elem_level: Optional[torch.Tensor] = None):
+           beta: Optional[torch.Tensor] = None, elem_level: Optional[torch.Tensor] = None,
+           out: Optional[dict] = None, warm: Optional[bool] = None):
     """Alg. 1 on every subdomain (D is updated in place).
-    Returns (beta, elem_level, rounds, round_stats [n_sub, R+1, 6], stats)."""
+    Returns (beta, elem_level, rounds, round_stats [n_sub, R+1, 6], stats).
+    out: optional dict of caller-owned outputs (rounds, round_stats, stats)
+    reused instead of new tensors; warm: beta is a warm start (default: when
+    beta is given)."""
     dev = D.m.device
-    warm = beta is not None
+    warm = (beta is not None) if warm is None else warm
     if beta is None:
         beta = torch.zeros((D.n_sub, D.m_cap), dtype=torch.float64, device=dev)
     if elem_level is None:
         elem_level = torch.zeros(int(S.off_host[-1]), dtype=torch.int32, device=dev)
-    rounds = torch.zeros(D.n_sub, dtype=torch.int32, device=dev)
-    rstats = torch.zeros((D.n_sub, ropts.max_rounds + 1, 6), dtype=torch.float64, device=dev)
-    stats = new_stats(D.n_sub, dev)
+    out = out or {}
+    rounds = out.get("rounds")
+    if rounds is None:
+        rounds = torch.zeros(D.n_sub, dtype=torch.int32, device=dev)
+    rstats = out.get("round_stats")
+    if rstats is None:
+        rstats = torch.zeros((D.n_sub, ropts.max_rounds + 1, 6), dtype=torch.float64, device=dev)
+    stats = out.get("stats")
+    if stats is None:
+        stats = new_stats(D.n_sub, dev)
     r = N.PamRefineOpts()
     r.k_top = int(ropts.k_top)
     kts = None

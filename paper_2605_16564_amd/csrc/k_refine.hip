@@ -14,9 +14,13 @@ static constexpr int kIC = 256;  // centers staged per pass
 // Gauss-Legendre per axis at x_T +- h_T/(2 sqrt 3), weights |T| / 2^d, of the
 // squared misfit of the normalized expansion (log10 values, or 10^values).
 // One thread per element; all 2^d points accumulate against each staged
-// center, in FP64 so that marking decisions follow the exact indicator.
+// center, in FP64 so that marking decisions follow the exact indicator. The
+// dimension is a template parameter, so the 2^d points' coordinates and sums
+// stay in registers.
+template <int DIM>
 __global__ void __launch_bounds__(kT)
 k_indicator(RefineArgs a, double *__restrict__ R) {
+    constexpr int NQ = 1 << DIM;
     const int s = blockIdx.y;
     if (!a.active[s]) return;
     const int64_t j0 = a.off[s];
@@ -27,36 +31,39 @@ k_indicator(RefineArgs a, double *__restrict__ R) {
         return;
     }
     const int M = max(0, min(a.m[s], a.m_cap));
-    const int dim = a.dim;
-    const int nq = 1 << dim;
-    __shared__ double sc[kIC * 3];
+    __shared__ double sc[kIC * DIM];
     __shared__ double sa[kIC];
     __shared__ double sb[kIC];
-    double xq[8][3];
-    double num[8], den[8];
+    double xq[NQ][DIM];
+    double num[NQ], den[NQ];
     const bool live = j < N;
     double vol = 1.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        num[q] = 0.0;
+        den[q] = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xq[q][d] = 0.0;
+    }
     if (live) {
         const double off = 0.28867513459481287;  // 1 / (2 sqrt 3)
-        for (int q = 0; q < nq; ++q) {
-            for (int d = 0; d < dim; ++d) {
-                const double hd = a.h[(j0 + j) * dim + d];
-                const double sg = ((q >> d) & 1) ? 1.0 : -1.0;
-                xq[q][d] = a.x[(j0 + j) * dim + d] + sg * off * hd;
-            }
-            num[q] = 0.0;
-            den[q] = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            const double hd = a.h[(j0 + j) * DIM + d];
+            const double xd = a.x[(j0 + j) * DIM + d];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) xq[q][d] = xd + (((q >> d) & 1) ? 1.0 : -1.0) * off * hd;
+            vol *= hd;
         }
-        for (int d = 0; d < dim; ++d) vol *= a.h[(j0 + j) * dim + d];
     }
-    const double *cs = a.c + (size_t)s * a.m_cap * dim;
+    const double *cs = a.c + (size_t)s * a.m_cap * DIM;
     const double *ss = a.sigma + (size_t)s * a.m_cap;
     const double *bs = a.beta + (size_t)s * a.m_cap;
     for (int m0 = 0; m0 < M; m0 += kIC) {
         const int cnt = min(kIC, M - m0);
         __syncthreads();
+        for (int t = threadIdx.x; t < cnt * DIM; t += kT) sc[t] = cs[(size_t)m0 * DIM + t];
         for (int t = threadIdx.x; t < cnt; t += kT) {
-            for (int d = 0; d < dim; ++d) sc[t * 3 + d] = cs[(size_t)(m0 + t) * dim + d];
             const double sg = ss[m0 + t];
             sa[t] = 0.5 / (sg * sg);
             sb[t] = bs[m0 + t];
@@ -65,10 +72,15 @@ k_indicator(RefineArgs a, double *__restrict__ R) {
         if (live) {
             for (int t = 0; t < cnt; ++t) {
                 const double ia = sa[t], bt = sb[t];
-                for (int q = 0; q < nq; ++q) {
+                double cc[DIM];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) cc[d] = sc[t * DIM + d];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
                     double r2 = 0.0;
-                    for (int d = 0; d < dim; ++d) {
-                        const double df = xq[q][d] - sc[t * 3 + d];
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) {
+                        const double df = xq[q][d] - cc[d];
                         r2 += df * df;
                     }
                     const double p = exp(-r2 * ia);
@@ -80,9 +92,10 @@ k_indicator(RefineArgs a, double *__restrict__ R) {
     }
     if (!live) return;
     const double yv = a.y[j0 + j];
-    const double w = vol / (double)nq;
+    const double w = vol / (double)NQ;
     double acc = 0.0;
-    for (int q = 0; q < nq; ++q) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
         const double v = a.basis == PAM_BASIS_PLAIN ? num[q] : num[q] / den[q];
         const double e = a.space == 0 ? v - yv : exp10(v) - exp10(yv);
         acc += w * e * e;
@@ -92,7 +105,8 @@ k_indicator(RefineArgs a, double *__restrict__ R) {
 
 pam_status launch_indicator(pam_ctx *ctx, const RefineArgs &a) {
     dim3 grid((a.n_max + kT - 1) / kT, a.n_sub);
-    hipLaunchKernelGGL(k_indicator, grid, dim3(kT), 0, ctx->stream, a, wsp<double>(ctx, BUF_R));
+    auto kern = a.dim == 1 ? k_indicator<1> : a.dim == 2 ? k_indicator<2> : k_indicator<3>;
+    hipLaunchKernelGGL(kern, grid, dim3(kT), 0, ctx->stream, a, wsp<double>(ctx, BUF_R));
     PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;
 }

@@ -179,3 +179,33 @@ void build_lattice_table(const pam_grid *g, const int32_t *gl, double sigma_fact
 }
 
 }  // namespace pam
+
+namespace pam {
+
+// Small fill and copy kernels: used instead of memset and device-to-device
+// copy nodes wherever the work may be captured into a HIP graph.
+__global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_copy_i32(int32_t *__restrict__ d, const int32_t *__restrict__ s, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) d[i] = s[i];
+}
+
+pam_status launch_fill_u32(pam_ctx *ctx, void *p, uint32_t v, int64_t n) {
+    if (n <= 0) return PAM_OK;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, ctx->stream, (uint32_t *)p, v, n);
+    PAM_CHECK_HIP(hipGetLastError());
+    return PAM_OK;
+}
+
+pam_status launch_copy_i32(pam_ctx *ctx, int32_t *d, const int32_t *s, int64_t n) {
+    if (n <= 0) return PAM_OK;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_copy_i32, dim3(blocks), dim3(256), 0, ctx->stream, d, s, n);
+    PAM_CHECK_HIP(hipGetLastError());
+    return PAM_OK;
+}
+
+}  // namespace pam

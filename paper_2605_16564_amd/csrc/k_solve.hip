@@ -1941,12 +1941,25 @@ pam_status solve_check_capacity(int m_cap, int precision) {
     return PAM_OK;
 }
 
+// The dynamic-LDS limit of both instances of one Gram type, set only when it
+// changes (so that launches inside a graph capture make no attribute calls
+// once the size is settled).
 template <typename TG>
 static pam_status solve_set_lds(size_t lds) {
+    static size_t current = 0;
+    if (current == lds) return PAM_OK;
     for (bool team : {false, true})
         PAM_CHECK_HIP(hipFuncSetAttribute(solve_fn<TG>(team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    current = lds;
     return PAM_OK;
 }
+
+pam_status solve_prepare(int m_cap, int precision) {
+    const size_t lds = solve_lds_bytes(m_cap);
+    return precision == PAM_PREC_F64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds);
+}
+
+size_t solve_team_ctl_bytes(int sub_count) { return (size_t)sub_count * kCtl * sizeof(unsigned long long); }
 
 int solve_team_size(int sub_count, int m_cap, int precision, int requested) {
     if (requested == 1 || sub_count < 1) return 1;
@@ -1977,10 +1990,10 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     unsigned long long *tctl = nullptr;
     if (T > 1) {
         // control words start at zero (no command posted) for every launch
-        const size_t bytes = (size_t)a.sub_count * kCtl * sizeof(unsigned long long);
+        const size_t bytes = solve_team_ctl_bytes(a.sub_count);
         if ((st = ensure(ctx, BUF_TEAM, bytes)) != PAM_OK) return st;
         tctl = wsp<unsigned long long>(ctx, BUF_TEAM);
-        PAM_CHECK_HIP(hipMemsetAsync(tctl, 0, bytes, ctx->stream));
+        if ((st = launch_fill_u32(ctx, tctl, 0u, (int64_t)(bytes / 4))) != PAM_OK) return st;
     }
     const bool f64 = a.precision == PAM_PREC_F64;
     if ((st = f64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return st;

@@ -18,6 +18,10 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 pam_status ensure(pam_ctx *ctx, Buf b, size_t bytes) {
     if (bytes == 0) bytes = 256;
     if (ctx->ws.bytes[b] >= bytes) return PAM_OK;
+    if (ctx->graphs.capturing) {   // workspace is sized before a capture; the caller falls back
+        set_error("workspace growth during a graph capture");
+        return PAM_ERR_STATE;
+    }
     if (ctx->ws.ptr[b]) {
         PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));
         PAM_CHECK_HIP(hipFree(ctx->ws.ptr[b]));
@@ -159,12 +163,18 @@ static size_t ws_budget() {
 static size_t wbytes(int prec) { return prec == PAM_PREC_F64 ? 8 : (prec == PAM_PREC_F32 ? 4 : 2); }
 static size_t gbytes(int prec) { return prec == PAM_PREC_F64 ? 8 : 4; }
 
-// Validate and run a3-a6 for subdomains [0, n_sub) in batches that fit the
-// workspace budget (batched = 0: one subdomain per launch).
-static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
-                          const pam_enet_opts *o, double *beta, pam_fit_stats *stats,
-                          const int32_t *active, int warm_start, const double *h = nullptr) {
+// Launch plan of a3-a6 for subdomains [0, n_sub): the kernel arguments, the
+// batch (subdomains per launch, from the workspace budget; batched = 0: one
+// per launch) and the solve's team size.
+struct FitPlan {
     FitArgs a;
+    int batch = 1;
+};
+
+static FitPlan fit_plan(const pam_samples *S, const pam_dict *D, const pam_enet_opts *o,
+                        double *beta, pam_fit_stats *stats) {
+    FitPlan p;
+    FitArgs &a = p.a;
     memset(&a, 0, sizeof(a));
     a.n_sub = S->n_sub;
     a.dim = S->dim;
@@ -185,11 +195,9 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
     a.precision = o->precision;
     a.cd_sweeps = o->cd_sweeps;
     a.max_iter = o->max_iter;
-    a.warm_start = warm_start;
     a.hint = o->support_hint;
     a.beta = beta;
     a.stats = stats;
-    a.active = active;
     a.basis = D->basis;
     a.team = 1;
     a.team_min = o->team_min > 0 ? o->team_min : 128;
@@ -198,19 +206,40 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
                            (size_t)a.mpad * a.mpad * gbytes(a.precision) +
                            solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad, a.precision, 1) * 8;
     int batch = o->batched ? (int)std::max<size_t>(1, ws_budget() / std::max<size_t>(per_sub, 1)) : 1;
-    batch = std::min(batch, a.n_sub);
-    if (o->batched) a.team = solve_team_size(batch, a.m_cap, a.precision, o->team);
+    p.batch = std::min(batch, a.n_sub);
+    if (o->batched) a.team = solve_team_size(p.batch, a.m_cap, a.precision, o->team);
+    return p;
+}
+
+// Every workspace buffer the plan's launches use, at its final size (so that
+// nothing grows while the launches are captured into a graph).
+static pam_status fit_ensure(pam_ctx *ctx, const FitPlan &p) {
+    const FitArgs &a = p.a;
+    const size_t b = (size_t)p.batch;
     pam_status st;
-    if ((st = ensure(ctx, BUF_WT, (size_t)batch * a.mpad * a.npad * wbytes(a.precision))) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_G, (size_t)batch * a.mpad * a.mpad * gbytes(a.precision))) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_H, (size_t)batch * solve_h_elems(a.m_cap) * 8)) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_VEC, (size_t)batch * solve_scratch_elems(a.m_cap, a.npad, a.precision, a.team) * 8)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_WT, b * a.mpad * a.npad * wbytes(a.precision))) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_G, b * a.mpad * a.mpad * gbytes(a.precision))) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_H, b * solve_h_elems(a.m_cap) * 8)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_VEC, b * solve_scratch_elems(a.m_cap, a.npad, a.precision, a.team) * 8)) != PAM_OK)
+        return st;
     if ((st = ensure(ctx, BUF_FLAGS, (size_t)a.n_sub * 4)) != PAM_OK) return st;
-    PAM_CHECK_HIP(hipMemsetAsync(ctx->ws.ptr[BUF_FLAGS], 0, (size_t)a.n_sub * 4, ctx->stream));
+    if (a.team > 1 && (st = ensure(ctx, BUF_TEAM, solve_team_ctl_bytes(p.batch))) != PAM_OK) return st;
+    return solve_prepare(a.m_cap, a.precision);
+}
+
+// Enqueue a3-a6 of the plan: flags cleared, input check, then per batch the
+// assembly, the Gram and the solve.
+static pam_status fit_enqueue(pam_ctx *ctx, const FitPlan &p, const int32_t *active, int warm_start,
+                              const double *h) {
+    FitArgs a = p.a;
+    a.active = active;
+    a.warm_start = warm_start;
+    pam_status st;
+    if ((st = launch_fill_u32(ctx, ctx->ws.ptr[BUF_FLAGS], 0u, a.n_sub)) != PAM_OK) return st;
     if ((st = launch_check_finite(ctx, a, h)) != PAM_OK) return st;
-    for (int b0 = 0; b0 < a.n_sub; b0 += batch) {
+    for (int b0 = 0; b0 < a.n_sub; b0 += p.batch) {
         a.sub_begin = b0;
-        a.sub_count = std::min(batch, a.n_sub - b0);
+        a.sub_count = std::min(p.batch, a.n_sub - b0);
         {
             KernelTimer kt(ctx, PAM_TK_ASSEMBLE);
             if ((st = launch_assemble(ctx, a)) != PAM_OK) return st;
@@ -224,6 +253,90 @@ static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
             if ((st = launch_solve(ctx, a)) != PAM_OK) return st;
         }
     }
+    return PAM_OK;
+}
+
+// Eager a3-a6 (plan, workspace, launches).
+static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
+                          const pam_enet_opts *o, double *beta, pam_fit_stats *stats,
+                          const int32_t *active, int warm_start, const double *h = nullptr) {
+    const FitPlan p = fit_plan(S, D, o, beta, stats);
+    pam_status st = fit_ensure(ctx, p);
+    if (st != PAM_OK) return st;
+    return fit_enqueue(ctx, p, active, warm_start, h);
+}
+
+// ---------------------------------------------------------------- graphs
+// FNV-1a over the values that shape a call's launches.
+struct KeyHash {
+    uint64_t h = 1469598103934665603ull;
+    void bytes(const void *p, size_t n) {
+        const unsigned char *c = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    }
+    template <class T> void v(const T &x) { bytes(&x, sizeof(x)); }
+};
+
+static void graph_key_common(KeyHash &k, pam_ctx *ctx, const FitPlan &p, const pam_enet_opts *o) {
+    k.v(p.a);   // every kernel argument of the fit (pointers, sizes, parameters, team)
+    k.v(p.batch);
+    k.v(o->batched);
+    for (int b = 0; b < BUF_COUNT; ++b) k.v(ctx->ws.ptr[b]);
+    k.v(ctx->sticky);
+}
+
+// Runs enqueue() as one HIP graph launch on the context's stream: the
+// launches are captured on a private stream into a graph, instantiated and
+// kept by key. With kernel timing on, the launches are enqueued directly
+// instead (timing events recorded inside a captured graph give no elapsed
+// times on this runtime). When a capture cannot be made the work runs
+// eagerly with the same launches.
+template <class F>
+static pam_status graph_run(pam_ctx *ctx, uint64_t key, F &&enqueue) {
+    GraphCache &gc = ctx->graphs;
+    if (!gc.on || ctx->timing.on) return enqueue();
+    hipGraphExec_t exec = nullptr;
+    for (auto &e : gc.entries)
+        if (e.key == key) {
+            exec = e.exec;
+            e.used = ++gc.clock;
+            break;
+        }
+    if (!exec) {
+        if (!gc.capture) PAM_CHECK_HIP(hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking));
+        if (hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return enqueue();
+        }
+        const hipStream_t saved = ctx->stream;
+        ctx->stream = gc.capture;
+        gc.capturing = true;
+        const pam_status st = enqueue();
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(gc.capture, &g);
+        ctx->stream = saved;
+        gc.capturing = false;
+        hipError_t ei = hipErrorUnknown;
+        if (st == PAM_OK && ec == hipSuccess && g) ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            (void)hipGetLastError();
+            exec = nullptr;
+            if (st != PAM_OK && st != PAM_ERR_STATE) return st;   // the call itself failed
+            return enqueue();                                      // capture not possible: eager
+        }
+        if (gc.entries.size() >= 16) {
+            auto lru = std::min_element(gc.entries.begin(), gc.entries.end(),
+                                        [](const GraphCache::Entry &x, const GraphCache::Entry &y) {
+                                            return x.used < y.used;
+                                        });
+            PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));   // it may still be running
+            (void)hipGraphExecDestroy(lru->exec);
+            gc.entries.erase(lru);
+        }
+        gc.entries.push_back({key, exec, ++gc.clock});
+    }
+    PAM_CHECK_HIP(hipGraphLaunch(exec, ctx->stream));
     return PAM_OK;
 }
 
@@ -306,6 +419,9 @@ pam_status pam_destroy(pam_ctx *ctx) {
     if (!ctx) return PAM_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto &e : ctx->graphs.entries) (void)hipGraphExecDestroy(e.exec);
+    ctx->graphs.entries.clear();
+    if (ctx->graphs.capture) (void)hipStreamDestroy(ctx->graphs.capture);
     for (int b = 0; b < BUF_COUNT; ++b)
         if (ctx->ws.ptr[b]) (void)hipFree(ctx->ws.ptr[b]);
     for (auto &p : ctx->timing.pending) {
@@ -341,6 +457,13 @@ pam_status pam_sync(pam_ctx *ctx) {
                   " subdomain fit(s) since the previous pam_sync; see the per-subdomain status");
         return PAM_ERR_NONFINITE;
     }
+    return PAM_OK;
+}
+
+pam_status pam_graph_enable(pam_ctx *ctx, int32_t on) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    ctx->graphs.on = on != 0;
     return PAM_OK;
 }
 
@@ -444,7 +567,13 @@ pam_status pam_fit_subdomains(pam_ctx *ctx, const pam_samples *samples, const pa
     pam_status st = check_ctx(ctx);
     if (st != PAM_OK) return st;
     if ((st = check_fit_args(samples, dict, opts, beta)) != PAM_OK) return st;
-    return run_fit(ctx, samples, dict, opts, beta, stats, nullptr, opts->warm_start);
+    const FitPlan plan = fit_plan(samples, dict, opts, beta, stats);
+    if ((st = fit_ensure(ctx, plan)) != PAM_OK) return st;
+    KeyHash k;
+    k.v(1);   // a single fit
+    graph_key_common(k, ctx, plan, opts);
+    k.v(opts->warm_start);
+    return graph_run(ctx, k.h, [&]() { return fit_enqueue(ctx, plan, nullptr, opts->warm_start, nullptr); });
 }
 
 pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, double *beta,
@@ -459,7 +588,8 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     PAM_REQUIRE(r->space == 0 || r->space == 1, "space must be 0 or 1");
     if ((st = mark_check_capacity(samples->n_max)) != PAM_OK) return st;
     const int n = samples->n_sub;
-    // per-subdomain int tables: active, m0, k_top
+    // per-subdomain int tables: active, m0, k_top (uploaded before the
+    // rounds; the rounds themselves are one graph launch)
     std::vector<int32_t> tab((size_t)3 * n);
     for (int s = 0; s < n; ++s) {
         tab[s] = 1;
@@ -469,9 +599,10 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     int32_t *active = wsp<int32_t>(ctx, BUF_TABLE);
     int32_t *m0 = active + n;
     int32_t *ktop = active + 2 * n;
-    PAM_CHECK_HIP(hipMemcpyAsync(m0, dict->m, (size_t)n * 4, hipMemcpyDeviceToDevice, ctx->stream));
-    int64_t n_tot = samples->off_host[n];
+    const int64_t n_tot = samples->off_host[n];
     if ((st = ensure(ctx, BUF_R, (size_t)std::max<int64_t>(n_tot, 1) * 8)) != PAM_OK) return st;
+    const FitPlan plan = fit_plan(samples, dict, opts, beta, stats);
+    if ((st = fit_ensure(ctx, plan)) != PAM_OK) return st;
     RefineArgs ra;
     memset(&ra, 0, sizeof(ra));
     ra.n_sub = n;
@@ -500,22 +631,35 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     ra.round_stats = r->round_stats;
     ra.stats = stats;
     ra.basis = dict->basis;
-    for (int round = 0; round <= r->max_rounds; ++round) {
-        const int warm = round == 0 ? opts->warm_start : (r->cold_rounds ? 0 : 1);
-        if ((st = run_fit(ctx, samples, dict, opts, beta, stats, active, warm, samples->h)) != PAM_OK)
-            return st;
-        ra.flags = wsp<int32_t>(ctx, BUF_FLAGS);
-        ra.round = round;
-        {
-            KernelTimer kt(ctx, PAM_TK_INDICATOR);
-            if ((st = launch_indicator(ctx, ra)) != PAM_OK) return st;
+    ra.flags = wsp<int32_t>(ctx, BUF_FLAGS);
+    // every round is enqueued up front: subdomains that stop clear their
+    // active flag on the device and every later kernel skips them
+    auto rounds = [&]() -> pam_status {
+        pam_status s2;
+        if ((s2 = launch_copy_i32(ctx, m0, dict->m, n)) != PAM_OK) return s2;
+        for (int round = 0; round <= r->max_rounds; ++round) {
+            const int warm = round == 0 ? opts->warm_start : (r->cold_rounds ? 0 : 1);
+            if ((s2 = fit_enqueue(ctx, plan, active, warm, samples->h)) != PAM_OK) return s2;
+            RefineArgs rr = ra;
+            rr.round = round;
+            {
+                KernelTimer kt(ctx, PAM_TK_INDICATOR);
+                if ((s2 = launch_indicator(ctx, rr)) != PAM_OK) return s2;
+            }
+            {
+                KernelTimer kt(ctx, PAM_TK_MARK);
+                if ((s2 = launch_mark_enrich(ctx, rr)) != PAM_OK) return s2;
+            }
         }
-        {
-            KernelTimer kt(ctx, PAM_TK_MARK);
-            if ((st = launch_mark_enrich(ctx, ra)) != PAM_OK) return st;
-        }
-    }
-    return PAM_OK;
+        return PAM_OK;
+    };
+    KeyHash k;
+    k.v(2);   // a refinement
+    graph_key_common(k, ctx, plan, opts);
+    k.v(ra);
+    k.v(opts->warm_start);
+    k.v(r->cold_rounds);
+    return graph_run(ctx, k.h, rounds);
 }
 
 pam_status pam_select_lambda(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -72,12 +73,26 @@ struct Timing {
 
 }  // namespace pam
 
+namespace pam {
+// Executable graphs of fit / refinement calls, keyed by everything that
+// shapes their launches (pointers, sizes, options, workspace addresses).
+struct GraphCache {
+    struct Entry { uint64_t key; hipGraphExec_t exec; uint64_t used; };
+    std::vector<Entry> entries;
+    uint64_t clock = 0;
+    hipStream_t capture = nullptr;         // private stream the calls are captured on
+    bool on = true;                        // pam_graph_enable
+    bool capturing = false;                // a capture is in progress (workspace frozen)
+};
+}  // namespace pam
+
 struct pam_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     pam::Workspace ws;
     pam::Staging staging;
     pam::Timing timing;
+    pam::GraphCache graphs;
     int32_t *sticky = nullptr;   // device [4]: [0] subdomains met with non-finite input
     bool alive = true;
 };
@@ -144,6 +159,13 @@ pam_status launch_check_finite(pam_ctx *ctx, const FitArgs &a, const double *h);
 pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_gram(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a);
+// Dynamic-LDS attribute of the solve instances for a capacity (host only;
+// call before a graph capture), and the team control bytes of a launch.
+pam_status solve_prepare(int m_cap, int precision);
+size_t solve_team_ctl_bytes(int sub_count);
+// Graph-safe fills and copies (kernels, not memset / copy nodes).
+pam_status launch_fill_u32(pam_ctx *ctx, void *p, uint32_t v, int64_t n_words);
+pam_status launch_copy_i32(pam_ctx *ctx, int32_t *dst, const int32_t *src, int64_t n);
 pam_status solve_check_capacity(int m_cap, int precision);   // LDS of the solve's vectors
 __host__ __device__ size_t solve_h_elems(int m_cap);
 __host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team);
