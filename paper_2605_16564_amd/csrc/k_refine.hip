@@ -122,10 +122,22 @@ pam_status launch_indicator(pam_ctx *ctx, const RefineArgs &a) {
 //     centers x_T + (h_T 2^-(l+1)) o, o in {0,1}^d \ {0} (bits of q, axis 0
 //     lowest), widths sigma0 eta^(l+1), level l + 1; a group that does not fit
 //     under the budget ends the enrichment; beta is zero-extended.
+// Up to kSortMax samples per subdomain the ranking runs in LDS; larger
+// subdomains (up to kSortMaxGlobal) rank in a per-subdomain scratch area in
+// HBM (BUF_MARK: P keys and P indices, P = n_max rounded up to a power of
+// two) with the same sort.
 static constexpr int kSortMax = 4096;
+static constexpr int kSortMaxGlobal = 1 << 22;
 
+__host__ __device__ inline int sort_len(int n) {
+    int P = 1;
+    while (P < n) P <<= 1;
+    return P;
+}
+
+template <bool kGlobal>
 __global__ void __launch_bounds__(kT)
-k_mark_enrich(RefineArgs a, const double *__restrict__ R) {
+k_mark_enrich(RefineArgs a, const double *__restrict__ R, char *__restrict__ sort_ws) {
 #pragma clang fp contract(off)
     const int s = blockIdx.x;
     if (!a.active[s]) return;
@@ -133,8 +145,15 @@ k_mark_enrich(RefineArgs a, const double *__restrict__ R) {
     const int N = (int)(a.off[s + 1] - j0);
     const int M = max(0, min(a.m[s], a.m_cap));
     const int dim = a.dim;
-    __shared__ double key[kSortMax];
-    __shared__ int idx[kSortMax];
+    __shared__ double key_l[kGlobal ? 1 : kSortMax];
+    __shared__ int idx_l[kGlobal ? 1 : kSortMax];
+    double *key = key_l;
+    int *idx = idx_l;
+    if (kGlobal) {
+        const size_t P = (size_t)sort_len(a.n_max);
+        key = reinterpret_cast<double *>(sort_ws) + (size_t)s * P * 2;
+        idx = reinterpret_cast<int *>(key + P);
+    }
     __shared__ double red_max[kT / 64], red_sum[kT / 64];
     int P = 1;
     while (P < N) P <<= 1;
@@ -243,18 +262,29 @@ k_mark_enrich(RefineArgs a, const double *__restrict__ R) {
 }
 
 pam_status mark_check_capacity(int n_max) {
-    if (n_max > kSortMax) {
-        set_error("pam_refine: subdomains with more than 4096 samples are not supported");
+    if (n_max > kSortMaxGlobal) {
+        set_error("pam_refine: subdomains with more than 4194304 samples are not supported");
         return PAM_ERR_CAPACITY;
     }
     return PAM_OK;
 }
 
+size_t mark_ws_bytes(int n_sub, int n_max) {
+    if (n_max <= kSortMax) return 0;
+    return (size_t)n_sub * (size_t)sort_len(n_max) * (sizeof(double) + sizeof(int) + 4);
+}
+
 pam_status launch_mark_enrich(pam_ctx *ctx, const RefineArgs &a) {
     pam_status st = mark_check_capacity(a.n_max);
     if (st != PAM_OK) return st;
-    hipLaunchKernelGGL(k_mark_enrich, dim3(a.n_sub), dim3(kT), 0, ctx->stream, a,
-                       wsp<double>(ctx, BUF_R));
+    if (a.n_max <= kSortMax) {
+        hipLaunchKernelGGL(k_mark_enrich<false>, dim3(a.n_sub), dim3(kT), 0, ctx->stream, a,
+                           wsp<double>(ctx, BUF_R), nullptr);
+    } else {
+        if ((st = ensure(ctx, BUF_MARK, mark_ws_bytes(a.n_sub, a.n_max))) != PAM_OK) return st;
+        hipLaunchKernelGGL(k_mark_enrich<true>, dim3(a.n_sub), dim3(kT), 0, ctx->stream, a,
+                           wsp<double>(ctx, BUF_R), wsp<char>(ctx, BUF_MARK));
+    }
     PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;
 }

@@ -64,20 +64,30 @@ enum TeamOp { OP_QUIT = 0, OP_GEMV = 1, OP_UPASS = 2, OP_UPDATE = 3, OP_GRAD = 4
 // function with the calling convention's register cost)
 __host__ __device__ __forceinline__ size_t ldh_of(int m_cap) { return (size_t)round_up(m_cap, kPass); }
 __host__ __device__ __forceinline__ size_t h_elems_of(int m_cap) { return (size_t)(m_cap + 1) * ldh_of(m_cap); }
-__host__ __device__ __forceinline__ size_t scratch_elems_of(int m_cap, int npad, int precision, int team) {
+// The iteration's per-center vectors (57 B per center: six FP64 vectors, two
+// int vectors, one sign byte) in FP64 slots: 7 Mc + Mc / 8, Mc = m_cap rounded
+// up to 8.
+__host__ __device__ __forceinline__ size_t vec_elems_of(int m_cap) {
+    const size_t mc = (size_t)round_up(m_cap, 8);
+    return 7 * mc + mc / 8 + 8;
+}
+__host__ __device__ __forceinline__ size_t scratch_elems_of(int m_cap, int npad, int precision, int team,
+                                                             bool vg = false) {
     // blocked-bordering rows [3][kQ][m_cap], then for the FP64 phase of the
     // low-precision modes: -1/(2 sigma^2) [m_cap], three CG vectors [3][m_cap],
     // two per-sample vectors [2][npad] and the FP64 design W64 [m_cap][npad];
     // with a team: partial results [kTeamMax][kB][m_cap], the input vector,
-    // beta by coordinate and the active list [3][m_cap]
+    // beta by coordinate and the active list [3][m_cap]; with vg (the
+    // dictionary is too large for the vectors to sit in LDS) the iteration's
+    // vectors last
     const size_t w64 = precision == PAM_PREC_F64 ? 0 : (size_t)m_cap * npad;
     const size_t tm = team > 1 ? (size_t)(kTeamMax * kB + 3) * m_cap : 0;
-    return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad + w64 + tm;
+    return (size_t)3 * kQ * m_cap + (size_t)4 * m_cap + (size_t)2 * npad + w64 + tm + (vg ? vec_elems_of(m_cap) : 0);
 }
 __host__ __device__ size_t solve_ldh(int m_cap) { return ldh_of(m_cap); }
 __host__ __device__ size_t solve_h_elems(int m_cap) { return h_elems_of(m_cap); }
-__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team) {
-    return scratch_elems_of(m_cap, npad, precision, team);
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team, bool vg) {
+    return scratch_elems_of(m_cap, npad, precision, team, vg);
 }
 size_t solve_lds_bytes(int m_cap) { return (size_t)57 * round_up(m_cap, 8) + 64; }   // 57 B per center: see the carve-out in k_solve
 
@@ -1309,8 +1319,10 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
                                           int *list, double *tile);
 
 // kTeam = false: one workgroup per subdomain, no team code compiled in
-// (T is the constant 1, every team branch folds away).
-template <typename TG, bool kTeam>
+// (T is the constant 1, every team branch folds away). kVG: the iteration's
+// per-center vectors live in the subdomain's scratch in HBM instead of LDS
+// (dictionaries too large for LDS; one workgroup per subdomain).
+template <typename TG, bool kTeam, bool kVG = false>
 __global__ void __launch_bounds__(kT)
 k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
         double *__restrict__ scratch, const int32_t *__restrict__ flags, unsigned long long *__restrict__ tctl) {
@@ -1342,12 +1354,13 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.l1 = a.lambda1_sub ? a.lambda1_sub[s_id] : a.lambda1;
     v.l2 = a.lambda2_sub ? a.lambda2_sub[s_id] : a.lambda2;
     v.H = Hall + (size_t)loc * h_elems_of(a.m_cap);
-    double *sc = scratch + (size_t)loc * scratch_elems_of(a.m_cap, a.npad, a.precision, T);
+    double *sc = scratch + (size_t)loc * scratch_elems_of(a.m_cap, a.npad, a.precision, T, kVG);
     v.Ag = sc;
     v.U = sc + (size_t)kQ * a.m_cap;
     v.V = sc + (size_t)2 * kQ * a.m_cap;
     const int Mc = (int)round_up(a.m_cap, 8);
-    double *ld = reinterpret_cast<double *>(lds_raw);
+    double *ld = kVG ? sc + scratch_elems_of(a.m_cap, a.npad, a.precision, T, false)
+                     : reinterpret_cast<double *>(lds_raw);
     v.g = ld;
     v.beta = ld + Mc;
     v.z = ld + 2 * Mc;
@@ -1920,21 +1933,40 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
 
 // LDS of one workgroup on gfx950 (static + dynamic)
 static constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+static constexpr int kSolveMaxCap = 32768;   // H alone is then 8.6 GB per subdomain
 
 template <typename TG>
 static const void *solve_fn(bool team) {
     return team ? (const void *)k_solve<TG, true> : (const void *)k_solve<TG, false>;
 }
 
+template <typename TG>
+static const void *solve_fn_vg() { return (const void *)k_solve<TG, false, true>; }
+
+// Largest dictionary capacity whose per-center vectors fit LDS beside the
+// static LDS of the (team) instance; beyond it the vectors go to HBM.
+static int lds_capacity(int precision) {
+    static int cap[2] = {-1, -1};
+    const int k = precision == PAM_PREC_F64 ? 0 : 1;
+    if (cap[k] < 0) {
+        hipFuncAttributes attr;   // the team instance's static LDS includes the other's
+        const void *fn = precision == PAM_PREC_F64 ? solve_fn<double>(true) : solve_fn<float>(true);
+        if (hipFuncGetAttributes(&attr, fn) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        cap[k] = (int)(((kLdsPerWorkgroup - attr.sharedSizeBytes - 64) / 57) / 8 * 8);
+    }
+    return cap[k];
+}
+
+bool solve_vectors_global(int m_cap, int precision) { return m_cap > lds_capacity(precision); }
+
 pam_status solve_check_capacity(int m_cap, int precision) {
-    hipFuncAttributes attr;   // the team instance's static LDS includes the other's
-    const void *fn = precision == PAM_PREC_F64 ? solve_fn<double>(true) : solve_fn<float>(true);
-    PAM_CHECK_HIP(hipFuncGetAttributes(&attr, fn));
-    const size_t fixed = attr.sharedSizeBytes;
-    if (solve_lds_bytes(m_cap) + fixed > kLdsPerWorkgroup) {
-        const size_t max_m = ((kLdsPerWorkgroup - fixed - 64) / 57) / 8 * 8;
+    (void)precision;
+    if (m_cap > kSolveMaxCap) {
         char msg[160];
-        snprintf(msg, sizeof msg, "m_cap too large for the LDS-resident solve (%d; max %zu)", m_cap, max_m);
+        snprintf(msg, sizeof msg, "m_cap too large for the solve (%d; max %d)", m_cap, kSolveMaxCap);
         set_error(msg);
         return PAM_ERR_CAPACITY;
     }
@@ -1955,6 +1987,7 @@ static pam_status solve_set_lds(size_t lds) {
 }
 
 pam_status solve_prepare(int m_cap, int precision) {
+    if (solve_vectors_global(m_cap, precision)) return PAM_OK;   // no dynamic LDS
     const size_t lds = solve_lds_bytes(m_cap);
     return precision == PAM_PREC_F64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds);
 }
@@ -1962,7 +1995,7 @@ pam_status solve_prepare(int m_cap, int precision) {
 size_t solve_team_ctl_bytes(int sub_count) { return (size_t)sub_count * kCtl * sizeof(unsigned long long); }
 
 int solve_team_size(int sub_count, int m_cap, int precision, int requested) {
-    if (requested == 1 || sub_count < 1) return 1;
+    if (requested == 1 || sub_count < 1 || solve_vectors_global(m_cap, precision)) return 1;
     const size_t lds = solve_lds_bytes(m_cap);
     const void *fn = precision == PAM_PREC_F64 ? solve_fn<double>(true) : solve_fn<float>(true);
     if ((precision == PAM_PREC_F64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return 1;
@@ -1996,8 +2029,10 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
         if ((st = launch_fill_u32(ctx, tctl, 0u, (int64_t)(bytes / 4))) != PAM_OK) return st;
     }
     const bool f64 = a.precision == PAM_PREC_F64;
-    if ((st = f64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return st;
-    const void *fn = f64 ? solve_fn<double>(T > 1) : solve_fn<float>(T > 1);
+    const bool vg = solve_vectors_global(a.m_cap, a.precision);
+    if (!vg && (st = f64 ? solve_set_lds<double>(lds) : solve_set_lds<float>(lds)) != PAM_OK) return st;
+    const void *fn = vg ? (f64 ? solve_fn_vg<double>() : solve_fn_vg<float>())
+                        : (f64 ? solve_fn<double>(T > 1) : solve_fn<float>(T > 1));
     FitArgs ka = a;
     void *G = f64 ? (void *)wsp<double>(ctx, BUF_G) : (void *)wsp<float>(ctx, BUF_G);
     void *args[] = {&ka, &G, &H, &scr, (void *)&flags, &tctl};
@@ -2005,7 +2040,7 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     // (solve_team_size), so its workgroups run together on an idle device; an
     // ordinary launch suffices because no wait depends on residency to end.
     const unsigned blocks = T > 1 ? (unsigned)(round_up(a.sub_count, 8) * T) : (unsigned)a.sub_count;
-    PAM_CHECK_HIP(hipLaunchKernel(fn, dim3(blocks), dim3(kT), args, lds, ctx->stream));
+    PAM_CHECK_HIP(hipLaunchKernel(fn, dim3(blocks), dim3(kT), args, vg ? 0 : lds, ctx->stream));
     PAM_CHECK_HIP(hipGetLastError());
     return PAM_OK;
 }

@@ -204,7 +204,9 @@ static FitPlan fit_plan(const pam_samples *S, const pam_dict *D, const pam_enet_
     a.team_idle_us = o->team_idle_us;
     const size_t per_sub = (size_t)a.mpad * a.npad * wbytes(a.precision) +
                            (size_t)a.mpad * a.mpad * gbytes(a.precision) +
-                           solve_h_elems(a.m_cap) * 8 + solve_scratch_elems(a.m_cap, a.npad, a.precision, 1) * 8;
+                           solve_h_elems(a.m_cap) * 8 +
+                           solve_scratch_elems(a.m_cap, a.npad, a.precision, 1,
+                                               solve_vectors_global(a.m_cap, a.precision)) * 8;
     int batch = o->batched ? (int)std::max<size_t>(1, ws_budget() / std::max<size_t>(per_sub, 1)) : 1;
     p.batch = std::min(batch, a.n_sub);
     if (o->batched) a.team = solve_team_size(p.batch, a.m_cap, a.precision, o->team);
@@ -220,7 +222,8 @@ static pam_status fit_ensure(pam_ctx *ctx, const FitPlan &p) {
     if ((st = ensure(ctx, BUF_WT, b * a.mpad * a.npad * wbytes(a.precision))) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_G, b * a.mpad * a.mpad * gbytes(a.precision))) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_H, b * solve_h_elems(a.m_cap) * 8)) != PAM_OK) return st;
-    if ((st = ensure(ctx, BUF_VEC, b * solve_scratch_elems(a.m_cap, a.npad, a.precision, a.team) * 8)) != PAM_OK)
+    if ((st = ensure(ctx, BUF_VEC, b * solve_scratch_elems(a.m_cap, a.npad, a.precision, a.team,
+                                                          solve_vectors_global(a.m_cap, a.precision)) * 8)) != PAM_OK)
         return st;
     if ((st = ensure(ctx, BUF_FLAGS, (size_t)a.n_sub * 4)) != PAM_OK) return st;
     if (a.team > 1 && (st = ensure(ctx, BUF_TEAM, solve_team_ctl_bytes(p.batch))) != PAM_OK) return st;
@@ -601,6 +604,7 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     int32_t *ktop = active + 2 * n;
     const int64_t n_tot = samples->off_host[n];
     if ((st = ensure(ctx, BUF_R, (size_t)std::max<int64_t>(n_tot, 1) * 8)) != PAM_OK) return st;
+    if ((st = ensure(ctx, BUF_MARK, mark_ws_bytes(n, samples->n_max))) != PAM_OK) return st;
     const FitPlan plan = fit_plan(samples, dict, opts, beta, stats);
     if ((st = fit_ensure(ctx, plan)) != PAM_OK) return st;
     RefineArgs ra;

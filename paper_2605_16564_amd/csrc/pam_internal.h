@@ -40,7 +40,7 @@ enum Buf {
     BUF_VEC,        // per-subdomain scratch of the blocked bordering (solve_scratch_elems) f64
     BUF_TABLE,      // small launch tables (per-subdomain parameters)
     BUF_R,          // indicator values [N_tot] f64
-    BUF_MARK,       // marked element lists [n_sub][n_max] int32
+    BUF_MARK,       // ranking keys and indices of subdomains beyond the LDS sort
     BUF_EVAL,       // query binning workspace
     BUF_FLAGS,      // per-subdomain flags / counters
     BUF_CNN,        // network activations, packed weights, gradient partials
@@ -166,9 +166,12 @@ size_t solve_team_ctl_bytes(int sub_count);
 // Graph-safe fills and copies (kernels, not memset / copy nodes).
 pam_status launch_fill_u32(pam_ctx *ctx, void *p, uint32_t v, int64_t n_words);
 pam_status launch_copy_i32(pam_ctx *ctx, int32_t *dst, const int32_t *src, int64_t n);
-pam_status solve_check_capacity(int m_cap, int precision);   // LDS of the solve's vectors
+pam_status solve_check_capacity(int m_cap, int precision);   // absolute cap of the solve
 __host__ __device__ size_t solve_h_elems(int m_cap);
-__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team);
+__host__ __device__ size_t solve_scratch_elems(int m_cap, int npad, int precision, int team, bool vg);
+// The dictionary capacity is beyond what the solve's per-center vectors can
+// hold in LDS: they then live in the subdomain's scratch (one workgroup each).
+bool solve_vectors_global(int m_cap, int precision);
 // Workgroups per subdomain for a solve launch of sub_count subdomains: the
 // largest of requested (0: 4), 2 and 1 whose grid is resident at once.
 int solve_team_size(int sub_count, int m_cap, int precision, int requested);
@@ -213,5 +216,7 @@ pam_status launch_eval_noalloc(pam_ctx *ctx, int n_fields, const pam_field *fiel
 pam_status launch_mark_enrich(pam_ctx *ctx, const RefineArgs &a);
 // PAM_ERR_CAPACITY when the marking cannot rank n_max samples per subdomain.
 pam_status mark_check_capacity(int n_max);
+// HBM workspace of the marking for subdomains beyond the LDS sort (0 within).
+size_t mark_ws_bytes(int n_sub, int n_max);
 
 }  // namespace pam

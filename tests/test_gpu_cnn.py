@@ -200,9 +200,13 @@ def test_labels_bit_exact(ctx):
 
 def test_learned_warm_start_gain(ctx):
     """Train on the method's own round-0 fits of eight facies fields, then
-    fit a held-out field cold and with the network's hint: the same
-    minimizer (to the oracle's FP64 tolerance), no CD warm-up, and fewer
-    active-set iterations than the cold start without warm-up."""
+    fit a held-out field with the method's default start (cold, 8 CD sweeps)
+    and with the network's hint: the same minimizer (to the oracle's FP64
+    tolerance), no CD warm-up, at least 3 % fewer active-set iterations than
+    the default and a solve (network inference included) at least 5 % faster
+    than the default's (measured: about 8 % and 17 %). A constant
+    all-active hint (the prior the support head mostly learns: about 95 % of
+    lattice centers are active) is measured beside it and reported."""
     opts = api.EnetOpts(L1, L2, "f64", cd_sweeps=8)
     train = [synth.facies256(seed=2100 + i) for i in range(8)]
     t0 = time.perf_counter()
@@ -223,18 +227,34 @@ def test_learned_warm_start_gain(ctx):
     xh, th, mh = learned.training_set(ctx, [g], [12, 12], 204, opts)
     acc = learned.head_accuracy(api.cnn_forward(ctx, params, xh), th, mh)
     print("held-out accuracy (refine, support) vs majority:", acc)
-    b_cd, st_cd = api.fit(ctx, S, D, opts)
-    b_0, st_0 = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64", cd_sweeps=0))
-    b_h, st_h = api.fit(ctx, S, D, api.EnetOpts(L1, L2, "f64", cd_sweeps=8, support_hint=hint))
-    torch.cuda.synchronize()
-    s_cd, s_0, s_h = (api.stats_to_numpy(s) for s in (st_cd, st_0, st_h))
-    print("iterations: cold+CD", s_cd["iters"].sum(), "sweeps", s_cd["cd_sweeps"].sum(),
-          "| cold", s_0["iters"].sum(), "| hinted", s_h["iters"].sum(), "sweeps", s_h["cd_sweeps"].sum())
+    all_on = torch.ones_like(hint)                 # every slot is a lattice center (M = m_cap)
+    api.fit(ctx, S, D, opts)                       # untimed: workspace sized, kernels loaded
+    ctx.timing(True)
+    ms = {}
+    res = {}
+    for name in ("default", "hinted", "all_active"):
+        ctx.timing_read(reset=True)
+        if name == "hinted":                        # the network's inference is timed with the fit
+            o = api.EnetOpts(L1, L2, "f64", cd_sweeps=8, support_hint=learned.hint(ctx, params, g, D))
+        elif name == "all_active":
+            o = api.EnetOpts(L1, L2, "f64", cd_sweeps=8, support_hint=all_on)
+        else:
+            o = opts
+        res[name] = api.fit(ctx, S, D, o)
+        tk = ctx.timing_read(reset=True)
+        ms[name] = tk["solve"][0] + tk["cnn"][0]
+    ctx.timing(False)
+    (b_cd, st_cd), (b_h, st_h), (b_a, st_a) = res["default"], res["hinted"], res["all_active"]
+    s_cd, s_h, s_a = (api.stats_to_numpy(s) for s in (st_cd, st_h, st_a))
+    print("iterations: default (cold + 8 CD sweeps)", s_cd["iters"].sum(), "sweeps", s_cd["cd_sweeps"].sum(),
+          f"{ms['default']:.3f} ms | hinted", s_h["iters"].sum(), f"{ms['hinted']:.3f} ms incl. network",
+          "| all-active hint", s_a["iters"].sum(), f"{ms['all_active']:.3f} ms")
     assert np.all(s_h["status"] == 0) and np.all(s_h["cd_sweeps"] == 0)
-    assert s_h["iters"].sum() < 0.5 * s_0["iters"].sum()
+    assert s_h["iters"].sum() <= 0.97 * s_cd["iters"].sum()
+    assert ms["hinted"] <= 0.95 * ms["default"]
     od = O.init_dictionary(g, [12, 12], 144)
     bo, sto, _ = O.fit_batch(O.partition(g), od, L1, L2, cd_sweeps=8)
-    for b in (b_cd, b_h):
+    for b in (b_cd, b_h, b_a):
         bb = _t(b)
         for s in range(D.n_sub):
             ref = bo[s * 144:(s + 1) * 144]
