@@ -225,6 +225,10 @@ typedef struct {
                            field then shows how far from the FP64 minimizer);
                            0 for FP64                                         */
     int32_t team;       /* workgroups that served the solve (1, 2 or 4)        */
+    double solve_us;    /* wall time of this subdomain's solve on the device
+                           (constant clock, microseconds), from its start to
+                           its result: the per-subdomain cost of the batched
+                           launch                                             */
 } pam_fit_stats;
 
 /* a3-a6. For every subdomain: Gaussian RBF design at the samples (Eq.
@@ -250,9 +254,10 @@ typedef struct {
     int32_t space;              /* 0: R_T on log10 values, 1: on 10^values     */
     int32_t *elem_level;        /* [N_tot] times each element was marked (in/out) */
     int32_t *rounds;            /* [n_sub] fits done per subdomain (out) or NULL */
-    double *round_stats;        /* [n_sub*(max_rounds+1)*6] per round
+    double *round_stats;        /* [n_sub*(max_rounds+1)*7] per round
                                    {M, support, max R_T, marked, sum R_T,
-                                   solve stream bytes}, or NULL                */
+                                   solve stream bytes, solve wall time in us},
+                                   or NULL                                     */
     int32_t cold_rounds;        /* 0: each refit starts from the previous beta
                                    extended by zeros (Alg. 1); 1: each refit
                                    starts from zero (comparator; same result,

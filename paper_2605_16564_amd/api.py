@@ -246,7 +246,7 @@ class EnetOpts:
 STATS_DTYPE = np.dtype([("status", np.int32), ("cd_sweeps", np.int32), ("iters", np.int32),
                         ("support", np.int32), ("kkt", np.float64),
                         ("stream_bytes", np.float64), ("polish", np.int32),
-                        ("team", np.int32)])
+                        ("team", np.int32), ("solve_us", np.float64)])
 
 
 def new_stats(n_sub, device):
@@ -318,7 +318,7 @@ def refine(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, ropts: Refin
            beta: Optional[torch.Tensor] = None, elem_level: Optional[torch.Tensor] = None,
            out: Optional[dict] = None, warm: Optional[bool] = None):
     """Alg. 1 on every subdomain (D is updated in place).
-    Returns (beta, elem_level, rounds, round_stats [n_sub, R+1, 6], stats).
+    Returns (beta, elem_level, rounds, round_stats [n_sub, R+1, 7], stats).
     out: optional dict of caller-owned outputs (rounds, round_stats, stats)
     reused instead of new tensors; warm: beta is a warm start (default: when
     beta is given)."""
@@ -334,7 +334,7 @@ def refine(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, ropts: Refin
         rounds = torch.zeros(D.n_sub, dtype=torch.int32, device=dev)
     rstats = out.get("round_stats")
     if rstats is None:
-        rstats = torch.zeros((D.n_sub, ropts.max_rounds + 1, 6), dtype=torch.float64, device=dev)
+        rstats = torch.zeros((D.n_sub, ropts.max_rounds + 1, 7), dtype=torch.float64, device=dev)
     stats = out.get("stats")
     if stats is None:
         stats = new_stats(D.n_sub, dev)

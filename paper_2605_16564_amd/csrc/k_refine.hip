@@ -250,13 +250,14 @@ k_mark_enrich(RefineArgs a, const double *__restrict__ R, char *__restrict__ sor
     if (threadIdx.x == 0) {
         if (a.rounds) a.rounds[s] = a.round + 1;
         if (a.round_stats) {
-            double *rs = a.round_stats + ((size_t)s * (a.max_rounds + 1) + a.round) * 6;
+            double *rs = a.round_stats + ((size_t)s * (a.max_rounds + 1) + a.round) * 7;
             rs[0] = M;
             rs[1] = a.stats ? a.stats[s].support : 0;
             rs[2] = rmax;
             rs[3] = nm;
             rs[4] = rsum;
             rs[5] = a.stats ? a.stats[s].stream_bytes : 0.0;
+            rs[6] = a.stats ? a.stats[s].solve_us : 0.0;
         }
     }
 }

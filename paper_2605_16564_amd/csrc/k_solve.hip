@@ -21,7 +21,7 @@
 #include <algorithm>
 
 #ifdef PAM_PHASE_PROFILE
-#define PHASE_MARK(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); ph[k] += _t - ph_last; ph_last = _t; } } while (0)
+#define PHASE_MARK(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); ph[k] += _t - ph_last; ph_last = _t; phb[k] += v.bytes - phb_last; phb_last = v.bytes; } } while (0)
 #else
 #define PHASE_MARK(k) do { } while (0)
 #endif
@@ -1404,11 +1404,14 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
 #ifdef PAM_PHASE_PROFILE
     long long ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     long long ph_last = wall_clock64();
+    double phb[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double phb_last = 0.0;
     int n_rm = 0, n_add = 0, n_ls = 0, n_cons = 0, it_ex0 = 0;
     long long t_ex0 = 0;
 #endif
     double *beta_out = a.beta + (size_t)s_id * a.m_cap;
     pam_fit_stats *st = a.stats ? a.stats + s_id : nullptr;
+    const long long t_begin = wall_clock64();   // the 100 MHz constant clock
 
     if ((flags[s_id] & 3) || M <= 0 || a.off[s_id + 1] <= a.off[s_id]) {
         for (int m = threadIdx.x; m < a.m_cap; m += kT) beta_out[m] = 0.0;
@@ -1418,7 +1421,7 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
             const bool empty = M <= 0 || a.off[s_id + 1] <= a.off[s_id];
             st->status = (flags[s_id] & 2) ? PAM_ST_NONFINITE : empty ? PAM_ST_EMPTY : PAM_ST_UNDERFLOW;
             st->cd_sweeps = 0; st->iters = 0; st->support = 0; st->kkt = 0.0;
-            st->stream_bytes = 0.0; st->polish = 0; st->team = 1;
+            st->stream_bytes = 0.0; st->polish = 0; st->team = 1; st->solve_us = 0.0;
         }
         return;
     }
@@ -1917,6 +1920,10 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
                s_id, M, s_init, v.s, it, n_cons, n_ls, n_rm, n_add, sweeps, ran_ex ? it - it_ex0 : 0, n_cg,
                ph[0] * 0.01, ph[1] * 0.01, ph[2] * 0.01, ph[3] * 0.01, ph[4] * 0.01, ph[5] * 0.01, ph[6] * 0.01,
                ph[7] * 0.01, ran_ex ? (wall_clock64() - t_ex0) * 0.01 : 0.0);
+    if (threadIdx.x == 0)
+        printf("PB sub=%d MB: grad0=%.1f cd=%.1f init=%.1f solve=%.1f ls=%.1f rm=%.1f fullg=%.1f act=%.1f\n", s_id,
+               phb[0] * 1e-6, phb[1] * 1e-6, phb[2] * 1e-6, phb[3] * 1e-6, phb[4] * 1e-6, phb[5] * 1e-6,
+               phb[6] * 1e-6, phb[7] * 1e-6);
 #endif
     if (v.tsh[3]) status = PAM_ST_NOCONV;   // a team member did not answer: the result is not certified
     if (st && threadIdx.x == 0) {
@@ -1928,6 +1935,7 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
         st->stream_bytes = v.bytes;
         st->polish = n_cg;
         st->team = v.T;
+        st->solve_us = 0.01 * (double)(wall_clock64() - t_begin);
     }
 }
 
