@@ -4,8 +4,10 @@ one center per element (1,024, width h = 1/32), K_top = 204, eta = 1/2, five
 enrichment rounds without a stopping test (eps_tol = 0), so the center counts
 run 1024, 1636, 2248, 2860, 3472, 4084 as in the table; lambda1 = 4.59e-4,
 lambda2 = 4.64e-6. The paper's Case 1/2 fields are not available: the field is
-the circle of the circle workload (log10 K = 3 inside r = 0.3 at (0.5, 0.5), 0
-outside) on the 32 x 32 mesh. Reference of the GPU's large-dictionary test.
+a three-facies field on the 32 x 32 mesh, generated as the facies workload
+(seed 2010): a symmetric field such as the circle would make many indicator
+values tie exactly, so that the marking could legitimately differ between
+two correct computations. Reference of the GPU's large-dictionary test.
 
 Per round: center count, support, largest indicator, marked count; then the
 SHA-256 of the final dictionary (centers, widths, levels as little-endian
@@ -33,7 +35,7 @@ OUT = Path(__file__).resolve().parent / "table2_refine5.txt"
 
 
 def main():
-    g = synth.circle64(n=32, n_sub=1, overlap=0.0)
+    g = synth.facies256(seed=2010, n=32, n_sub=1)
     S = O.partition(g)
     D = O.init_dictionary(g, [32, 32], M_CAP)
     Dr, beta, lvl, info = O.refine_batch(S, D, synth.LAMBDA1, synth.LAMBDA2, k_top=204,
@@ -55,7 +57,7 @@ def main():
     l1 = float(np.sum(wts * np.abs(v - g.y[cell_of])))
     rs = info["round_stats"][0]
     nr = int(info["rounds"][0])
-    lines = ["# FP64 oracle, Table 2 structure on the 32 x 32 circle field; written by "
+    lines = ["# FP64 oracle, Table 2 structure on a 32 x 32 facies field; written by "
              "make_table2_refine.py (do not edit)",
              f"# m_cap {M_CAP}",
              f"status {int(info['status'][0])}",
