@@ -35,6 +35,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 from pathlib import Path
 
@@ -779,8 +780,22 @@ def run_workload(ctx, api, synth, args, name, prec, use_learned, params, steps, 
     return rec, res, ctx_state
 
 
+def _read_tune_cache():
+    path = os.environ.get("PAM_TUNE_CACHE")
+    if not path or not os.path.exists(path):
+        return []
+    with open(path) as f:
+        return [json.loads(line) for line in f if line.strip()]
+
+
 def main():
     args = parse()
+    # the Gram tuner's choices go to a fresh JSON-lines file the record reads
+    if "PAM_TUNE_CACHE" not in os.environ:
+        fd, tpath = tempfile.mkstemp(prefix="pam_tune_", suffix=".jsonl")
+        os.close(fd)
+        os.unlink(tpath)
+        os.environ["PAM_TUNE_CACHE"] = tpath
     if args.gpus != 1:
         print(f"bench.py: this build runs the hot path on one GPU; --gpus {args.gpus} is not "
               "supported (see the sharding notes in DESIGN.md)", file=sys.stderr)
@@ -835,6 +850,28 @@ def main():
     ctx.graphs(True)
     rec["graph"] = gr
     progress("graph on/off done")
+    # the FP32/BF16 Gram path: the tuner's choice per (precision, padded M,
+    # padded N) bucket, and one timed step with each path forced (same bits)
+    if prec != "f64":
+        gp = {"tuner": _read_tune_cache()}
+        for mode in ("materialized", "fused"):
+            ctx.gram_path(mode)
+            step()
+            torch.cuda.synchronize()
+            ctx.timing(True)
+            ctx.timing_read(reset=True)
+            tg = time.perf_counter()
+            rg = step()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - tg
+            tkg = ctx.timing_read(reset=True)
+            ctx.timing(False)
+            gp[mode] = {"value": int(rg["rounds"].sum().item()) / dt, "unit": "fits/s",
+                        "assemble_ms": tkg["assemble"][0], "gram_ms": tkg["gram"][0],
+                        "same_coefficients": bool(torch.equal(rg["beta"], res["beta"]))}
+        ctx.gram_path("tuned")
+        rec["gram_path"] = gp
+        progress("gram paths done")
     # the FP64 oracle on sampled subdomains runs in spawned worker processes
     # (CPU only) while the GPU extras below run
     subs = sample_subdomains(int(res["D"].n_sub), args.cpu_sample_subdomains)

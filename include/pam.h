@@ -92,6 +92,16 @@ pam_status pam_sync(pam_ctx *ctx);
  * with on = 0, the same launches are enqueued directly. Results are
  * identical either way. */
 pam_status pam_graph_enable(pam_ctx *ctx, int32_t on);
+/* Path of the FP32 / BF16 Gram products (a5 with a3-a4): 1 = the assembly
+ * writes the normalized design W to HBM and the MFMA Gram tiles read it;
+ * 2 = fused: the Shepard denominators are computed first, then every Gram
+ * tile computes the design entries it needs in LDS and contracts them on
+ * MFMA, so W never reaches HBM; 0 (default) = tuned: both are timed on the
+ * first batched fit of each (precision, padded M, padded N) bucket and the
+ * faster is kept for the process (and appended to the JSON-lines file
+ * PAM_TUNE_CACHE names, read back at the first lookup). The two paths give
+ * bit-identical Gram products. FP64 always uses the stored design. */
+pam_status pam_gram_path(pam_ctx *ctx, int32_t mode);
 /* [host] Message of the last failing call on this thread ("" if none). */
 const char *pam_last_error(void);
 /* [host] Library version string. */

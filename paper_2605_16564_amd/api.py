@@ -44,6 +44,11 @@ class Context:
         """Fits and refinements as one HIP graph launch each (default on)."""
         N.check(N.lib().pam_graph_enable(self.h, 1 if on else 0), "pam_graph_enable")
 
+    def gram_path(self, mode: str = "tuned"):
+        """FP32/BF16 Gram path: 'tuned' (default), 'materialized' or 'fused'."""
+        m = {"tuned": 0, "materialized": 1, "fused": 2}[mode]
+        N.check(N.lib().pam_gram_path(self.h, m), "pam_gram_path")
+
     def timing(self, on: bool = True):
         N.check(N.lib().pam_timing_enable(self.h, 1 if on else 0), "pam_timing_enable")
 

@@ -65,6 +65,25 @@ pam_status launch_check_finite(pam_ctx *ctx, const FitArgs &a, const double *h) 
     return PAM_OK;
 }
 
+// One Gaussian of the low-precision modes: 2^(-(float)(r2 * sa)) with r2 the
+// squared distance in FP64 and sa = log2(e) / (2 sigma^2). Contraction is off
+// and the operations are written out once here, so that the assembly and the
+// fused Gram (which recomputes the design inside its tiles) produce the same
+// bits for every entry.
+__device__ __forceinline__ double lp_scale(double sg) {
+#pragma clang fp contract(off)
+    return 0.7213475204444817 / (sg * sg);   // log2(e) / 2 / sigma^2
+}
+__device__ __forceinline__ float lp_phi(const double *x, const double *c, int dim, double sa) {
+#pragma clang fp contract(off)
+    double r2 = 0.0;
+    for (int d = 0; d < dim; ++d) {
+        const double df = x[d] - c[d];
+        r2 = r2 + df * df;
+    }
+    return __builtin_amdgcn_exp2f(-(float)(r2 * sa));
+}
+
 template <typename TW, bool kF64>
 __global__ void __launch_bounds__(kThreads)
 k_assemble(FitArgs a, TW *__restrict__ Wt, int32_t *__restrict__ flags) {
@@ -108,7 +127,7 @@ k_assemble(FitArgs a, TW *__restrict__ Wt, int32_t *__restrict__ flags) {
             for (int t = threadIdx.x; t < cnt; t += kThreads) {
                 for (int d = 0; d < dim; ++d) sc[t * 3 + d] = cs[(size_t)(m0 + t) * dim + d];
                 const double sg = ss[m0 + t];
-                sa[t] = kF64 ? 0.5 / (sg * sg) : 1.4426950408889634 * 0.5 / (sg * sg);
+                sa[t] = kF64 ? 0.5 / (sg * sg) : lp_scale(sg);
             }
             __syncthreads();
             if (j < a.npad) {
@@ -123,7 +142,7 @@ k_assemble(FitArgs a, TW *__restrict__ Wt, int32_t *__restrict__ flags) {
                         if (pass == 0) sum += p;
                         else W[(size_t)(m0 + t) * a.npad + j] = to_w<TW>(live ? p * inv : 0.0);
                     } else {
-                        const float p = __builtin_amdgcn_exp2f(-(float)(r2 * sa[t]));
+                        const float p = lp_phi(xj, &sc[t * 3], dim, sa[t]);
                         if (pass == 0) sumf += p;
                         else W[(size_t)(m0 + t) * a.npad + j] = to_w<TW>(live ? (double)(p * invf) : 0.0);
                     }
@@ -338,7 +357,265 @@ k_gram_bf16(FitArgs a, const __hip_bfloat16 *__restrict__ Wt, float *__restrict_
             }
 }
 
+// ---------------------------------------------------------------- fused path
+// The low-precision design without its HBM round trip: k_rowsum computes the
+// Shepard denominators exactly as the assembly's first pass (inv[j] =
+// 1 / sum_m phi_jm, the same order of the same float sums), then the fused
+// Gram tiles compute every W_mj = phi_mj * inv[j] they need in LDS and
+// contract them on MFMA: the Gram is the same bits as through the stored
+// design, and W never reaches HBM (at the price of recomputing each entry in
+// every tile that uses it).
+__global__ void __launch_bounds__(kThreads)
+k_rowsum(FitArgs a, float *__restrict__ inv, int32_t *__restrict__ flags) {
+    const int s = a.sub_begin + blockIdx.y;
+    if (a.active && !a.active[s]) return;
+    if (flags[s] & 2) return;
+    const int64_t j0 = a.off[s];
+    const int N = (int)(a.off[s + 1] - j0);
+    const int M = max(0, min(a.m[s], a.m_cap));
+    const int dim = a.dim;
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    __shared__ double sc[kChunk * 3];
+    __shared__ double sa[kChunk];
+    float *is = inv + (size_t)(s - a.sub_begin) * a.npad;
+    const bool live = j < N;
+    double xj[3] = {0.0, 0.0, 0.0};
+    if (live)
+        for (int d = 0; d < dim; ++d) xj[d] = a.x[(j0 + j) * dim + d];
+    if (a.basis == PAM_BASIS_PLAIN) {
+        if (j < a.npad) is[j] = 1.0f;
+        return;
+    }
+    const double *cs = a.c + (size_t)s * a.m_cap * dim;
+    const double *ss = a.sigma + (size_t)s * a.m_cap;
+    float sumf = 0.0f;
+    for (int m0 = 0; m0 < M; m0 += kChunk) {
+        const int cnt = min(kChunk, M - m0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += kThreads) {
+            for (int d = 0; d < dim; ++d) sc[t * 3 + d] = cs[(size_t)(m0 + t) * dim + d];
+            sa[t] = lp_scale(ss[m0 + t]);
+        }
+        __syncthreads();
+        if (live)
+            for (int t = 0; t < cnt; ++t) sumf += lp_phi(xj, &sc[t * 3], dim, sa[t]);
+    }
+    if (live && !(sumf >= FLT_MIN)) atomicOr(&flags[s], 1);
+    if (j < a.npad) is[j] = 1.0f / sumf;
+}
+
+// Value of the design entry (center row m, sample column j) as the assembly
+// stores it: rows m < M the normalized Gaussians, row M the data, zero for
+// padded samples and rows beyond M.
+template <typename TW>
+__device__ __forceinline__ TW fused_entry(int m, int M, bool live, const double *xj, const double *cm, int dim,
+                                          double sa, float invf, double yj) {
+    if (!live || m > M) return to_w<TW>(0.0);
+    if (m == M) return to_w<TW>(yj);
+    return to_w<TW>((double)(lp_phi(xj, cm, dim, sa) * invf));
+}
+
+template <typename TW, int KC>
+struct FusedStage {
+    double c[2][64][3];   // centers of the two tile rows
+    double sa[2][64];
+    double x[KC][3];      // the chunk's samples
+    double y[KC];
+    float inv[KC];
+    int live[KC];
+};
+
+// Stage the two tiles' centers (rows m0.., n0..) once per block.
+template <typename TW, int KC>
+__device__ __forceinline__ void fused_centers(const FitArgs &a, int s, int M, int m0, int n0, FusedStage<TW, KC> &st) {
+    const double *cs = a.c + (size_t)s * a.m_cap * a.dim;
+    const double *ss = a.sigma + (size_t)s * a.m_cap;
+    for (int t = threadIdx.x; t < 128; t += kThreads) {
+        const int side = t >> 6, r = t & 63;
+        const int m = (side ? n0 : m0) + r;
+        for (int d = 0; d < 3; ++d) st.c[side][r][d] = (m < M && d < a.dim) ? cs[(size_t)m * a.dim + d] : 0.0;
+        st.sa[side][r] = m < M ? lp_scale(ss[m]) : 0.0;
+    }
+}
+
+template <typename TW, int KC>
+__device__ __forceinline__ void fused_samples(const FitArgs &a, int64_t j0, int N, int k0, const float *is,
+                                              FusedStage<TW, KC> &st) {
+    for (int t = threadIdx.x; t < KC; t += kThreads) {
+        const int j = k0 + t;
+        const bool live = j < N;
+        st.live[t] = live;
+        for (int d = 0; d < 3; ++d) st.x[t][d] = (live && d < a.dim) ? a.x[(j0 + j) * a.dim + d] : 0.0;
+        st.y[t] = live ? a.y[j0 + j] : 0.0;
+        st.inv[t] = live ? is[j] : 0.0f;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_gram_fused_f32(FitArgs a, const float *__restrict__ inv, float *__restrict__ G, const int32_t *__restrict__ flags) {
+    const int s = a.sub_begin + blockIdx.y;
+    if (a.active && !a.active[s]) return;
+    if (flags[s] & 2) return;
+    const int M = max(0, min(a.m[s], a.m_cap));
+    const int M1 = M + 1;
+    const int nt = (M1 + 63) / 64;
+    if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+    int ti, tj;
+    tile_of(blockIdx.x, nt, ti, tj);
+    const int64_t j0 = a.off[s];
+    const int N = (int)(a.off[s + 1] - j0);
+    const int Nk = (N + 15) & ~15;
+    const float *is = inv + (size_t)(s - a.sub_begin) * a.npad;
+    float *Gs = G + (size_t)(s - a.sub_begin) * a.mpad * a.mpad;
+    __shared__ float sA[64][17];
+    __shared__ float sB[64][17];
+    __shared__ FusedStage<float, 16> st;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wr = wid >> 1, wc = wid & 1;
+    const int m0 = ti * 64, n0 = tj * 64;
+    fused_centers<float, 16>(a, s, M, m0, n0, st);
+    v4f acc[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Nk; k0 += 16) {
+        __syncthreads();
+        fused_samples<float, 16>(a, j0, N, k0, is, st);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = threadIdx.x + e * kThreads;
+            const int r = idx >> 4, cc = idx & 15;
+            const float va = fused_entry<float>(m0 + r, M, st.live[cc], st.x[cc], st.c[0][r], a.dim, st.sa[0][r],
+                                                st.inv[cc], st.y[cc]);
+            sA[r][cc] = va;
+            sB[r][cc] = ti == tj ? va
+                                 : fused_entry<float>(n0 + r, M, st.live[cc], st.x[cc], st.c[1][r], a.dim,
+                                                      st.sa[1][r], st.inv[cc], st.y[cc]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            float av[2], bv[2];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) av[p] = sA[wr * 32 + p * 16 + (lane & 15)][kk];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) bv[q] = sB[wc * 32 + q * 16 + (lane & 15)][kk];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p], bv[q], acc[p][q], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wr * 32 + p * 16 + 4 * (lane >> 4) + r;
+                const int col = n0 + wc * 32 + q * 16 + (lane & 15);
+                Gs[(size_t)row * a.mpad + col] = acc[p][q][r];
+                if (ti != tj) Gs[(size_t)col * a.mpad + row] = acc[p][q][r];
+            }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_gram_fused_bf16(FitArgs a, const float *__restrict__ inv, float *__restrict__ G, const int32_t *__restrict__ flags) {
+    const int s = a.sub_begin + blockIdx.y;
+    if (a.active && !a.active[s]) return;
+    if (flags[s] & 2) return;
+    const int M = max(0, min(a.m[s], a.m_cap));
+    const int M1 = M + 1;
+    const int nt = (M1 + 63) / 64;
+    if ((int)blockIdx.x >= nt * (nt + 1) / 2) return;
+    int ti, tj;
+    tile_of(blockIdx.x, nt, ti, tj);
+    const int64_t j0 = a.off[s];
+    const int N = (int)(a.off[s + 1] - j0);
+    const int Nk = (N + 31) & ~31;
+    const float *is = inv + (size_t)(s - a.sub_begin) * a.npad;
+    float *Gs = G + (size_t)(s - a.sub_begin) * a.mpad * a.mpad;
+    __shared__ __attribute__((aligned(16))) __hip_bfloat16 sA[64][40];
+    __shared__ __attribute__((aligned(16))) __hip_bfloat16 sB[64][40];
+    __shared__ FusedStage<__hip_bfloat16, 32> st;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wr = wid >> 1, wc = wid & 1;
+    const int m0 = ti * 64, n0 = tj * 64;
+    fused_centers<__hip_bfloat16, 32>(a, s, M, m0, n0, st);
+    v4f acc[2][2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) acc[p][q] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Nk; k0 += 32) {
+        __syncthreads();
+        fused_samples<__hip_bfloat16, 32>(a, j0, N, k0, is, st);
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = threadIdx.x + e * kThreads;   // 0..2047
+            const int r = idx >> 5, cc = idx & 31;
+            const __hip_bfloat16 va = fused_entry<__hip_bfloat16>(m0 + r, M, st.live[cc], st.x[cc], st.c[0][r],
+                                                                  a.dim, st.sa[0][r], st.inv[cc], st.y[cc]);
+            sA[r][cc] = va;
+            sB[r][cc] = ti == tj ? va
+                                 : fused_entry<__hip_bfloat16>(n0 + r, M, st.live[cc], st.x[cc], st.c[1][r],
+                                                               a.dim, st.sa[1][r], st.inv[cc], st.y[cc]);
+        }
+        __syncthreads();
+        const int kb = 8 * (lane >> 4);
+        v8bf av[2], bv[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+            av[p] = *reinterpret_cast<const v8bf *>(&sA[wr * 32 + p * 16 + (lane & 15)][kb]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            bv[q] = *reinterpret_cast<const v8bf *>(&sB[wc * 32 + q * 16 + (lane & 15)][kb]);
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                acc[p][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[p], bv[q], acc[p][q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wr * 32 + p * 16 + 4 * (lane >> 4) + r;
+                const int col = n0 + wc * 32 + q * 16 + (lane & 15);
+                Gs[(size_t)row * a.mpad + col] = acc[p][q][r];
+                if (ti != tj) Gs[(size_t)col * a.mpad + row] = acc[p][q][r];
+            }
+}
+
 // ---------------------------------------------------------------- launchers
+pam_status launch_rowsum(pam_ctx *ctx, const FitArgs &a) {
+    dim3 grid((a.npad + kThreads - 1) / kThreads, a.sub_count);
+    hipLaunchKernelGGL(k_rowsum, grid, dim3(kThreads), 0, ctx->stream, a, wsp<float>(ctx, BUF_ROWSUM),
+                       wsp<int32_t>(ctx, BUF_FLAGS));
+    PAM_CHECK_HIP(hipGetLastError());
+    return PAM_OK;
+}
+
+pam_status launch_gram_fused(pam_ctx *ctx, const FitArgs &a) {
+    const int nt = a.mpad / 64;
+    dim3 grid(nt * (nt + 1) / 2, a.sub_count);
+    if (a.precision == PAM_PREC_F32)
+        hipLaunchKernelGGL(k_gram_fused_f32, grid, dim3(kThreads), 0, ctx->stream, a, wsp<float>(ctx, BUF_ROWSUM),
+                           wsp<float>(ctx, BUF_G), wsp<int32_t>(ctx, BUF_FLAGS));
+    else
+        hipLaunchKernelGGL(k_gram_fused_bf16, grid, dim3(kThreads), 0, ctx->stream, a,
+                           wsp<float>(ctx, BUF_ROWSUM), wsp<float>(ctx, BUF_G), wsp<int32_t>(ctx, BUF_FLAGS));
+    PAM_CHECK_HIP(hipGetLastError());
+    return PAM_OK;
+}
+
 pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a) {
     dim3 grid((a.npad + kThreads - 1) / kThreads, a.sub_count);
     int32_t *flags = wsp<int32_t>(ctx, BUF_FLAGS);

@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -163,6 +165,126 @@ static size_t ws_budget() {
 static size_t wbytes(int prec) { return prec == PAM_PREC_F64 ? 8 : (prec == PAM_PREC_F32 ? 4 : 2); }
 static size_t gbytes(int prec) { return prec == PAM_PREC_F64 ? 8 : 4; }
 
+// ---------------------------------------------------------------- Gram tuner
+// The low-precision Gram has two paths: the assembly writes the normalized
+// design to HBM and the Gram tiles read it, or the row sums are taken first
+// and the Gram tiles compute the design entries they need in LDS (fused: no
+// design in HBM, every entry recomputed in each tile that uses it). Both give
+// the same bits; which is faster depends on the tile count (M), the sample
+// count (N) and the precision. The tuner times both on the first batched fit
+// of a (precision, padded M, padded N) bucket and keeps the faster: in
+// memory for the process and, when PAM_TUNE_CACHE names a file, as one JSON
+// object per line there (read at the first lookup, appended on each new
+// choice). pam_gram_path forces either path.
+struct TuneEntry { int fused; double ms_materialized, ms_fused; };
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneEntry> g_tune;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(const FitArgs &a) {
+    const char *pn = a.precision == PAM_PREC_F32 ? "f32" : "bf16";
+    return std::string("gfx950/gram/") + pn + "/mpad" + std::to_string(a.mpad) + "/npad" + std::to_string(a.npad);
+}
+
+static void tune_load() {
+    g_tune_loaded = true;
+    const char *path = getenv("PAM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        // {"key": "...", "path": "fused"|"materialized", "ms_materialized": x, "ms_fused": y}
+        const char *k = strstr(line, "\"key\": \"");
+        const char *pth = strstr(line, "\"path\": \"");
+        if (!k || !pth) continue;
+        k += 8;
+        const char *ke = strchr(k, '"');
+        if (!ke) continue;
+        TuneEntry e{strncmp(pth + 9, "fused", 5) == 0 ? 1 : 0, 0.0, 0.0};
+        const char *mm = strstr(line, "\"ms_materialized\": ");
+        const char *mf = strstr(line, "\"ms_fused\": ");
+        if (mm) e.ms_materialized = atof(mm + 19);
+        if (mf) e.ms_fused = atof(mf + 12);
+        g_tune[std::string(k, ke - k)] = e;
+    }
+    fclose(f);
+}
+
+static void tune_store(const std::string &key, const TuneEntry &e) {
+    const char *path = getenv("PAM_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"key\": \"%s\", \"path\": \"%s\", \"ms_materialized\": %.4f, \"ms_fused\": %.4f}\n", key.c_str(),
+            e.fused ? "fused" : "materialized", e.ms_materialized, e.ms_fused);
+    fclose(f);
+}
+
+// Time one Gram path on the first batch of a fit (two runs after a warm-up,
+// the faster kept); enqueued on the context's stream and synchronized.
+static pam_status tune_time(pam_ctx *ctx, FitArgs a, int fused, double *ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PAM_CHECK_HIP(hipEventCreate(&e0));
+    PAM_CHECK_HIP(hipEventCreate(&e1));
+    a.gram_fused = fused;
+    pam_status st = PAM_OK;
+    double best = 1e30;
+    for (int rep = 0; rep < 3 && st == PAM_OK; ++rep) {
+        if ((st = launch_fill_u32(ctx, ctx->ws.ptr[BUF_FLAGS], 0u, a.n_sub)) != PAM_OK) break;
+        (void)hipEventRecord(e0, ctx->stream);
+        st = fused ? launch_rowsum(ctx, a) : launch_assemble(ctx, a);
+        if (st == PAM_OK) st = fused ? launch_gram_fused(ctx, a) : launch_gram(ctx, a);
+        (void)hipEventRecord(e1, ctx->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            set_error("tuner: event synchronization failed");
+            st = PAM_ERR_HIP;
+            break;
+        }
+        float t = 0.0f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        if (rep > 0) best = std::min(best, (double)t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = best;
+    return st;
+}
+
+// Path of the plan's Gram: forced by pam_gram_path, else the tuner's choice.
+static pam_status tune_gram(pam_ctx *ctx, FitArgs &a, int batch) {
+    a.gram_fused = 0;
+    if (a.precision == PAM_PREC_F64) return PAM_OK;     // the FP64 design is materialized
+    if (ctx->gram_mode == 1) return PAM_OK;
+    if (ctx->gram_mode == 2) {
+        a.gram_fused = 1;
+        return PAM_OK;
+    }
+    const std::string key = tune_key(a);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        if (!g_tune_loaded) tune_load();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            a.gram_fused = it->second.fused;
+            return PAM_OK;
+        }
+    }
+    FitArgs t = a;
+    t.sub_begin = 0;
+    t.sub_count = std::min(batch, a.n_sub);
+    t.active = nullptr;
+    TuneEntry e{0, 0.0, 0.0};
+    pam_status st = tune_time(ctx, t, 0, &e.ms_materialized);
+    if (st == PAM_OK) st = tune_time(ctx, t, 1, &e.ms_fused);
+    if (st != PAM_OK) return st;
+    e.fused = e.ms_fused < e.ms_materialized ? 1 : 0;
+    a.gram_fused = e.fused;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (g_tune.emplace(key, e).second) tune_store(key, e);
+    return PAM_OK;
+}
+
 // Launch plan of a3-a6 for subdomains [0, n_sub): the kernel arguments, the
 // batch (subdomains per launch, from the workspace budget; batched = 0: one
 // per launch) and the solve's team size.
@@ -227,7 +349,16 @@ static pam_status fit_ensure(pam_ctx *ctx, const FitPlan &p) {
         return st;
     if ((st = ensure(ctx, BUF_FLAGS, (size_t)a.n_sub * 4)) != PAM_OK) return st;
     if (a.team > 1 && (st = ensure(ctx, BUF_TEAM, solve_team_ctl_bytes(p.batch))) != PAM_OK) return st;
+    if (a.precision != PAM_PREC_F64 && (st = ensure(ctx, BUF_ROWSUM, b * a.npad * 4)) != PAM_OK) return st;
     return solve_prepare(a.m_cap, a.precision);
+}
+
+// fit_ensure, then the Gram path (tuned before any graph capture).
+static pam_status fit_prepare(pam_ctx *ctx, FitPlan &p, const double *h) {
+    pam_status st = fit_ensure(ctx, p);
+    if (st != PAM_OK) return st;
+    (void)h;
+    return tune_gram(ctx, p.a, p.batch);
 }
 
 // Enqueue a3-a6 of the plan: flags cleared, input check, then per batch the
@@ -245,11 +376,11 @@ static pam_status fit_enqueue(pam_ctx *ctx, const FitPlan &p, const int32_t *act
         a.sub_count = std::min(p.batch, a.n_sub - b0);
         {
             KernelTimer kt(ctx, PAM_TK_ASSEMBLE);
-            if ((st = launch_assemble(ctx, a)) != PAM_OK) return st;
+            if ((st = a.gram_fused ? launch_rowsum(ctx, a) : launch_assemble(ctx, a)) != PAM_OK) return st;
         }
         {
             KernelTimer kt(ctx, PAM_TK_GRAM);
-            if ((st = launch_gram(ctx, a)) != PAM_OK) return st;
+            if ((st = a.gram_fused ? launch_gram_fused(ctx, a) : launch_gram(ctx, a)) != PAM_OK) return st;
         }
         {
             KernelTimer kt(ctx, PAM_TK_SOLVE);
@@ -263,8 +394,8 @@ static pam_status fit_enqueue(pam_ctx *ctx, const FitPlan &p, const int32_t *act
 static pam_status run_fit(pam_ctx *ctx, const pam_samples *S, const pam_dict *D,
                           const pam_enet_opts *o, double *beta, pam_fit_stats *stats,
                           const int32_t *active, int warm_start, const double *h = nullptr) {
-    const FitPlan p = fit_plan(S, D, o, beta, stats);
-    pam_status st = fit_ensure(ctx, p);
+    FitPlan p = fit_plan(S, D, o, beta, stats);
+    pam_status st = fit_prepare(ctx, p, h);
     if (st != PAM_OK) return st;
     return fit_enqueue(ctx, p, active, warm_start, h);
 }
@@ -463,6 +594,14 @@ pam_status pam_sync(pam_ctx *ctx) {
     return PAM_OK;
 }
 
+pam_status pam_gram_path(pam_ctx *ctx, int32_t mode) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(mode >= 0 && mode <= 2, "mode must be 0 (tuned), 1 (materialized) or 2 (fused)");
+    ctx->gram_mode = mode;
+    return PAM_OK;
+}
+
 pam_status pam_graph_enable(pam_ctx *ctx, int32_t on) {
     pam_status st = check_ctx(ctx);
     if (st != PAM_OK) return st;
@@ -570,8 +709,8 @@ pam_status pam_fit_subdomains(pam_ctx *ctx, const pam_samples *samples, const pa
     pam_status st = check_ctx(ctx);
     if (st != PAM_OK) return st;
     if ((st = check_fit_args(samples, dict, opts, beta)) != PAM_OK) return st;
-    const FitPlan plan = fit_plan(samples, dict, opts, beta, stats);
-    if ((st = fit_ensure(ctx, plan)) != PAM_OK) return st;
+    FitPlan plan = fit_plan(samples, dict, opts, beta, stats);
+    if ((st = fit_prepare(ctx, plan, nullptr)) != PAM_OK) return st;
     KeyHash k;
     k.v(1);   // a single fit
     graph_key_common(k, ctx, plan, opts);
@@ -605,8 +744,8 @@ pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, 
     const int64_t n_tot = samples->off_host[n];
     if ((st = ensure(ctx, BUF_R, (size_t)std::max<int64_t>(n_tot, 1) * 8)) != PAM_OK) return st;
     if ((st = ensure(ctx, BUF_MARK, mark_ws_bytes(n, samples->n_max))) != PAM_OK) return st;
-    const FitPlan plan = fit_plan(samples, dict, opts, beta, stats);
-    if ((st = fit_ensure(ctx, plan)) != PAM_OK) return st;
+    FitPlan plan = fit_plan(samples, dict, opts, beta, stats);
+    if ((st = fit_prepare(ctx, plan, samples->h)) != PAM_OK) return st;
     RefineArgs ra;
     memset(&ra, 0, sizeof(ra));
     ra.n_sub = n;

@@ -46,6 +46,7 @@ enum Buf {
     BUF_CNN,        // network activations, packed weights, gradient partials
     BUF_TEAM,       // control words of the solve's workgroup teams
     BUF_AUX,        // staging of generated query points (Darcy coefficient)
+    BUF_ROWSUM,     // Shepard denominators 1 / sum_m phi_jm of the fused Gram path [n_sub][npad] f32
     BUF_COUNT
 };
 
@@ -94,6 +95,7 @@ struct pam_ctx {
     pam::Timing timing;
     pam::GraphCache graphs;
     int32_t *sticky = nullptr;   // device [4]: [0] subdomains met with non-finite input
+    int gram_mode = 0;           // pam_gram_path: 0 tuned, 1 materialized, 2 fused
     bool alive = true;
 };
 
@@ -149,6 +151,7 @@ struct FitArgs {
     int32_t team;                   // workgroups per subdomain in the solve (1, 2 or 4)
     int32_t team_min;               // active-set size from which a team shares passes
     int32_t team_idle_us;           // a member's wait for a command before it leaves (0: 10 s)
+    int32_t gram_fused;             // 1: row sums + fused Gram tiles; 0: assembly + Gram
 };
 
 // Non-finite input check of a fit call: for every subdomain, its sample
@@ -158,6 +161,10 @@ struct FitArgs {
 pam_status launch_check_finite(pam_ctx *ctx, const FitArgs &a, const double *h);
 pam_status launch_assemble(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_gram(pam_ctx *ctx, const FitArgs &a);
+// Fused Gram path (FP32 / BF16): row sums, then Gram tiles that compute the
+// design in LDS (same bits as the assembly + Gram path).
+pam_status launch_rowsum(pam_ctx *ctx, const FitArgs &a);
+pam_status launch_gram_fused(pam_ctx *ctx, const FitArgs &a);
 pam_status launch_solve(pam_ctx *ctx, const FitArgs &a);
 // Dynamic-LDS attribute of the solve instances for a capacity (host only;
 // call before a graph capture), and the team control bytes of a launch.

@@ -25,7 +25,7 @@ EXPORTS = [
     "pam_grid_patches", "pam_support_hint", "pam_cnn_labels",
     "pam_eval_blend", "pam_interface_count", "pam_interface_jump", "pam_select_lambda",
     "pam_darcy_solve", "pam_darcy_error", "pam_darcy_coefficient", "pam_darcy_coefficient_cells",
-    "pam_eval_noalloc", "pam_graph_enable",
+    "pam_eval_noalloc", "pam_graph_enable", "pam_gram_path",
 ]
 TIMING_KINDS = ["gather", "lattice", "assemble", "gram", "solve", "indicator", "mark",
                 "eval_bin", "eval", "cnn", "blend", "jump",
@@ -143,6 +143,7 @@ def lib():
         L.pam_darcy_coefficient_cells.argtypes = [P, C.POINTER(PamDarcyOpts), P, P]
         L.pam_timing_enable.argtypes = [P, C.c_int32]
         L.pam_graph_enable.argtypes = [P, C.c_int32]
+        L.pam_gram_path.argtypes = [P, C.c_int32]
         L.pam_timing_read.argtypes = [P, P, P, C.c_int32]
         L.pam_cnn_param_count.argtypes = []
         L.pam_cnn_forward.argtypes = [P, P, C.c_int32, P, P, C.c_int32]
