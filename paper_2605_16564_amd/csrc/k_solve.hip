@@ -21,9 +21,21 @@
 #include <algorithm>
 
 #ifdef PAM_PHASE_PROFILE
+#include <stdio.h>
+// per-subdomain phase record of the profile build: [0, 8) microseconds per
+// phase, [8, 16) bytes per phase, [16, 28) counts (written by thread 0 at the
+// end of the solve, read and printed by the host after each launch)
+static constexpr int kPhaseW = 48, kPhaseSubs = 8192;
+__device__ double g_phase[kPhaseSubs * kPhaseW];
 #define PHASE_MARK(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); ph[k] += _t - ph_last; ph_last = _t; phb[k] += v.bytes - phb_last; phb_last = v.bytes; } } while (0)
+// sub-phases (thread 0's clock at the block's sync points): SUB_START opens a
+// region, SUB(k) adds the time since the last mark to slot k
+#define SUB_START() do { if (threadIdx.x == 0) v.sp[15] = wall_clock64(); } while (0)
+#define SUB(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); v.sp[k] += _t - v.sp[15]; v.sp[15] = _t; } } while (0)
 #else
 #define PHASE_MARK(k) do { } while (0)
+#define SUB_START() do { } while (0)
+#define SUB(k) do { } while (0)
 #endif
 
 namespace pam {
@@ -35,11 +47,13 @@ static constexpr int kAdd = 16;    // violators activated per consistent iterati
 static constexpr int kR = 1;       // GEMV outputs per thread per pass
 static constexpr int kTile = 128;  // rows staged in LDS per bordering tile
 static constexpr int kFz = 8;      // coordinates frozen before one batched downdate
-static constexpr int kQ = 16;      // rows of the low-rank update scratch (>= kB, kFz)
+static constexpr int kQ = 24;      // rows of the low-rank update scratch (>= kFz + 2 kB)
 static constexpr int kPass = kR * kT;
+static constexpr int kUR = 16;     // rows of H in flight per thread in the bordering product
+static constexpr int kHR = 16;     // rows of H in flight per thread in the low-rank updates
 static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the polish
 static constexpr int kIncMax = 48;     // incremental solution updates between full solves
-static_assert(kFz <= kB && kB <= kQ, "the low-rank passes are instantiated for kB rows");
+static_assert(kFz <= kB && kFz + 2 * kB <= kQ, "a pair of blocks defers onto a staged frozen set");
 
 // A team of up to kTeamMax workgroups may serve one subdomain (the launch is
 // sized so that the device holds all of its workgroups at once, by the
@@ -191,7 +205,8 @@ struct Sv {
     int s;                 // active-set size (uniform)
     double bytes;          // algorithmic bytes streamed (Gram rows, H)
     int r;                 // frozen positions awaiting the batched downdate
-    int pend;              // rank of a deferred bordering update (rows [0, pend) of U, V)
+    int pend;              // rank of a deferred update (rows [0, pend) of U, V)
+    int fz;                // frozen positions whose downdate is part of the deferred update
     int *Rp;               // LDS [kFz] frozen positions
     double *Cri;           // LDS [kFz*kFz] inverse of H[R, R]
     // team (T > 1): see kTeamMax. The team scratch holds partial results
@@ -203,6 +218,9 @@ struct Sv {
     unsigned long long *ctl;   // [kCtl] command, arguments, completion words
     double *part;              // team scratch
     unsigned *tsh;             // LDS [5]: command broadcast, commands posted, failure
+#ifdef PAM_PHASE_PROFILE
+    long long *sp;             // LDS [16] sub-phase clocks
+#endif
     __device__ double *xin() const { return part + (size_t)kTeamMax * kB * m_cap; }
     __device__ double *bco() const { return part + (size_t)(kTeamMax * kB + 1) * m_cap; }
     __device__ int *Sg() const { return reinterpret_cast<int *>(part + (size_t)(kTeamMax * kB + 2) * m_cap); }
@@ -334,7 +352,9 @@ __device__ __forceinline__ void hgemv(Sv<TG> &v, const double *in, double *out) 
     const int s = v.s;
     v.bytes += 8.0 * (double)s * (double)s;
     if (!team_on(v)) {
+        SUB_START();
         hgemv_rows(v, in, out, 0, s);
+        SUB(14);
         return;
     }
     double *xin = v.xin();
@@ -374,19 +394,19 @@ __device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *
             __syncthreads();
             if (!live) continue;
             int r = 0;
-            for (; r + 8 <= tn; r += 8) {
+            for (; r + kHR <= tn; r += kHR) {
                 double *h = Hc + (size_t)(t0 + r) * v.ldh;
-                double hv[8];
+                double hv[kHR];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) hv[e] = h[(size_t)e * v.ldh];
+                for (int e = 0; e < kHR; ++e) hv[e] = h[(size_t)e * v.ldh];
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     const double uq = uj[q];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) hv[e] += tile[q * kTile + r + e] * uq;
+                    for (int e = 0; e < kHR; ++e) hv[e] += tile[q * kTile + r + e] * uq;
                 }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) h[(size_t)e * v.ldh] = hv[e];
+                for (int e = 0; e < kHR; ++e) h[(size_t)e * v.ldh] = hv[e];
             }
             for (; r < tn; ++r) {
                 double *h = Hc + (size_t)(t0 + r) * v.ldh;
@@ -405,6 +425,7 @@ __device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *
 template <typename TG>
 __device__ __forceinline__ void hupdate_rows(Sv<TG> &v, int s, int nq, double *tile, int r0, int r1) {
     if (nq <= kB) hupdate<kB>(v, s, nq, v.V, v.U, tile, r0, r1);
+    else if (nq <= 2 * kB) hupdate<2 * kB>(v, s, nq, v.V, v.U, tile, r0, r1);
     else hupdate<kQ>(v, s, nq, v.V, v.U, tile, r0, r1);
 }
 
@@ -439,12 +460,12 @@ __device__ __forceinline__ void upass(Sv<TG> &v, int nb, int r0, int r1, double 
             }
             __syncthreads();
             int r = 0;
-            for (; r + 8 <= tn; r += 8) {
-                double h[8];
+            for (; r + kUR <= tn; r += kUR) {
+                double h[kUR];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) h[e] = Hc[(size_t)(t0 + r + e) * v.ldh];
+                for (int e = 0; e < kUR; ++e) h[e] = Hc[(size_t)(t0 + r + e) * v.ldh];
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
+                for (int e = 0; e < kUR; ++e)
 #pragma unroll
                     for (int q = 0; q < kB; ++q) acc[q] += h[e] * tile[q * kTile + r + e];
             }
@@ -459,6 +480,26 @@ __device__ __forceinline__ void upass(Sv<TG> &v, int nb, int r0, int r1, double 
             for (int q = 0; q < nb; ++q) out[(size_t)q * v.m_cap + i] = acc[q];
     }
     __syncthreads();
+}
+
+template <typename TG>
+__device__ __forceinline__ void drop_frozen(Sv<TG> &v);
+
+// sum_i x[i] y[i] over i = l16, l16 + 16, ... < s (one lane of a 16-lane
+// group): four partial sums, so that eight loads are in flight per lane
+__device__ __forceinline__ double dot16(const double *x, const double *y, int l16, int s) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = l16;
+    for (; i + 48 < s; i += 64) {
+        const double x0 = x[i], x1 = x[i + 16], x2 = x[i + 32], x3 = x[i + 48];
+        const double y0 = y[i], y1 = y[i + 16], y2 = y[i + 32], y3 = y[i + 48];
+        a0 += x0 * y0;
+        a1 += x1 * y1;
+        a2 += x2 * y2;
+        a3 += x3 * y3;
+    }
+    for (; i < s; i += 16) a0 += x[i] * y[i];
+    return (a0 + a1) + (a2 + a3);
 }
 
 // Blocked bordering: append the nb (<= kB) coordinates ks[] to the active
@@ -482,9 +523,20 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
     const int s = v.s, pend = v.pend;
     double *Ub = v.U + (size_t)pend * v.m_cap, *Vb = v.V + (size_t)pend * v.m_cap;
     v.bytes += 8.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
-    for (int q = 0; q < nb; ++q)
-        for (int i = threadIdx.x; i < s; i += kT) v.Ag[(size_t)q * v.m_cap + i] = Gat(v, ks[q], v.S[i]);
+    SUB_START();
+    // A_SB: the nb Gram rows of the block at the active coordinates (all
+    // loads of a thread issued before its stores)
+    for (int i = threadIdx.x; i < s; i += kT) {
+        const int k = v.S[i];
+        TG gq[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) gq[q] = q < nb ? v.G[(size_t)ks[q] * v.mpad + k] : (TG)0;
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+            if (q < nb) v.Ag[(size_t)q * v.m_cap + i] = (double)gq[q];
+    }
     __syncthreads();
+    SUB(0);
     // U = H A_SB: one pass over H for all nb columns
     if (!team_on(v)) {
         upass(v, nb, 0, s, Ub, tile);
@@ -502,82 +554,86 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         }
         __syncthreads();
     }
+    SUB(1);
     if (pend > 0) {
         // the stored block lacks the pending V_p U_p' on the old positions:
-        // U += V_p (U_p' A_SB), with U_p' A_SB in tile[kB*kB ...)
-        for (int pair0 = 0; pair0 < kB * kB; pair0 += kT / 16) {
+        // U += V_p (U_p' A_SB), with X = U_p' A_SB (pend x nb) in tile[kB*kB ...)
+        constexpr int kPairs = (kQ - kB) * kB;
+        double *X = tile + kB * kB;
+        for (int pair0 = 0; pair0 < kPairs; pair0 += kT / 16) {
             const int pair = pair0 + (threadIdx.x >> 4), l16 = threadIdx.x & 15;
             const int p = pair / kB, q = pair % kB;
             double acc = 0.0;
-            if (pair < kB * kB && p < pend && q < nb)
-                for (int i = l16; i < s; i += 16) acc += v.U[(size_t)p * v.m_cap + i] * v.Ag[(size_t)q * v.m_cap + i];
+            if (pair < kPairs && p < pend && q < nb)
+                acc = dot16(v.U + (size_t)p * v.m_cap, v.Ag + (size_t)q * v.m_cap, l16, s);
 #pragma unroll
             for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
-            if (l16 == 0 && pair < kB * kB) tile[kB * kB + pair] = acc;
+            if (l16 == 0 && pair < kPairs) X[pair] = acc;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < s; i += kT) {
-            double vp[kB];
+            double acc[kB];
 #pragma unroll
-            for (int p = 0; p < kB; ++p) vp[p] = p < pend ? v.V[(size_t)p * v.m_cap + i] : 0.0;
-            for (int q = 0; q < nb; ++q) {
-                double acc = Ub[(size_t)q * v.m_cap + i];
+            for (int q = 0; q < kB; ++q) acc[q] = q < nb ? Ub[(size_t)q * v.m_cap + i] : 0.0;
+            for (int p = 0; p < pend; ++p) {
+                const double vp = v.V[(size_t)p * v.m_cap + i];
 #pragma unroll
-                for (int p = 0; p < kB; ++p) acc += vp[p] * (p < pend ? tile[kB * kB + p * kB + q] : 0.0);
-                Ub[(size_t)q * v.m_cap + i] = acc;
+                for (int q = 0; q < kB; ++q) acc[q] += vp * X[p * kB + q];
             }
+#pragma unroll
+            for (int q = 0; q < kB; ++q)
+                if (q < nb) Ub[(size_t)q * v.m_cap + i] = acc[q];
         }
         __syncthreads();
     }
+    SUB(2);
     // C = A_BB + lambda2 I - A_SB' U: 16 threads per (p, q) pair
     for (int pair0 = 0; pair0 < kB * kB; pair0 += kT / 16) {
         const int pair = pair0 + (threadIdx.x >> 4), l16 = threadIdx.x & 15;
         const int p = pair / kB, q = pair % kB;
         double acc = 0.0;
         if (pair < kB * kB && p < nb && q < nb)
-            for (int i = l16; i < s; i += 16) acc += v.Ag[(size_t)p * v.m_cap + i] * Ub[(size_t)q * v.m_cap + i];
+            acc = dot16(v.Ag + (size_t)p * v.m_cap, Ub + (size_t)q * v.m_cap, l16, s);
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
         if (l16 == 0 && pair < kB * kB) tile[pair] = acc;
     }
+    // A_BB + lambda2 I in LDS for the factorization below (after X)
+    double *Abb = tile + kB * kB + (kQ - kB) * kB;
+    if ((int)threadIdx.x < nb * nb) {
+        const int p = threadIdx.x / nb, q = threadIdx.x - (threadIdx.x / nb) * nb;
+        Abb[p * kB + q] = Gat(v, ks[p], ks[q]) + (p == q ? v.l2 : 0.0);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // small Cholesky inverse in LDS (cinv holds L, then the inverse);
-        // tile[0 .. kB*kB) holds A_SB' U, tile[kB*kB .. 2*kB*kB) is scratch
-        double *L = cinv, *Li = tile + kB * kB;
+    SUB(3);
+    if (threadIdx.x < 64) {
+        // C^-1 by Gauss-Jordan elimination in wave 0, one lane per entry of
+        // the (padded) kB x kB block; C is symmetric positive definite, so the
+        // pivots are the Schur complements that a Cholesky factorization would
+        // take roots of, checked against the same threshold
+        static_assert(kB * kB == 64, "one lane per entry of the bordering block");
+        const int lane = threadIdx.x, i = lane / kB, j = lane % kB;
+        double e = (i < nb && j < nb) ? Abb[i * kB + j] - tile[i * kB + j] : (i == j ? 1.0 : 0.0);
         int ok = 1;
-        for (int p = 0; p < nb && ok; ++p)
-            for (int q = 0; q <= p; ++q) {
-                double val = Gat(v, ks[p], ks[q]) - tile[p * kB + q];
-                if (p == q) val += v.l2;
-                for (int k = 0; k < q; ++k) val -= L[p * kB + k] * L[q * kB + k];
-                if (p == q) {
-                    const double dref = Gat(v, ks[p], ks[p]) + v.l2;
-                    if (!(val > 1e-14 * dref)) { ok = 0; break; }
-                    L[p * kB + p] = sqrt(val);
-                } else {
-                    L[p * kB + q] = val / L[q * kB + q];
-                }
-            }
-        if (ok) {
-            for (int q = 0; q < nb; ++q)
-                for (int p = 0; p < nb; ++p) {
-                    double val = p == q ? 1.0 : 0.0;
-                    for (int k = q; k < p; ++k) val -= L[p * kB + k] * Li[k * kB + q];
-                    Li[p * kB + q] = p < q ? 0.0 : val / L[p * kB + p];
-                }
-            for (int p = 0; p < nb; ++p)
-                for (int q = 0; q < nb; ++q) {
-                    double val = 0.0;
-                    for (int k = max(p, q); k < nb; ++k) val += Li[k * kB + p] * Li[k * kB + q];
-                    cinv[p * kB + q] = val;   // L no longer needed below the diagonal pass
-                }
+        for (int k = 0; k < nb; ++k) {
+            const double akk = __shfl(e, k * kB + k, 64);
+            const double aik = __shfl(e, i * kB + k, 64);
+            const double akj = __shfl(e, k * kB + j, 64);
+            if (!(akk > 1e-14 * Abb[k * kB + k])) { ok = 0; break; }   // uniform over the wave
+            const double ip = 1.0 / akk;
+            if (i == k && j == k) e = ip;
+            else if (i == k) e = akj * ip;
+            else if (j == k) e = -aik * ip;
+            else e = e - aik * akj * ip;
         }
-        red.flag = ok;
+        const double et = __shfl(e, j * kB + i, 64);
+        if (ok && i < nb && j < nb) cinv[i * kB + j] = 0.5 * (e + et);
+        if (lane == 0) red.flag = ok;
     }
     __syncthreads();
     const bool ok = red.flag != 0;
     __syncthreads();
+    SUB(4);
     if (!ok) return false;
     // V = U C^-1
     for (int i = threadIdx.x; i < s; i += kT) {
@@ -592,6 +648,7 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         }
     }
     __syncthreads();
+    SUB(5);
     if (upd_z) {
         double ur[kB];
 #pragma unroll
@@ -622,11 +679,14 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
     }
     // H[i][j] += sum_q V[q][i] U[q][j] over the old block (with the pending
     // rows, which are zero on the pending block's own positions)
-    const bool keep = defer && pend == 0;
+    // defer when the next block still fits the scratch rows
+    const bool keep = defer && pend + nb + kB <= kQ;
+    SUB(6);
     if (!keep) {
         v.bytes += 16.0 * (double)s * (double)s;
         hupdate_all(v, s, pend + nb, tile);
     }
+    SUB(7);
     for (int j = threadIdx.x; j < s; j += kT)
         for (int q = 0; q < nb; ++q) {
             const double val = -Vb[(size_t)q * v.m_cap + j];
@@ -642,16 +702,19 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
         v.pos[ks[threadIdx.x]] = s + threadIdx.x;
     }
     if (keep) {
-        // the pending factors vanish on the new positions
-        for (int e = threadIdx.x; e < nb * nb; e += kT) {
+        // the pending factors (earlier ones and this block's) vanish on the
+        // new positions
+        for (int e = threadIdx.x; e < (pend + nb) * nb; e += kT) {
             const int q = e / nb, i = s + e % nb;
             v.U[(size_t)q * v.m_cap + i] = 0.0;
             v.V[(size_t)q * v.m_cap + i] = 0.0;
         }
     }
     __syncthreads();
-    v.pend = keep ? nb : 0;
+    SUB(8);
+    v.pend = keep ? pend + nb : 0;
     v.s = s + nb;
+    if (!keep && v.fz > 0) drop_frozen(v);
     return true;
 }
 
@@ -660,8 +723,11 @@ template <typename TG>
 __device__ __forceinline__ void flush_pending(Sv<TG> &v, double *tile) {
     if (v.pend == 0) return;
     v.bytes += 16.0 * (double)v.s * (double)v.s;
+    SUB_START();
     hupdate_all(v, v.s, v.pend, tile);
+    SUB(7);
     v.pend = 0;
+    if (v.fz > 0) drop_frozen(v);
 }
 
 // Drop active position p (no update of H): the last position moves into p.
@@ -701,12 +767,18 @@ template <typename TG>
 __device__ __forceinline__ void freeze(Sv<TG> &v, int p, bool upd_z = false) {
     const int s = v.s, r = v.r;
     v.bytes += 8.0 * s;
+    SUB_START();
     for (int i = threadIdx.x; i < s; i += kT) v.U[(size_t)r * v.m_cap + i] = v.H[(size_t)p * v.ldh + i];
+    __syncthreads();
+    // H[R, p] and H[p, p] into LDS in parallel for the serial part below
+    if ((int)threadIdx.x <= r) {
+        double *c = v.Cri + kFz * kFz;
+        c[threadIdx.x] = v.U[(size_t)threadIdx.x * v.m_cap + p];   // row r holds H[p, .]
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         double *c = v.Cri + kFz * kFz, *u = c + kFz;   // scratch after C^-1
-        for (int q = 0; q < r; ++q) c[q] = v.U[(size_t)q * v.m_cap + p];
-        double delta = v.H[(size_t)p * v.ldh + p];
+        double delta = c[r];
         for (int q = 0; q < r; ++q) {
             double t = 0.0;
             for (int k = 0; k < r; ++k) t += v.Cri[q * kFz + k] * c[k];
@@ -738,6 +810,7 @@ __device__ __forceinline__ void freeze(Sv<TG> &v, int p, bool upd_z = false) {
         if ((int)threadIdx.x <= r) v.z[v.Rp[threadIdx.x]] = 0.0;
         __syncthreads();
     }
+    SUB(9);
     v.r = r + 1;
 }
 
@@ -747,10 +820,14 @@ template <typename TG>
 __device__ __forceinline__ void heff_axpy(Sv<TG> &v, int p, double d) {
     const int s = v.s, r = v.r;
     double *t = v.Cri + kFz * kFz + 2 * kFz + 1;   // [kFz] scratch after delta
+    // t = C^-1 W[p, .]': the r entries of W at p fetched in parallel first
+    double *wp = v.Cri + kFz * kFz;   // c of freeze, free here
+    if ((int)threadIdx.x < r) wp[threadIdx.x] = v.U[(size_t)threadIdx.x * v.m_cap + p];
+    __syncthreads();
     if (threadIdx.x == 0)
         for (int q = 0; q < r; ++q) {
             double acc = 0.0;
-            for (int k = 0; k < r; ++k) acc += v.Cri[q * kFz + k] * v.U[(size_t)k * v.m_cap + p];
+            for (int k = 0; k < r; ++k) acc += v.Cri[q * kFz + k] * wp[k];
             t[q] = acc;
         }
     __syncthreads();
@@ -765,15 +842,11 @@ __device__ __forceinline__ void heff_axpy(Sv<TG> &v, int p, double d) {
     __syncthreads();
 }
 
-// Apply the frozen set to H (one rank-r pass: H <- H - W' C^-1 W) and drop
-// the frozen positions from the active list.
+// V = -C^-1 W over the live block (rows [0, r) of V; W is in rows [0, r)
+// of U): the frozen set's downdate H <- H + V' W as a rank-r update.
 template <typename TG>
-__device__ __forceinline__ void compact(Sv<TG> &v, double *tile) {
-    const int r = v.r;
-    if (r == 0) return;
-    const int s = v.s;
-    v.bytes += 16.0 * (double)s * (double)s;
-    // V = -C^-1 W (r x s)
+__device__ __forceinline__ void frozen_factors(Sv<TG> &v) {
+    const int r = v.r, s = v.s;
     for (int i = threadIdx.x; i < s; i += kT) {
         double w[kFz];
 #pragma unroll
@@ -786,8 +859,14 @@ __device__ __forceinline__ void compact(Sv<TG> &v, double *tile) {
         }
     }
     __syncthreads();
-    hupdate_all(v, s, r, tile);
-    // drop frozen positions in descending order (each hole takes the last live one)
+}
+
+// Drop the frozen positions (their rows and columns of H are zero once the
+// downdate is applied) in descending order, each hole taking the last live
+// position.
+template <typename TG>
+__device__ __forceinline__ void drop_frozen(Sv<TG> &v) {
+    const int r = v.r;
     for (int n = 0; n < r; ++n) {
         int best = -1;
         for (int q = 0; q < r; ++q) best = max(best, v.Rp[q]);
@@ -799,6 +878,37 @@ __device__ __forceinline__ void compact(Sv<TG> &v, double *tile) {
         drop_position(v, best);
     }
     v.r = 0;
+    v.fz = 0;
+}
+
+// Apply the frozen set to H (one rank-r pass: H <- H - W' C^-1 W) and drop
+// the frozen positions from the active list.
+template <typename TG>
+__device__ __forceinline__ void compact(Sv<TG> &v, double *tile) {
+    const int r = v.r;
+    if (r == 0) return;
+    const int s = v.s;
+    v.bytes += 16.0 * (double)s * (double)s;
+    SUB_START();
+    frozen_factors(v);
+    SUB(10);
+    hupdate_all(v, s, r, tile);
+    SUB(11);
+    drop_frozen(v);
+    SUB(12);
+}
+
+// Stage the frozen set as a deferred update instead of applying it: the
+// next bordering block folds its rank into the pass that applies its own
+// update (the frozen positions stay in the list, zero in beta and z, until
+// that pass, and are dropped after it). With nothing to activate, the
+// caller applies it with flush_pending.
+template <typename TG>
+__device__ __forceinline__ void stage_frozen(Sv<TG> &v) {
+    if (v.r == 0 || v.pend != 0) return;
+    frozen_factors(v);
+    v.pend = v.r;
+    v.fz = v.r;
 }
 
 // z = (inverse of the active block without the frozen positions) * in,
@@ -908,7 +1018,9 @@ __device__ __forceinline__ void full_gradient(Sv<TG> &v) {
     const int s = v.s, M = v.M;
     v.bytes += (double)s * M * sizeof(TG);
     if (!team_on(v)) {
+        SUB_START();
         grad_rows<false>(v, v.S, v.beta, 0, s, v.g);
+        SUB(13);
         return;
     }
     int *Sg = v.Sg();
@@ -1335,6 +1447,10 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __shared__ int frz[kFz];
     __shared__ double cri[kFz * kFz + 3 * kFz + 1];
     __shared__ unsigned tsh[5];
+#ifdef PAM_PHASE_PROFILE
+    __shared__ long long sp[16];
+    if (threadIdx.x < 16) sp[threadIdx.x] = 0;
+#endif
     // Workgroups are dispatched to the 8 XCDs round robin (block b to XCD
     // b mod 8): a team takes T blocks of one XCD (shared L2 for its partial
     // results) and the leaders spread evenly over all XCDs. With T = 1 this
@@ -1374,12 +1490,16 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     v.bytes = 0.0;
     v.r = 0;
     v.pend = 0;
+    v.fz = 0;
     v.Rp = frz;
     v.Cri = cri;
     v.T = T;
     v.team_min = a.team_min;
     v.idle = a.team_idle_us > 0 ? (long long)a.team_idle_us * 100 : kTeamWait;   // 100 MHz clock
     v.tsh = tsh;
+#ifdef PAM_PHASE_PROFILE
+    v.sp = sp;
+#endif
     v.ctl = nullptr;
     v.part = nullptr;
     if (threadIdx.x < 5) tsh[threadIdx.x] = 0;
@@ -1801,7 +1921,9 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
             }
             for (int i = threadIdx.x; i < s; i += kT) v.beta[v.S[i]] = v.z[i];
             __syncthreads();
-            compact(v, tile);
+            // the frozen set's downdate rides on the next activation's update
+            if (ex) compact(v, tile);
+            else stage_frozen(v);
         }
         skip_solve = false;
         if (ex) grad64(v, P);
@@ -1855,6 +1977,13 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
             dbg_op = 3;
 #endif
             PHASE_MARK(7);
+            continue;
+        }
+        if (v.pend > 0) {
+            // a staged frozen set and nothing to activate: apply it, then
+            // select again with its coordinates inactive
+            flush_pending(v, tile);
+            skip_solve = true;
             continue;
         }
         // optimal up to the reduced-system residual r_S = g_S - lambda1 theta_S
@@ -1915,15 +2044,16 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
     const double nzs = bsum(nz, red);
     for (int m = threadIdx.x; m < a.m_cap; m += kT) beta_out[m] = m < M ? v.beta[m] : 0.0;
 #ifdef PAM_PHASE_PROFILE
-    if (threadIdx.x == 0)
-        printf("PH sub=%d M=%d s_init=%d s=%d it=%d cons=%d ls=%d rm=%d add=%d sweeps=%d it_ex=%d cg=%d us: grad0=%.0f cd=%.0f init=%.0f solve=%.0f ls=%.0f rm=%.0f fullg=%.0f act=%.0f ex=%.0f\n",
-               s_id, M, s_init, v.s, it, n_cons, n_ls, n_rm, n_add, sweeps, ran_ex ? it - it_ex0 : 0, n_cg,
-               ph[0] * 0.01, ph[1] * 0.01, ph[2] * 0.01, ph[3] * 0.01, ph[4] * 0.01, ph[5] * 0.01, ph[6] * 0.01,
-               ph[7] * 0.01, ran_ex ? (wall_clock64() - t_ex0) * 0.01 : 0.0);
-    if (threadIdx.x == 0)
-        printf("PB sub=%d MB: grad0=%.1f cd=%.1f init=%.1f solve=%.1f ls=%.1f rm=%.1f fullg=%.1f act=%.1f\n", s_id,
-               phb[0] * 1e-6, phb[1] * 1e-6, phb[2] * 1e-6, phb[3] * 1e-6, phb[4] * 1e-6, phb[5] * 1e-6,
-               phb[6] * 1e-6, phb[7] * 1e-6);
+    if (threadIdx.x == 0 && s_id < kPhaseSubs) {
+        double *o = g_phase + (size_t)s_id * kPhaseW;
+        for (int k = 0; k < 8; ++k) { o[k] = ph[k] * 0.01; o[8 + k] = phb[k]; }
+        o[16] = M; o[17] = s_init; o[18] = v.s; o[19] = it; o[20] = n_cons; o[21] = n_ls; o[22] = n_rm;
+        o[23] = n_add; o[24] = sweeps; o[25] = ran_ex ? it - it_ex0 : 0; o[26] = n_cg;
+        o[27] = ran_ex ? (wall_clock64() - t_ex0) * 0.01 : 0.0;
+        o[28] = 0.01 * (double)(wall_clock64() - t_begin);
+        o[29] = 1.0;
+        for (int k = 0; k < 15; ++k) o[30 + k] = 0.01 * (double)v.sp[k];
+    }
 #endif
     if (v.tsh[3]) status = PAM_ST_NOCONV;   // a team member did not answer: the result is not certified
     if (st && threadIdx.x == 0) {
@@ -2048,8 +2178,39 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
     // (solve_team_size), so its workgroups run together on an idle device; an
     // ordinary launch suffices because no wait depends on residency to end.
     const unsigned blocks = T > 1 ? (unsigned)(round_up(a.sub_count, 8) * T) : (unsigned)a.sub_count;
+#ifdef PAM_PHASE_PROFILE
+    {
+        std::vector<double> z((size_t)kPhaseSubs * kPhaseW, 0.0);
+        PAM_CHECK_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(g_phase), z.data(), z.size() * 8, 0, hipMemcpyHostToDevice,
+                                             ctx->stream));
+    }
+#endif
     PAM_CHECK_HIP(hipLaunchKernel(fn, dim3(blocks), dim3(kT), args, vg ? 0 : lds, ctx->stream));
     PAM_CHECK_HIP(hipGetLastError());
+#ifdef PAM_PHASE_PROFILE
+    {
+        std::vector<double> o((size_t)kPhaseSubs * kPhaseW);
+        PAM_CHECK_HIP(hipMemcpyFromSymbolAsync(o.data(), HIP_SYMBOL(g_phase), o.size() * 8, 0, hipMemcpyDeviceToHost,
+                                               ctx->stream));
+        PAM_CHECK_HIP(hipStreamSynchronize(ctx->stream));
+        for (int sidx = a.sub_begin; sidx < a.sub_begin + a.sub_count && sidx < kPhaseSubs; ++sidx) {
+            const double *r = &o[(size_t)sidx * kPhaseW];
+            if (r[29] != 1.0) continue;
+            printf("PH sub=%d M=%.0f s_init=%.0f s=%.0f it=%.0f cons=%.0f ls=%.0f rm=%.0f add=%.0f sweeps=%.0f it_ex=%.0f "
+                   "cg=%.0f us: grad0=%.0f cd=%.0f init=%.0f solve=%.0f ls=%.0f rm=%.0f fullg=%.0f act=%.0f ex=%.0f "
+                   "total=%.0f\n", sidx, r[16], r[17], r[18], r[19], r[20], r[21], r[22], r[23], r[24], r[25], r[26],
+                   r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[27], r[28]);
+            printf("SP sub=%d us: gather=%.0f upass=%.0f pendfix=%.0f cmat=%.0f chol=%.0f vmat=%.0f updz=%.0f "
+                   "hupd=%.0f border=%.0f freeze=%.0f cpv=%.0f cphupd=%.0f cpdrop=%.0f grad=%.0f hgemv=%.0f\n", sidx,
+                   r[30], r[31], r[32], r[33], r[34], r[35], r[36], r[37], r[38], r[39], r[40], r[41], r[42], r[43],
+                   r[44]);
+            printf("PB sub=%d MB: grad0=%.1f cd=%.1f init=%.1f solve=%.1f ls=%.1f rm=%.1f fullg=%.1f act=%.1f\n", sidx,
+                   r[8] * 1e-6, r[9] * 1e-6, r[10] * 1e-6, r[11] * 1e-6, r[12] * 1e-6, r[13] * 1e-6, r[14] * 1e-6,
+                   r[15] * 1e-6);
+        }
+        fflush(stdout);
+    }
+#endif
     return PAM_OK;
 }
 
