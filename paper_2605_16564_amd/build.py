@@ -15,7 +15,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "_build" / "libpam.so"
-SOURCES = ["pam_api.hip", "k_setup.hip", "k_fit.hip", "k_solve.hip", "k_refine.hip", "k_eval.hip", "k_cnn.hip",
+SOURCES = ["pam_api.hip", "k_setup.hip", "k_fit.hip", "k_solve.hip", "k_solve_f64.hip", "k_solve_f32.hip", "k_solve_vg.hip", "k_refine.hip", "k_eval.hip", "k_cnn.hip",
            "k_select.hip", "k_darcy.hip"]
 ARCH = os.environ.get("PAM_OFFLOAD_ARCH", "gfx950")
 
@@ -55,7 +55,7 @@ def build(verbose: bool = False, out: Path = OUT, defines=()) -> Path:
     if verbose:
         for cmd in cmds:
             print(" ".join(cmd), flush=True)
-    # one hipcc per source, the longest (the solve: four kernel instances) first
+    # one hipcc per source, the longest (the solve instances) first
     jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     order = sorted(cmds, key=lambda c: "k_solve" not in c[-3])
     with ThreadPoolExecutor(max_workers=jobs) as pool:
