@@ -45,16 +45,17 @@ static constexpr int kT = 512;
 static constexpr int kW = kT / 64;
 static constexpr int kB = 8;       // coordinates activated per blocked bordering step
 static constexpr int kAdd = 16;    // violators activated per consistent iteration
+static constexpr int kInit = 24;   // coordinates per activation call when a block is built from scratch
 static constexpr int kR = 1;       // GEMV outputs per thread per pass
 static constexpr int kTile = 128;  // rows staged in LDS per bordering tile
 static constexpr int kFz = 8;      // coordinates frozen before one batched downdate
 static constexpr int kQ = 24;      // rows of the low-rank update scratch (>= kFz + 2 kB)
 static constexpr int kPass = kR * kT;
-static constexpr int kUR = 16;     // rows of H in flight per thread in the bordering product
-static constexpr int kHR = 8;      // rows of H in flight per thread in the low-rank updates
+static constexpr int kUR = 8;      // rows of H per batch in the bordering product (two batches in flight)
+static constexpr int kHR = 8;      // rows of H per batch in the low-rank updates (two batches in flight)
 static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the polish
 static constexpr int kIncMax = 48;     // incremental solution updates between full solves
-static_assert(kFz <= kB && kFz + 2 * kB <= kQ, "a pair of blocks defers onto a staged frozen set");
+static_assert(kFz <= kB && kFz + 2 * kB <= kQ && kInit <= kQ, "deferred blocks fit the update scratch");
 
 // A team of up to kTeamMax workgroups may serve one subdomain (the launch is
 // sized so that the device holds all of its workgroups at once, by the
@@ -304,6 +305,37 @@ __device__ __forceinline__ void hgemv_r(Sv<TG> &v, const double *in, double *out
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
         const double *Hc = v.H + base + threadIdx.x;
         int jj = r0;
+        const int nfull = (r1 - r0) / kRows;
+        if (R <= 2 && nfull > 0) {
+            // two batches in flight: the next batch loaded while this one is used
+            double h[kRows][R];
+#pragma unroll
+            for (int q = 0; q < kRows; ++q)
+#pragma unroll
+                for (int r = 0; r < R; ++r) h[q][r] = Hc[(size_t)(jj + q) * v.ldh + r * kT];
+            for (int bi = 0; bi < nfull; ++bi, jj += kRows) {
+                const bool more = bi + 1 < nfull;
+                double hn[kRows][R];
+                if (more) {
+#pragma unroll
+                    for (int q = 0; q < kRows; ++q)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) hn[q][r] = Hc[(size_t)(jj + kRows + q) * v.ldh + r * kT];
+                }
+#pragma unroll
+                for (int q = 0; q < kRows; ++q) {
+                    const double x = in[jj + q];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] += h[q][r] * x;
+                }
+                if (more) {
+#pragma unroll
+                    for (int q = 0; q < kRows; ++q)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) h[q][r] = hn[q][r];
+                }
+            }
+        }
         for (; jj + kRows <= r1; jj += kRows) {
             double h[kRows][R];
 #pragma unroll
@@ -388,20 +420,36 @@ __device__ __forceinline__ void hupdate(Sv<TG> &v, int s, int nq, const double *
             }
             __syncthreads();
             if (!live) continue;
+            // batches of kHR rows, the next batch's loads issued before this
+            // batch's stores (rows are disjoint), so that loads stay in
+            // flight while the stores drain
+            const int nfull = tn / kHR;
             int r = 0;
-            for (; r + kHR <= tn; r += kHR) {
-                double *h = Hc + (size_t)(t0 + r) * v.ldh;
+            if (nfull > 0) {
                 double hv[kHR];
 #pragma unroll
-                for (int e = 0; e < kHR; ++e) hv[e] = h[(size_t)e * v.ldh];
+                for (int e = 0; e < kHR; ++e) hv[e] = Hc[(size_t)(t0 + e) * v.ldh];
+                for (int bi = 0; bi < nfull; ++bi, r += kHR) {
+                    const bool more = bi + 1 < nfull;
+                    double hn[kHR];
+                    if (more) {
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    const double uq = uj[q];
+                        for (int e = 0; e < kHR; ++e) hn[e] = Hc[(size_t)(t0 + r + kHR + e) * v.ldh];
+                    }
 #pragma unroll
-                    for (int e = 0; e < kHR; ++e) hv[e] += tile[q * kTile + r + e] * uq;
+                    for (int q = 0; q < NQ; ++q) {
+                        const double uq = uj[q];
+#pragma unroll
+                        for (int e = 0; e < kHR; ++e) hv[e] += tile[q * kTile + r + e] * uq;
+                    }
+                    double *h = Hc + (size_t)(t0 + r) * v.ldh;
+#pragma unroll
+                    for (int e = 0; e < kHR; ++e) h[(size_t)e * v.ldh] = hv[e];
+                    if (more) {
+#pragma unroll
+                        for (int e = 0; e < kHR; ++e) hv[e] = hn[e];
+                    }
                 }
-#pragma unroll
-                for (int e = 0; e < kHR; ++e) h[(size_t)e * v.ldh] = hv[e];
             }
             for (; r < tn; ++r) {
                 double *h = Hc + (size_t)(t0 + r) * v.ldh;
@@ -454,15 +502,29 @@ __device__ __forceinline__ void upass(Sv<TG> &v, int nb, int r0, int r1, double 
                 tile[e] = (q < nb && r < tn) ? v.Ag[(size_t)q * v.m_cap + t0 + r] : 0.0;
             }
             __syncthreads();
+            // batches of kUR rows, the next batch loaded while this one is used
+            const int nfull = tn / kUR;
             int r = 0;
-            for (; r + kUR <= tn; r += kUR) {
+            if (nfull > 0) {
                 double h[kUR];
 #pragma unroll
-                for (int e = 0; e < kUR; ++e) h[e] = Hc[(size_t)(t0 + r + e) * v.ldh];
+                for (int e = 0; e < kUR; ++e) h[e] = Hc[(size_t)(t0 + e) * v.ldh];
+                for (int bi = 0; bi < nfull; ++bi, r += kUR) {
+                    const bool more = bi + 1 < nfull;
+                    double hn[kUR];
+                    if (more) {
 #pragma unroll
-                for (int e = 0; e < kUR; ++e)
+                        for (int e = 0; e < kUR; ++e) hn[e] = Hc[(size_t)(t0 + r + kUR + e) * v.ldh];
+                    }
 #pragma unroll
-                    for (int q = 0; q < kB; ++q) acc[q] += h[e] * tile[q * kTile + r + e];
+                    for (int e = 0; e < kUR; ++e)
+#pragma unroll
+                        for (int q = 0; q < kB; ++q) acc[q] += h[e] * tile[q * kTile + r + e];
+                    if (more) {
+#pragma unroll
+                        for (int e = 0; e < kUR; ++e) h[e] = hn[e];
+                    }
+                }
             }
             for (; r < tn; ++r) {
                 const double h0 = Hc[(size_t)(t0 + r) * v.ldh];
@@ -1083,8 +1145,8 @@ __device__ __forceinline__ void rebuild(Sv<TG> &v, int *list, Red &red, double *
     for (int i = threadIdx.x; i < s; i += kT) v.pos[v.S[i]] = -1;
     __syncthreads();
     v.s = 0;
-    for (int b0 = 0; b0 < s; b0 += kAdd) {
-        const int nb = min(kAdd, s - b0);
+    for (int b0 = 0; b0 < s; b0 += kInit) {
+        const int nb = min(kInit, s - b0);
         if (threadIdx.x < nb) list[threadIdx.x] = (int)v.rhs[b0 + threadIdx.x];
         __syncthreads();
         activate(v, list, nb, red, cinv, blk, tile);
@@ -1437,7 +1499,7 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __shared__ Red red;
     __shared__ double cinv[kB * kB];
     __shared__ int blk[kB];
-    __shared__ int list[kAdd];
+    __shared__ int list[kAdd > kInit ? kAdd : kInit];
     __shared__ double tile[kQ * kTile];
     __shared__ int frz[kFz];
     __shared__ double cri[kFz * kFz + 3 * kFz + 1];
@@ -1597,7 +1659,8 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
         v.th[m] = (signed char)t;
     }
     __syncthreads();
-    // initial active block, ascending coordinate order, kAdd at a time
+    // initial active block, ascending coordinate order, kInit at a time (three
+    // bordering blocks whose updates go to H in one rank-24 pass)
     for (int m0 = 0; m0 < M; m0 += kT) {
         const int m = m0 + threadIdx.x;
         const bool on = m < M && v.th[m] != 0;
@@ -1615,8 +1678,8 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
         __syncthreads();
         if (on) v.rhs[wbase + pre] = (double)m;   // rhs is free here
         __syncthreads();
-        for (int b0 = 0; b0 < tot; b0 += kAdd) {
-            const int nb = min(kAdd, tot - b0);
+        for (int b0 = 0; b0 < tot; b0 += kInit) {
+            const int nb = min(kInit, tot - b0);
             if (threadIdx.x < nb) list[threadIdx.x] = (int)v.rhs[b0 + threadIdx.x];
             __syncthreads();
             activate(v, list, nb, red, cinv, blk, tile);
