@@ -51,7 +51,7 @@ static constexpr int kTile = 128;  // rows staged in LDS per bordering tile
 static constexpr int kFz = 8;      // coordinates frozen before one batched downdate
 static constexpr int kQ = 24;      // rows of the low-rank update scratch (>= kFz + 2 kB)
 static constexpr int kPass = kR * kT;
-static constexpr int kUR = 8;      // rows of H per batch in the bordering product (two batches in flight)
+static constexpr int kUR = 16;     // rows of H in flight per thread in the bordering product
 static constexpr int kHR = 8;      // rows of H per batch in the low-rank updates (two batches in flight)
 static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the polish
 static constexpr int kIncMax = 48;     // incremental solution updates between full solves
@@ -305,37 +305,6 @@ __device__ __forceinline__ void hgemv_r(Sv<TG> &v, const double *in, double *out
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
         const double *Hc = v.H + base + threadIdx.x;
         int jj = r0;
-        const int nfull = (r1 - r0) / kRows;
-        if (R <= 2 && nfull > 0) {
-            // two batches in flight: the next batch loaded while this one is used
-            double h[kRows][R];
-#pragma unroll
-            for (int q = 0; q < kRows; ++q)
-#pragma unroll
-                for (int r = 0; r < R; ++r) h[q][r] = Hc[(size_t)(jj + q) * v.ldh + r * kT];
-            for (int bi = 0; bi < nfull; ++bi, jj += kRows) {
-                const bool more = bi + 1 < nfull;
-                double hn[kRows][R];
-                if (more) {
-#pragma unroll
-                    for (int q = 0; q < kRows; ++q)
-#pragma unroll
-                        for (int r = 0; r < R; ++r) hn[q][r] = Hc[(size_t)(jj + kRows + q) * v.ldh + r * kT];
-                }
-#pragma unroll
-                for (int q = 0; q < kRows; ++q) {
-                    const double x = in[jj + q];
-#pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r] += h[q][r] * x;
-                }
-                if (more) {
-#pragma unroll
-                    for (int q = 0; q < kRows; ++q)
-#pragma unroll
-                        for (int r = 0; r < R; ++r) h[q][r] = hn[q][r];
-                }
-            }
-        }
         for (; jj + kRows <= r1; jj += kRows) {
             double h[kRows][R];
 #pragma unroll
@@ -502,29 +471,15 @@ __device__ __forceinline__ void upass(Sv<TG> &v, int nb, int r0, int r1, double 
                 tile[e] = (q < nb && r < tn) ? v.Ag[(size_t)q * v.m_cap + t0 + r] : 0.0;
             }
             __syncthreads();
-            // batches of kUR rows, the next batch loaded while this one is used
-            const int nfull = tn / kUR;
             int r = 0;
-            if (nfull > 0) {
+            for (; r + kUR <= tn; r += kUR) {
                 double h[kUR];
 #pragma unroll
-                for (int e = 0; e < kUR; ++e) h[e] = Hc[(size_t)(t0 + e) * v.ldh];
-                for (int bi = 0; bi < nfull; ++bi, r += kUR) {
-                    const bool more = bi + 1 < nfull;
-                    double hn[kUR];
-                    if (more) {
+                for (int e = 0; e < kUR; ++e) h[e] = Hc[(size_t)(t0 + r + e) * v.ldh];
 #pragma unroll
-                        for (int e = 0; e < kUR; ++e) hn[e] = Hc[(size_t)(t0 + r + kUR + e) * v.ldh];
-                    }
+                for (int e = 0; e < kUR; ++e)
 #pragma unroll
-                    for (int e = 0; e < kUR; ++e)
-#pragma unroll
-                        for (int q = 0; q < kB; ++q) acc[q] += h[e] * tile[q * kTile + r + e];
-                    if (more) {
-#pragma unroll
-                        for (int e = 0; e < kUR; ++e) h[e] = hn[e];
-                    }
-                }
+                    for (int q = 0; q < kB; ++q) acc[q] += h[e] * tile[q * kTile + r + e];
             }
             for (; r < tn; ++r) {
                 const double h0 = Hc[(size_t)(t0 + r) * v.ldh];
