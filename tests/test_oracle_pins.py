@@ -165,6 +165,113 @@ def test_step_fit_l1_scales_like_sigma2_over_c():
     assert np.all((ratio > 0.5) & (ratio < 2.0))
 
 
+
+# Sec. 4 in two dimensions: an interface at an angle. Centers +-c n on the
+# normal n = (cos th, sin th) through the origin; the two squared distances
+# differ by 4 c t (t = n . x), so beta = (1, 0) gives the logistic of slope
+# 2c / sigma^2 in t whatever the tangential coordinate u is.
+def _chord(t, th):
+    """[u_lo, u_hi] of the line n . x = t inside [-1, 1]^2 (x = t n + u u_hat,
+    u_hat = (-sin th, cos th)), 0 < th < pi/2."""
+    ct, st = math.cos(th), math.sin(th)
+    lo = np.maximum((t * ct - 1.0) / st, (-1.0 - t * st) / ct)
+    hi = np.minimum((t * ct + 1.0) / st, (1.0 - t * st) / ct)
+    return lo, np.maximum(hi, lo)
+
+
+def _l1_square_rotated(th, value, n_t=400, k_scale=None):
+    """int over [-1, 1]^2 of |H(n . x) - value(x)|, in (t, u): composite
+    20-point Gauss-Legendre in t with breakpoints at 0 and at the chord kinks
+    +-(cos th - sin th) (panels graded towards t = 0 on the scale k_scale),
+    10-point Gauss-Legendre in u on each chord."""
+    ct, st = math.cos(th), math.sin(th)
+    T, tmax = abs(ct - st), ct + st
+    gx, gw = np.polynomial.legendre.leggauss(20)
+    ux, uw = np.polynomial.legendre.leggauss(10)
+    inner = np.unique(np.concatenate([np.geomspace(1e-3 / k_scale, T, n_t // 2), [T]]))
+    outer = np.linspace(T, tmax, n_t // 4 + 1)
+    edges = np.concatenate([[0.0], inner, outer[1:]])
+    total = 0.0
+    for side in (-1.0, 1.0):
+        a, b = edges[:-1], edges[1:]
+        t = side * ((0.5 * (a + b))[:, None] + 0.5 * (b - a)[:, None] * gx[None, :]).ravel()
+        wt = (0.5 * (b - a)[:, None] * gw[None, :]).ravel()
+        lo, hi = _chord(t, th)
+        u = (0.5 * (lo + hi))[:, None] + 0.5 * (hi - lo)[:, None] * ux[None, :]
+        wu = 0.5 * (hi - lo)[:, None] * uw[None, :]
+        X = np.stack([t[:, None] * ct - u * st, t[:, None] * st + u * ct], axis=-1).reshape(-1, 2)
+        v = value(X).reshape(u.shape)
+        H = (t > 0).astype(float)[:, None]
+        total += float((wt[:, None] * wu * np.abs(H - v)).sum())
+    return total
+
+
+ANGLED_CASES = [(math.radians(30.0), 0.3, 0.05), (math.radians(10.0), 0.5, 0.1), (math.radians(40.0), 0.4, 0.05)]
+
+
+@pytest.mark.parametrize("th,c,sigma", ANGLED_CASES)
+def test_two_center_logistic_2d_angled(th, c, sigma):
+    """Theorem (Sec. 4) at an angle: the oracle's two-center Shepard field
+    is logistic(2 c t / sigma^2) at every tangential offset u."""
+    n = np.array([math.cos(th), math.sin(th)])
+    cen = np.stack([c * n, -c * n])
+    D, axis, beta = _single_model(-1.0, 1.0, cen, np.array([sigma, sigma]), [1.0, 0.0])
+    k = 2.0 * c / sigma ** 2
+    t = np.linspace(-25.0 / k, 25.0 / k, 101)
+    u = np.linspace(-0.4, 0.4, 9)
+    T, U = np.meshgrid(t, u, indexing="ij")
+    X = np.stack([T * n[0] - U * n[1], T * n[1] + U * n[0]], axis=-1).reshape(-1, 2)
+    v, _ = O.evaluate(axis, D, beta, X)
+    ref = 1.0 / (1.0 + np.exp(-k * T.ravel()))
+    assert np.max(np.abs(v - ref) / np.maximum(ref, 1e-300)) < 1e-11
+
+
+@pytest.mark.parametrize("th,c,sigma", ANGLED_CASES)
+def test_two_center_l1_2d_angled_closed_form(th, c, sigma):
+    """Eq. (1d_error) per unit length of interface: on [-1, 1]^2 with the
+    interface through the center at angle th, every chord |t| <= cos th -
+    sin th has length 2 / cos th, so int |H - K*| = (2 / cos th) (2 / k)
+    (ln 2 - ln(1 + exp(-k T))) + the corners (below exp(-k T)), k = 2c/sigma^2."""
+    n = np.array([math.cos(th), math.sin(th)])
+    cen = np.stack([c * n, -c * n])
+    D, axis, beta = _single_model(-1.0, 1.0, cen, np.array([sigma, sigma]), [1.0, 0.0])
+    k = 2.0 * c / sigma ** 2
+    T = math.cos(th) - math.sin(th)
+    assert k * T > 30.0   # the corners are below exp(-30) relative
+    got = _l1_square_rotated(th, lambda X: O.evaluate(axis, D, beta, X)[0], k_scale=k)
+    exact = (2.0 / math.cos(th)) * (2.0 / k) * (math.log(2.0) - math.log1p(math.exp(-k * T)))
+    assert abs(got - exact) / exact < 1e-9
+    # the law of the theorem: ln 2 sigma^2 / c per unit length of interface
+    assert abs(got / (2.0 / math.cos(th)) - math.log(2.0) * sigma ** 2 / c) / (math.log(2.0) * sigma ** 2 / c) < 1e-9
+
+
+def test_step_fit_l1_scales_like_sigma2_over_c_2d():
+    """a3-a6 on a 2-D jump across a line at 30 degrees (cell-centered samples
+    of H(n . x) on a 100 x 100 grid of [-1, 1]^2): two fitted centers at
+    +-c n; the L1 error of the fitted field over the square follows the
+    theorem's sigma^2 / c law (log-log slope 1) and its size per unit length
+    of interface is ln 2 sigma^2 / c to a factor of 2."""
+    th = math.radians(30.0)
+    n = np.array([math.cos(th), math.sin(th)])
+    g = (np.arange(100) + 0.5) * 0.02 - 1.0
+    X1, X2 = np.meshgrid(g, g, indexing="ij")
+    xs = np.stack([X1.ravel(), X2.ravel()], axis=1)
+    y = (xs @ n > 0).astype(float)
+    c = 0.3
+    sig = np.array([0.04, 0.06, 0.09])
+    l1 = []
+    for s in sig:
+        cen = np.stack([c * n, -c * n])
+        beta, st, _ = O.fit_one(xs, y, cen, np.array([s, s]), 0.0, 0.0, cd_sweeps=4)
+        assert st == 0
+        D, axis, _ = _single_model(-1.0, 1.0, cen, np.array([s, s]), beta)
+        l1.append(_l1_square_rotated(th, lambda X: O.evaluate(axis, D, beta, X)[0], k_scale=2 * c / s ** 2))
+    slope = np.polyfit(np.log(sig ** 2 / c), np.log(l1), 1)[0]
+    assert abs(slope - 1.0) < 0.05
+    per_length = np.array(l1) / (2.0 / math.cos(th))
+    ratio = per_length / (math.log(2) * sig ** 2 / c)
+    assert np.all((ratio > 0.5) & (ratio < 2.0))
+
 # ---------------------------------------------------------------- elastic net
 def _brute_force_enet(G, b, l1, l2):
     """Enumerate all 3^M sign patterns; return the KKT-feasible solutions."""
