@@ -455,18 +455,28 @@ __device__ __forceinline__ void hupdate_all(Sv<TG> &v, int s, int nq, double *ti
 // out[q][i] = sum_{r0 <= t < r1} H[t][i] Ag[q][t] for i < s, q < nb (rows
 // [q * m_cap, ...) of out): one pass over rows [r0, r1) of H for all nb
 // columns, the rows of Ag staged through LDS tiles.
+template <int NB, typename TG>
+__device__ __forceinline__ void upass_n(Sv<TG> &v, int nb, int r0, int r1, double *out, double *tile);
+
 template <typename TG>
 __device__ __forceinline__ void upass(Sv<TG> &v, int nb, int r0, int r1, double *out, double *tile) {
+    upass_n<kB>(v, nb, r0, r1, out, tile);
+}
+
+// upass for up to NB columns (rows [0, nb) of Ag): NB = 2 kB serves two
+// consecutive bordering blocks in one pass over H.
+template <int NB, typename TG>
+__device__ __forceinline__ void upass_n(Sv<TG> &v, int nb, int r0, int r1, double *out, double *tile) {
     const int s = v.s;
     for (int base = 0; base < s; base += kPass) {
-        double acc[kB];
+        double acc[NB];
 #pragma unroll
-        for (int q = 0; q < kB; ++q) acc[q] = 0.0;
+        for (int q = 0; q < NB; ++q) acc[q] = 0.0;
         const double *Hc = v.H + base + threadIdx.x;
         for (int t0 = r0; t0 < r1; t0 += kTile) {
             const int tn = min(kTile, r1 - t0);
             __syncthreads();
-            for (int e = threadIdx.x; e < kB * kTile; e += kT) {
+            for (int e = threadIdx.x; e < NB * kTile; e += kT) {
                 const int q = e / kTile, r = e - q * kTile;
                 tile[e] = (q < nb && r < tn) ? v.Ag[(size_t)q * v.m_cap + t0 + r] : 0.0;
             }
@@ -479,12 +489,12 @@ __device__ __forceinline__ void upass(Sv<TG> &v, int nb, int r0, int r1, double 
 #pragma unroll
                 for (int e = 0; e < kUR; ++e)
 #pragma unroll
-                    for (int q = 0; q < kB; ++q) acc[q] += h[e] * tile[q * kTile + r + e];
+                    for (int q = 0; q < NB; ++q) acc[q] += h[e] * tile[q * kTile + r + e];
             }
             for (; r < tn; ++r) {
                 const double h0 = Hc[(size_t)(t0 + r) * v.ldh];
 #pragma unroll
-                for (int q = 0; q < kB; ++q) acc[q] += h0 * tile[q * kTile + r];
+                for (int q = 0; q < NB; ++q) acc[q] += h0 * tile[q * kTile + r];
             }
         }
         const int i = base + threadIdx.x;
@@ -531,13 +541,15 @@ __device__ __forceinline__ double dot16(const double *x, const double *y, int l1
 // streams H three times instead of four.
 template <typename TG>
 __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red &red, double *cinv, double *tile,
-                                          bool upd_z = false, bool defer = false) {
+                                          bool upd_z = false, bool defer = false, const int *ks_next = nullptr,
+                                          int nb_next = 0, bool pre = false) {
     const int s = v.s, pend = v.pend;
     double *Ub = v.U + (size_t)pend * v.m_cap, *Vb = v.V + (size_t)pend * v.m_cap;
-    v.bytes += 8.0 * (double)s * (double)s + (double)nb * s * sizeof(TG);
+    v.bytes += (pre ? 0.0 : 8.0 * (double)s * (double)s) + (double)(nb + nb_next) * s * sizeof(TG);
     SUB_START();
     // A_SB: the nb Gram rows of the block at the active coordinates (all
-    // loads of a thread issued before its stores)
+    // loads of a thread issued before its stores); with nb_next, the next
+    // block's rows too (rows [kB, kB + nb_next) of Ag), for a shared pass
     for (int i = threadIdx.x; i < s; i += kT) {
         const int k = v.S[i];
         TG gq[kB];
@@ -546,11 +558,52 @@ __device__ __forceinline__ bool add_block(Sv<TG> &v, const int *ks, int nb, Red 
 #pragma unroll
         for (int q = 0; q < kB; ++q)
             if (q < nb) v.Ag[(size_t)q * v.m_cap + i] = (double)gq[q];
+        if (nb_next > 0) {
+#pragma unroll
+            for (int q = 0; q < kB; ++q) gq[q] = q < nb_next ? v.G[(size_t)ks_next[q] * v.mpad + k] : (TG)0;
+#pragma unroll
+            for (int q = 0; q < kB; ++q)
+                if (q < nb_next) v.Ag[(size_t)(kB + q) * v.m_cap + i] = (double)gq[q];
+        }
     }
     __syncthreads();
     SUB(0);
-    // U = H A_SB: one pass over H for all nb columns
-    if (!team_on(v)) {
+    if (pre) {
+        // U over the old positions i < k0 came from the previous block's
+        // shared pass (H of the block before it, which that block left
+        // unchanged: it deferred its update); add the previous block's border
+        // rows k0.. of H (in the order the pass over H would), and take the
+        // new positions' entries as dots of their border rows with A_SB
+        const int k0 = s - kB;
+        for (int i = threadIdx.x; i < k0; i += kT) {
+            double hb[kB];
+#pragma unroll
+            for (int p = 0; p < kB; ++p) hb[p] = v.H[(size_t)(k0 + p) * v.ldh + i];
+            for (int q = 0; q < nb; ++q) {
+                double acc = Ub[(size_t)q * v.m_cap + i];
+#pragma unroll
+                for (int p = 0; p < kB; ++p) acc += hb[p] * v.Ag[(size_t)q * v.m_cap + k0 + p];
+                Ub[(size_t)q * v.m_cap + i] = acc;
+            }
+        }
+        for (int pair0 = 0; pair0 < kB * kB; pair0 += kT / 16) {
+            const int pair = pair0 + (threadIdx.x >> 4), l16 = threadIdx.x & 15;
+            const int p = pair / kB, q = pair % kB;
+            double acc = 0.0;
+            if (pair < kB * kB && q < nb)
+                acc = dot16(v.H + (size_t)(k0 + p) * v.ldh, v.Ag + (size_t)q * v.m_cap, l16, s);
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 16);
+            if (l16 == 0 && pair < kB * kB && q < nb) Ub[(size_t)q * v.m_cap + k0 + p] = acc;
+        }
+        __syncthreads();
+    } else if (nb_next > 0) {
+        // one pass over H for this block's nb = kB columns and the next
+        // block's nb_next: rows [0, kB + nb_next) of Ub (the next block's
+        // rows start where its own Ub will, this block deferring its update)
+        upass_n<2 * kB>(v, kB + nb_next, 0, s, Ub, tile);
+    } else if (!team_on(v)) {
+        // U = H A_SB: one pass over H for all nb columns
         upass(v, nb, 0, s, Ub, tile);
     } else {
         team_post(v, OP_UPASS, s, nb);
@@ -1058,15 +1111,22 @@ template <typename TG>
 __device__ __forceinline__ bool activate(Sv<TG> &v, int *list, int n, Red &red, double *cinv, int *blk, double *tile,
                                          bool upd_z = false) {
     bool any = false;
+    bool pre = false;   // this block's product came from the previous block's pass
     for (int b0 = 0; b0 < n; b0 += kB) {
         const int nb = min(kB, n - b0);
         if (threadIdx.x < nb) blk[threadIdx.x] = list[b0 + threadIdx.x];
         __syncthreads();
-        // a block followed by another defers its update to the pair's end
-        if (add_block(v, blk, nb, red, cinv, tile, upd_z, b0 + nb < n)) {
+        // a full block followed by another shares its pass over H with it
+        // (one workgroup only: the team's partial results hold kB columns);
+        // a block followed by another defers its update
+        const int nb_next = (!pre && nb == kB && b0 + nb < n && !team_on(v) && v.pend + 2 * kB <= kQ)
+                                ? min(kB, n - b0 - nb) : 0;
+        if (add_block(v, blk, nb, red, cinv, tile, upd_z, b0 + nb < n, list + b0 + nb, nb_next, pre)) {
             any = true;
+            pre = nb_next > 0;
             continue;
         }
+        pre = false;
         for (int q = 0; q < nb; ++q) {
             const int k = list[b0 + q];
             if (threadIdx.x == 0) blk[0] = k;
