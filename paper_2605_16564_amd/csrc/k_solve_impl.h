@@ -26,13 +26,13 @@
 // per-subdomain phase record of the profile build: [0, 8) microseconds per
 // phase, [8, 16) bytes per phase, [16, 28) counts (written by thread 0 at the
 // end of the solve, read and printed by the host after each launch)
-static constexpr int kPhaseW = 48, kPhaseSubs = 8192;
+static constexpr int kPhaseW = 56, kPhaseSubs = 8192;
 static __device__ double g_phase[kPhaseSubs * kPhaseW];
 #define PHASE_MARK(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); ph[k] += _t - ph_last; ph_last = _t; phb[k] += v.bytes - phb_last; phb_last = v.bytes; } } while (0)
 // sub-phases (thread 0's clock at the block's sync points): SUB_START opens a
 // region, SUB(k) adds the time since the last mark to slot k
-#define SUB_START() do { if (threadIdx.x == 0) v.sp[15] = wall_clock64(); } while (0)
-#define SUB(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); v.sp[k] += _t - v.sp[15]; v.sp[15] = _t; } } while (0)
+#define SUB_START() do { if (threadIdx.x == 0) v.sp[23] = wall_clock64(); } while (0)
+#define SUB(k) do { if (threadIdx.x == 0) { long long _t = wall_clock64(); v.sp[k] += _t - v.sp[23]; v.sp[23] = _t; } } while (0)
 #else
 #define PHASE_MARK(k) do { } while (0)
 #define SUB_START() do { } while (0)
@@ -215,7 +215,7 @@ struct Sv {
     double *part;              // team scratch
     unsigned *tsh;             // LDS [5]: command broadcast, commands posted, failure
 #ifdef PAM_PHASE_PROFILE
-    long long *sp;             // LDS [16] sub-phase clocks
+    long long *sp;             // LDS [24] sub-phase clocks
 #endif
     __device__ double *xin() const { return part + (size_t)kTeamMax * kB * m_cap; }
     __device__ double *bco() const { return part + (size_t)(kTeamMax * kB + 1) * m_cap; }
@@ -879,36 +879,6 @@ __device__ __forceinline__ void freeze(Sv<TG> &v, int p, bool upd_z = false) {
     v.r = r + 1;
 }
 
-// z += d * (column p of the effective inverse H - W C^-1 W'): the solution
-// after the right-hand side of position p changed by d.
-template <typename TG>
-__device__ __forceinline__ void heff_axpy(Sv<TG> &v, int p, double d) {
-    const int s = v.s, r = v.r;
-    double *t = v.Cri + kFz * kFz + 2 * kFz + 1;   // [kFz] scratch after delta
-    // t = C^-1 W[p, .]': the r entries of W at p fetched in parallel first
-    double *wp = v.Cri + kFz * kFz;   // c of freeze, free here
-    if ((int)threadIdx.x < r) wp[threadIdx.x] = v.U[(size_t)threadIdx.x * v.m_cap + p];
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int q = 0; q < r; ++q) {
-            double acc = 0.0;
-            for (int k = 0; k < r; ++k) acc += v.Cri[q * kFz + k] * wp[k];
-            t[q] = acc;
-        }
-    __syncthreads();
-    for (int i = threadIdx.x; i < s; i += kT) {
-        double h = v.H[(size_t)p * v.ldh + i];
-        for (int q = 0; q < r; ++q) h -= v.U[(size_t)q * v.m_cap + i] * t[q];
-        v.z[i] += d * h;
-    }
-    __syncthreads();
-    // frozen positions stay exactly zero
-    if ((int)threadIdx.x < r) v.z[v.Rp[threadIdx.x]] = 0.0;
-    __syncthreads();
-}
-
-// V = -C^-1 W over the live block (rows [0, r) of V; W is in rows [0, r)
-// of U): the frozen set's downdate H <- H + V' W as a rank-r update.
 template <typename TG>
 __device__ __forceinline__ void frozen_factors(Sv<TG> &v) {
     const int r = v.r, s = v.s;
@@ -944,6 +914,85 @@ __device__ __forceinline__ void drop_frozen(Sv<TG> &v) {
     }
     v.r = 0;
     v.fz = 0;
+}
+
+// z += sum_p u_p (column p of the effective inverse H - W C^-1 W') over the
+// positions p with u_p != 0 (right-hand sides moved by u_p), then u_p = 0:
+// the update for all of them in one pass over their rows of H. Returns their
+// number. The position list goes to v.rhs (free between solves).
+template <typename TG>
+__device__ __forceinline__ int heff_axpy_all(Sv<TG> &v, Red &red) {
+    const int s = v.s, r = v.r;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int nf = 0;
+    for (int i0 = 0; i0 < s; i0 += kT) {
+        const int i = i0 + threadIdx.x;
+        const bool on = i < s && v.u[i] != 0.0;
+        const unsigned long long bal = __ballot(on);
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) red.i[wid] = __popcll(bal);
+        __syncthreads();
+        int wbase = 0, tot = 0;
+        for (int w = 0; w < kW; ++w) {
+            if (w < wid) wbase += red.i[w];
+            tot += red.i[w];
+        }
+        __syncthreads();
+        if (on) v.rhs[nf + wbase + pre] = (double)i;
+        nf += tot;
+    }
+    __syncthreads();
+    if (nf == 0) return 0;
+    // T = C^-1 (sum_p u_p W[., p]) for the frozen correction
+    double T[kFz];
+    {
+        double wsum[kFz];
+#pragma unroll
+        for (int q = 0; q < kFz; ++q) wsum[q] = 0.0;
+        for (int j = threadIdx.x; j < nf; j += kT) {
+            const int p = (int)v.rhs[j];
+            const double d = v.u[p];
+#pragma unroll
+            for (int q = 0; q < kFz; ++q)
+                if (q < r) wsum[q] += d * v.U[(size_t)q * v.m_cap + p];
+        }
+        if (r > 0) bsum_vec<kFz>(wsum, red);
+#pragma unroll
+        for (int q = 0; q < kFz; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < kFz; ++k) acc += (q < r && k < r) ? v.Cri[q * kFz + k] * wsum[k] : 0.0;
+            T[q] = acc;
+        }
+    }
+    for (int i = threadIdx.x; i < s; i += kT) {
+        double acc = 0.0;
+        int j = 0;
+        for (; j + 4 <= nf; j += 4) {
+            double h[4], d[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int p = (int)v.rhs[j + e];
+                h[e] = v.H[(size_t)p * v.ldh + i];
+                d[e] = v.u[p];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc += d[e] * h[e];
+        }
+        for (; j < nf; ++j) {
+            const int p = (int)v.rhs[j];
+            acc += v.u[p] * v.H[(size_t)p * v.ldh + i];
+        }
+        for (int q = 0; q < r; ++q) acc -= v.U[(size_t)q * v.m_cap + i] * T[q];
+        v.z[i] += acc;
+    }
+    v.bytes += 8.0 * (double)s * nf;
+    __syncthreads();
+    // frozen positions stay exactly zero; the moved right-hand sides are used
+    if ((int)threadIdx.x < r) v.z[v.Rp[threadIdx.x]] = 0.0;
+    for (int j = threadIdx.x; j < nf; j += kT) v.u[(int)v.rhs[j]] = 0.0;
+    __syncthreads();
+    return nf;
 }
 
 // Apply the frozen set to H (one rank-r pass: H <- H - W' C^-1 W) and drop
@@ -1520,8 +1569,8 @@ k_solve(FitArgs a, const TG *__restrict__ Gall, double *__restrict__ Hall,
     __shared__ double cri[kFz * kFz + 3 * kFz + 1];
     __shared__ unsigned tsh[5];
 #ifdef PAM_PHASE_PROFILE
-    __shared__ long long sp[16];
-    if (threadIdx.x < 16) sp[threadIdx.x] = 0;
+    __shared__ long long sp[24];
+    if (threadIdx.x < 24) sp[threadIdx.x] = 0;
 #endif
     // Workgroups are dispatched to the 8 XCDs round robin (block b to XCD
     // b mod 8): a team takes T blocks of one XCD (shared L2 for its partial
@@ -1814,7 +1863,9 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
             };
             bool fresh = true;
             if (ex) {
+                SUB_START();
                 n_cg += cg64(v, P, red, gtol, v.z);
+                SUB(19);
             } else if (zv && n_inc < kIncMax) {
                 fresh = n_inc == 0;   // carried by the identities
 #ifdef PAM_INC_CHECK
@@ -1923,6 +1974,7 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
                 }
                 const double tstar = best_t;
                 PHASE_MARK(4);
+                SUB_START();
                 for (int i = threadIdx.x; i < s; i += kT) {
                     const int k = v.S[i];
                     const double b0 = v.beta[k], zi = v.z[i];
@@ -1939,28 +1991,21 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
                     v.th[k] = (signed char)t1;
                 }
                 __syncthreads();
+                SUB(15);
                 const bool inc = zv && !ex;
                 if (inc) {
-                    for (;;) {
-                        VI x; x.v = -1.0; x.i = -1;
-                        for (int i = threadIdx.x; i < s; i += kT)
-                            if (v.u[i] != 0.0) { VI c; c.v = (double)i; c.i = i; x = vmax(x, c); }
-                        x = bargmax(x, red);
-                        if (x.i < 0) break;
-                        const double d = v.u[x.i];
-                        __syncthreads();
-                        if (threadIdx.x == 0) v.u[x.i] = 0.0;
-                        heff_axpy(v, x.i, d);
-                        ++n_inc;
+                    const int nf = heff_axpy_all(v, red);
+                    n_inc += nf;
 #ifdef PAM_INC_CHECK
-                        dbg_op = (dbg_op % 1000) * 10 + 1;
+                    if (nf > 0) dbg_op = (dbg_op % 1000) * 10 + 1;
 #endif
-                    }
                 } else {
                     zv = false;
                 }
+                SUB(16);
                 // freeze the coordinates that reached zero (batched downdate)
                 for (;;) {
+                    SUB_START();
                     VI x; x.v = -1.0; x.i = -1;
                     for (int p = threadIdx.x; p < v.s; p += kT) {
                         if (v.th[v.S[p]] != 0) continue;
@@ -1971,6 +2016,7 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
                         x = vmax(x, c);
                     }
                     x = bargmax(x, red);
+                    SUB(17);
                     if (x.i < 0) break;
                     if (v.r == kFz) {
                         compact(v, tile);
@@ -2005,6 +2051,7 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
 #ifdef PAM_PHASE_PROFILE
         ++n_cons;
 #endif
+        SUB_START();
         // worst inactive violations (up to kAdd, by |g| then index), bordered
         // kB at a time
         int nadd = 0;
@@ -2029,6 +2076,7 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
             // after many iterations fall back to one activation per step
             if (it > 4 * M) break;
         }
+        SUB(18);
         if (nadd > 0) {
 #ifdef PAM_PHASE_PROFILE
             n_add += nadd;
@@ -2125,7 +2173,7 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
         o[27] = ran_ex ? (wall_clock64() - t_ex0) * 0.01 : 0.0;
         o[28] = 0.01 * (double)(wall_clock64() - t_begin);
         o[29] = 1.0;
-        for (int k = 0; k < 15; ++k) o[30 + k] = 0.01 * (double)v.sp[k];
+        for (int k = 0; k < 23; ++k) o[30 + k] = 0.01 * (double)v.sp[k];
     }
 #endif
     if (v.tsh[3]) status = PAM_ST_NOCONV;   // a team member did not answer: the result is not certified
