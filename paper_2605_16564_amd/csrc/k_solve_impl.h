@@ -55,6 +55,11 @@ static constexpr int kUR = 16;     // rows of H in flight per thread in the bord
 static constexpr int kHR = 8;      // rows of H per batch in the low-rank updates (two batches in flight)
 static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the polish
 static constexpr int kIncMax = 48;     // incremental solution updates between full solves
+// a sign-consistent carried solution is confirmed by a full solve only when
+// more than kConfirm incremental updates separate it from the last full solve
+// (each loses about eps cond(G); the steps it accepts are still certified by
+// the reduced-system residual and the KKT check at the end)
+static constexpr int kConfirm = 24;
 static_assert(kFz <= kB && kFz + 2 * kB <= kQ && kInit <= kQ, "deferred blocks fit the update scratch");
 
 // A team of up to kTeamMax workgroups may serve one subdomain (the launch is
@@ -1902,10 +1907,11 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
             bool mine = true;
             for (int i = threadIdx.x; i < s; i += kT)
                 if ((int)sgn(v.z[i]) != v.th[v.S[i]]) mine = false;
-            // the carried solution steers line searches; a step is accepted
-            // as consistent only on a solve of its own (the identities lose
-            // about eps * cond(G) per update)
-            if (!fresh && ball(mine, red)) {
+            // the carried solution steers line searches; after more than
+            // kConfirm updates a step is accepted as consistent only on a
+            // solve of its own (the identities lose about eps * cond(G) per
+            // update)
+            if (!fresh && n_inc > kConfirm && ball(mine, red)) {
                 solve_full();
                 mine = true;
                 for (int i = threadIdx.x; i < s; i += kT)
