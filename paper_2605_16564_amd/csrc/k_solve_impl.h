@@ -2060,27 +2060,89 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
         SUB_START();
         // worst inactive violations (up to kAdd, by |g| then index), bordered
         // kB at a time
+        // (after many iterations: one activation per step). Each wave takes
+        // its own best kAdd by repeated wave reductions, each pick the best
+        // candidate ordered after the previous one; wave 0 then takes the
+        // best of the waves' picks the same way: the same list, in the same
+        // order, as kAdd block-wide reductions, with two barriers.
+        const int kmax = it > 4 * M ? 1 : kAdd;
         int nadd = 0;
-        for (int q = 0; q < kAdd; ++q) {
-            VI x; x.v = -1.0; x.i = -1;
-            for (int m = threadIdx.x; m < M; m += kT) {
-                if (v.pos[m] >= 0) continue;
-                bool taken = false;
-                for (int e = 0; e < nadd; ++e) taken |= list[e] == m;
-                if (taken) continue;
-                VI c; c.v = fabs(v.g[m]); c.i = m;
-                x = vmax(x, c);
+        {
+            static_assert(kW * kAdd == 2 * 64, "the waves' picks are two per lane of one wave");
+            const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            double *cv = tile, *ci = tile + kW * kAdd;   // the waves' picks (tile is free here)
+            double pv = INFINITY;
+            int pi = -1;
+            int r = 0;
+            for (; r < kmax; ++r) {
+                VI x; x.v = -1.0; x.i = -1;
+                for (int m = lane + 64 * wid; m < M; m += kT) {
+                    if (v.pos[m] >= 0) continue;
+                    const double c = fabs(v.g[m]);
+                    if (!(c < pv || (c == pv && m > pi))) continue;   // ordered after the last pick
+                    VI cc; cc.v = c; cc.i = m;
+                    x = vmax(x, cc);
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    VI y;
+                    y.v = __shfl_xor(x.v, o, 64);
+                    y.i = __shfl_xor(x.i, o, 64);
+                    x = vmax(x, y);
+                }
+                if (x.i < 0 || x.v <= viol_tol) break;   // uniform over the wave
+                if (lane == 0) {
+                    cv[wid * kAdd + r] = x.v;
+                    ci[wid * kAdd + r] = (double)x.i;
+                }
+                pv = x.v;
+                pi = x.i;
             }
-            x = bargmax(x, red);
-            if (x.i < 0 || x.v <= viol_tol) break;
-            if (threadIdx.x == 0) {
-                list[nadd] = x.i;
-                v.th[x.i] = (signed char)sgn(v.g[x.i]);
+            if (lane == 0)
+                for (; r < kAdd; ++r) {
+                    cv[wid * kAdd + r] = -1.0;
+                    ci[wid * kAdd + r] = -1.0;
+                }
+            __syncthreads();
+            if (wid == 0) {
+                double mv[2];
+                int mi[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    mv[e] = cv[lane + 64 * e];
+                    mi[e] = (int)ci[lane + 64 * e];
+                }
+                pv = INFINITY;
+                pi = -1;
+                int n = 0;
+                for (; n < kmax; ++n) {
+                    VI x; x.v = -1.0; x.i = -1;
+#pragma unroll
+                    for (int e = 0; e < 2; ++e)
+                        if (mi[e] >= 0 && (mv[e] < pv || (mv[e] == pv && mi[e] > pi))) {
+                            VI cc; cc.v = mv[e]; cc.i = mi[e];
+                            x = vmax(x, cc);
+                        }
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) {
+                        VI y;
+                        y.v = __shfl_xor(x.v, o, 64);
+                        y.i = __shfl_xor(x.i, o, 64);
+                        x = vmax(x, y);
+                    }
+                    if (x.i < 0) break;
+                    if (lane == 0) {
+                        list[n] = x.i;
+                        v.th[x.i] = (signed char)sgn(v.g[x.i]);
+                    }
+                    pv = x.v;
+                    pi = x.i;
+                }
+                if (lane == 0) red.count = n;
             }
             __syncthreads();
-            ++nadd;
-            // after many iterations fall back to one activation per step
-            if (it > 4 * M) break;
+            nadd = red.count;
+            __syncthreads();
         }
         SUB(18);
         if (nadd > 0) {
