@@ -139,9 +139,9 @@ pam_status launch_solve(pam_ctx *ctx, const FitArgs &a) {
                    r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[27], r[28]);
             printf("SP sub=%d us: gather=%.0f upass=%.0f pendfix=%.0f cmat=%.0f chol=%.0f vmat=%.0f updz=%.0f "
                    "hupd=%.0f border=%.0f freeze=%.0f cpv=%.0f cphupd=%.0f cpdrop=%.0f grad=%.0f hgemv=%.0f lsupd=%.0f "
-                   "inc=%.0f fzscan=%.0f select=%.0f cg=%.0f\n", sidx,
+                   "inc=%.0f fzscan=%.0f select=%.0f cg=%.0f w64=%.0f grad64=%.0f excompact=%.0f\n", sidx,
                    r[30], r[31], r[32], r[33], r[34], r[35], r[36], r[37], r[38], r[39], r[40], r[41], r[42], r[43],
-                   r[44], r[45], r[46], r[47], r[48], r[49]);
+                   r[44], r[45], r[46], r[47], r[48], r[49], r[50], r[51], r[52]);
             printf("PB sub=%d MB: grad0=%.1f cd=%.1f init=%.1f solve=%.1f ls=%.1f rm=%.1f fullg=%.1f act=%.1f\n", sidx,
                    r[8] * 1e-6, r[9] * 1e-6, r[10] * 1e-6, r[11] * 1e-6, r[12] * 1e-6, r[13] * 1e-6, r[14] * 1e-6,
                    r[15] * 1e-6);

@@ -1320,28 +1320,47 @@ __device__ __forceinline__ void center_pass(const Pol &P, int n, K key, F out) {
 // basis) for all m < M, j < N: one exponential per entry, built once when the
 // FP64 phase starts; every later product streams it.
 template <typename TG>
-__device__ __forceinline__ void build_w64(Sv<TG> &v, const Pol &P) {
-    v.bytes += (P.plain ? 8.0 : 24.0) * (double)v.M * (double)P.N;
-    for (int j = threadIdx.x; j < P.N; j += kT) {
+__device__ __forceinline__ void build_w64(Sv<TG> &v, const Pol &P, double *tile) {
+    // W64[m][j] = phi_mj / sum_k phi_kj: per sample j the sum over all M
+    // centers first, then the normalized entries written once (the
+    // exponentials are recomputed, the same values in the same order); the
+    // centers and widths are staged in LDS in chunks of kCW
+    constexpr int kCW = 512;
+    static_assert(4 * kCW <= kQ * kTile, "center staging fits the tile");
+    double *scx = tile, *sw = tile + 3 * kCW;
+    const int M = v.M;
+    v.bytes += 8.0 * (double)M * (double)P.N;
+    for (int j0 = 0; j0 < P.N; j0 += kT) {
+        const int j = j0 + threadIdx.x;
+        const bool live = j < P.N;
         double xj[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) xj[a] = a < P.dim ? P.x[(size_t)j * P.dim + a] : 0.0;
-        double sj = 0.0;
-        for (int m = 0; m < v.M; ++m) {
-            double d = 0.0;
+        for (int a = 0; a < 3; ++a) xj[a] = (live && a < P.dim) ? P.x[(size_t)j * P.dim + a] : 0.0;
+        double is = 1.0;
+        for (int pass = P.plain ? 1 : 0; pass < 2; ++pass) {
+            double sj = 0.0;
+            for (int m0 = 0; m0 < M; m0 += kCW) {
+                const int cnt = min(kCW, M - m0);
+                __syncthreads();
+                for (int t = threadIdx.x; t < cnt; t += kT) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double ca = a < P.dim ? P.c[(size_t)m * P.dim + a] : 0.0;
-                d += (xj[a] - ca) * (xj[a] - ca);
+                    for (int a = 0; a < 3; ++a) scx[t * 3 + a] = a < P.dim ? P.c[(size_t)(m0 + t) * P.dim + a] : 0.0;
+                    sw[t] = P.w[m0 + t];
+                }
+                __syncthreads();
+                if (!live) continue;
+                for (int t = 0; t < cnt; ++t) {
+                    double d = 0.0;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) d += (xj[a] - scx[t * 3 + a]) * (xj[a] - scx[t * 3 + a]);
+                    const double f = exp(d * sw[t]);
+                    if (pass == 0) sj += f;
+                    else P.W[(size_t)(m0 + t) * P.ldw + j] = P.plain ? f : f * is;
+                }
             }
-            const double f = exp(d * P.w[m]);
-            P.W[(size_t)m * P.ldw + j] = f;
-            sj += f;
+            if (pass == 0) is = 1.0 / sj;
         }
-        const double is = P.plain ? 1.0 : 1.0 / sj;
-        P.is[j] = is;
-        if (!P.plain)
-            for (int m = 0; m < v.M; ++m) P.W[(size_t)m * P.ldw + j] *= is;
+        if (live) P.is[j] = is;
     }
     __syncthreads();
 }
@@ -1823,8 +1842,11 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
         if (status != PAM_ST_OK) break;
         __syncthreads();
         compact(v, tile);
-        build_w64(v, P);
+        SUB_START();
+        build_w64(v, P, tile);
+        SUB(20);
         grad64(v, P);
+        SUB(21);
         status = PAM_ST_NOCONV;
         refines = 0;
         rebuilds = 0;
@@ -1853,7 +1875,9 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
             skip_solve = false;
         }
         if (v.s > 0 && !skip_solve) {
+            SUB_START();
             if (ex) compact(v, tile);   // the CG solve runs on live positions only
+            SUB(22);
             const int s = v.s;
             // full solve of the signed block into v.z
             auto solve_full = [&]() {
