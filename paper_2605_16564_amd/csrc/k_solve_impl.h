@@ -1715,10 +1715,15 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
     // and a support hint (cold fits only) replaces the warm-up
     const uint8_t *hint = (a.hint && !a.warm_start) ? a.hint + (size_t)s_id * a.m_cap : nullptr;
     const int cd_sweeps = (a.warm_start || hint) ? 0 : a.cd_sweeps;
+    if (cd_sweeps > 0) {
+        // diagonal of the Gram + lambda2 in LDS (u is free until the active set)
+        for (int m = threadIdx.x; m < M; m += kT) v.u[m] = Gat(v, m, m) + v.l2;
+        __syncthreads();
+    }
     for (; sweeps < cd_sweeps; ++sweeps) {
         double dmax = 0.0;
         for (int m = 0; m < M; ++m) {
-            const double amm = Gat(v, m, m) + v.l2;
+            const double amm = v.u[m];
             const double bm = v.beta[m];
             const double zz = v.g[m] + amm * bm;
             const double az = fabs(zz) - v.l1;
@@ -1727,12 +1732,14 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
             if (d != 0.0) {
                 dmax = fmax(dmax, fabs(d));
                 v.bytes += (double)M * sizeof(TG);
-                __syncthreads();
-                for (int k = threadIdx.x; k < M; k += kT) v.g[k] -= (double)v.G[(size_t)m * v.mpad + k] * d;
-                __syncthreads();
-                if (threadIdx.x == 0) {
-                    v.g[m] -= v.l2 * d;
-                    v.beta[m] = nb;
+                __syncthreads();   // every thread has read g_m and beta_m
+                for (int k = threadIdx.x; k < M; k += kT) {
+                    double gk = v.g[k] - (double)v.G[(size_t)m * v.mpad + k] * d;
+                    if (k == m) {
+                        gk -= v.l2 * d;
+                        v.beta[m] = nb;
+                    }
+                    v.g[k] = gk;
                 }
                 __syncthreads();
             }
