@@ -2041,32 +2041,51 @@ __device__ __forceinline__ void solve_one(const FitArgs &a, Sv<TG> &v, int s_id,
                 }
                 SUB(16);
                 // freeze the coordinates that reached zero (batched downdate)
+                // (every zero position not yet frozen, highest first; a full
+                // frozen set is applied and the positions are collected again)
                 for (;;) {
                     SUB_START();
-                    VI x; x.v = -1.0; x.i = -1;
-                    for (int p = threadIdx.x; p < v.s; p += kT) {
-                        if (v.th[v.S[p]] != 0) continue;
-                        bool fr = false;
-                        for (int q = 0; q < v.r; ++q) fr |= v.Rp[q] == p;
-                        if (fr) continue;
-                        VI c; c.v = (double)p; c.i = p;
-                        x = vmax(x, c);
+                    int nz = 0;
+                    {
+                        const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+                        for (int p0 = 0; p0 < v.s; p0 += kT) {
+                            const int p = p0 + threadIdx.x;
+                            bool on = p < v.s && v.th[v.S[p]] == 0;
+                            if (on)
+                                for (int q = 0; q < v.r; ++q) on &= v.Rp[q] != p;
+                            const unsigned long long bal = __ballot(on);
+                            const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+                            if (lane == 0) red.i[wid] = __popcll(bal);
+                            __syncthreads();
+                            int wbase = 0, tot = 0;
+                            for (int w = 0; w < kW; ++w) {
+                                if (w < wid) wbase += red.i[w];
+                                tot += red.i[w];
+                            }
+                            __syncthreads();
+                            if (on) v.rhs[nz + wbase + pre] = (double)p;   // rhs is free here
+                            nz += tot;
+                        }
+                        __syncthreads();
                     }
-                    x = bargmax(x, red);
                     SUB(17);
-                    if (x.i < 0) break;
-                    if (v.r == kFz) {
-                        compact(v, tile);
-                        continue;   // positions moved: search again
-                    }
-                    freeze(v, x.i, inc);
-                    n_inc += inc ? 1 : 0;
+                    bool moved = false;
+                    for (int e = nz - 1; e >= 0; --e) {
+                        if (v.r == kFz) {
+                            compact(v, tile);
+                            moved = true;   // positions moved: collect again
+                            break;
+                        }
+                        freeze(v, (int)v.rhs[e], inc);
+                        n_inc += inc ? 1 : 0;
 #ifdef PAM_INC_CHECK
-                    dbg_op = (dbg_op % 1000) * 10 + 2;
+                        dbg_op = (dbg_op % 1000) * 10 + 2;
 #endif
 #ifdef PAM_PHASE_PROFILE
-                    ++n_rm;
+                        ++n_rm;
 #endif
+                    }
+                    if (!moved) break;
                 }
                 PHASE_MARK(5);
 #ifdef PAM_PHASE_PROFILE
