@@ -26,7 +26,7 @@ treatment on the fitted field (continuous reconstruction across subdomain
 interfaces: its throughput and error beside the owner reconstruction's, and
 the interface jump it removes).
 
-Prints one JSON line. `--gpus N` with N > 1 is refused: this build runs on
+Prints one JSON line. `--gpus N` with N > 1 is refused: the hot path runs on
 one GPU.
 """
 from __future__ import annotations
@@ -798,8 +798,9 @@ def main():
         os.unlink(tpath)
         os.environ["PAM_TUNE_CACHE"] = tpath
     if args.gpus != 1:
-        print(f"bench.py: this build runs the hot path on one GPU; --gpus {args.gpus} is not "
-              "supported (see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the hot path runs on one GPU; --gpus {args.gpus} is not supported "
+              "(subdomain fits are independent and would be split across GPUs by subdomain, "
+              "with no communication until evaluation)", file=sys.stderr)
         sys.exit(2)
     progress("importing torch")
     import torch

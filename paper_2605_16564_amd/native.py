@@ -106,7 +106,7 @@ def lib():
     global _lib
     if _lib is None:
         if not LIB_PATH.exists():
-            raise PamError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+            raise PamError(f"{LIB_PATH} is not built; run python -m paper_2605_16564_amd.build first")
         L = C.CDLL(str(LIB_PATH))
         P = C.c_void_p
         L.pam_create.argtypes = [C.POINTER(P), C.c_int]
