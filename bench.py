@@ -357,6 +357,37 @@ def other_configs(ctx, api, synth, args, progress, skip=None):
     return out
 
 
+def plain_variants(prec):
+    """The unnormalized basis (the paper's Example 1 comparison) with the FP64
+    Gram, and with the workload's own Gram precision when that is lower: its
+    active blocks are far worse conditioned than the Shepard basis's, and a
+    subdomain whose FP64 pass does not converge from the low-precision start
+    reports it in its status (counted in the record)."""
+    v = [("plain_basis", dict(basis="plain", hinted=False, precision="f64"))]
+    if prec != "f64":
+        v.append((f"plain_basis_{prec}_gram", dict(basis="plain", hinted=False, precision=prec)))
+    return v
+
+
+def ablation(cs, step, kw, ref_value, ratio_key):
+    """One pattern switched: one untimed and one timed step; rate, field L1,
+    and every subdomain's final status and KKT residual."""
+    import torch
+    from paper_2605_16564_amd import api
+    step(**kw)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    ra = step(**kw)
+    torch.cuda.synchronize()
+    va = int(ra["rounds"].sum().item()) / (time.perf_counter() - ta)
+    l1a = float((cs["w_d"] * (ra["out"].double() - cs["ycell"]).abs()).sum().item()) / cs["area"]
+    st = api.stats_to_numpy(ra["stats"])
+    bad = int((st["status"] != 0).sum())
+    return {"value": va, "unit": "fits/s", ratio_key: ref_value / va, "field_l1_log10": l1a,
+            "precision": ra["prec"], "fit_status_ok": bad == 0, "subdomains_not_ok": bad,
+            "kkt_max": float(st["kkt"].max())}
+
+
 def facies_section(ctx, api, synth, args, progress, headline=None):
     """The 2-D facies256 workload (8 x 8 subdomains, three rounds, FP32 +
     FP64 pass) with the parts that exist in two dimensions only: the learned
@@ -381,21 +412,13 @@ def facies_section(ctx, api, synth, args, progress, headline=None):
                                    "centers_final_mean", "kernels", "roofline", "gram_roofline")}
         if not args.no_ablations:
             abl = {}
-            for vname, kw in (("no_learned", dict(hinted=False)), ("fp64", dict(precision="f64")),
-                              ("plain_basis", dict(basis="plain", hinted=False))):
-                if vname == "no_learned" and not use_learned:
-                    continue
-                cs["step"](**kw)
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                ra = cs["step"](**kw)
-                torch.cuda.synchronize()
-                va = int(ra["rounds"].sum().item()) / (time.perf_counter() - ta)
-                l1a = float((cs["w_d"] * (ra["out"].double() - cs["ycell"]).abs()).sum().item()) / cs["area"]
-                abl[vname] = {"value": va, "unit": "fits/s", "ratio_to_facies256": rec["value"] / va,
-                              "field_l1_log10": l1a}
+            variants = [("fp64", dict(precision="f64"))] + plain_variants(prec)
+            if use_learned:
+                variants.insert(0, ("no_learned", dict(hinted=False)))
+            for vname, kw in variants:
+                abl[vname] = ablation(cs, cs["step"], kw, rec["value"], "ratio_to_facies256")
+                progress(f"facies256 ablation {vname} done")
             out["ablations"] = abl
-            progress("facies256 ablations done")
     else:
         rec, res, cs, params, learned_rec = headline
         out = {}
@@ -889,18 +912,9 @@ def main():
         if use_learned:
             variants.insert(0, ("no_learned", dict(hinted=False)))
         if grid.dim == 2:
-            variants.append(("plain_basis", dict(basis="plain", hinted=False)))
+            variants += plain_variants(prec)
         for vname, kw in variants:
-            step(**kw)
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            ra = step(**kw)
-            torch.cuda.synchronize()
-            va = int(ra["rounds"].sum().item()) / (time.perf_counter() - ta)
-            l1a = float((cs["w_d"] * (ra["out"].double() - cs["ycell"]).abs()).sum().item()) / cs["area"]
-            abl[vname] = {"value": va, "unit": "fits/s", "ratio_to_headline": value / va,
-                          "field_l1_log10": l1a,
-                          "kkt_max": float(api.stats_to_numpy(ra["stats"])["kkt"].max())}
+            abl[vname] = ablation(cs, step, kw, value, "ratio_to_headline")
             progress(f"ablation {vname} done")
         rec["ablations"] = abl
     if not args.no_comparator:
