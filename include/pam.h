@@ -62,7 +62,13 @@ enum {
 
 /* Precision of the normalized design and of its Gram products. The
  * active-support solve, its residual refinement and the KKT certificate are
- * FP64 in every mode. */
+ * FP64 in every mode. The FP32 and BF16 modes start the FP64 refinement from
+ * the active set the low-precision Gram settles on; that start is close on
+ * the Shepard basis, but on far worse conditioned active blocks (the
+ * unnormalized basis, PAM_BASIS_PLAIN, on refined dictionaries) the FP64
+ * refinement can reach its iteration cap first. Such a subdomain reports
+ * PAM_ST_NOCONV with the coefficients it reached; fit it again with
+ * PAM_PREC_F64. */
 typedef enum {
     PAM_PREC_F64 = 0,   /* FP64 design, FP64 MFMA Gram                         */
     PAM_PREC_F32 = 1,   /* FP32 design, FP32 MFMA Gram, FP64 refinement        */
