@@ -388,6 +388,32 @@ def ablation(cs, step, kw, ref_value, ratio_key):
             "kkt_max": float(st["kkt"].max())}
 
 
+def plain_refit(ctx, cs, step, prec):
+    """The plain-basis refinement with the low-precision Gram, then
+    pam_refit_nonconverged: the subdomains it left not converged are fitted
+    again with the FP64 Gram on their final dictionaries (timed on its own,
+    after one untimed pass that sizes the FP64 workspace); field L1 and
+    statuses after it."""
+    import torch
+    from paper_2605_16564_amd import api
+    wl = cs["wl"]
+    o = api.EnetOpts(wl.lambda1, wl.lambda2, prec)
+    for timed in (False, True):
+        ra = step(basis="plain", hinted=False, precision=prec)
+        torch.cuda.synchronize()
+        before = int((api.stats_to_numpy(ra["stats"])["status"] != 0).sum())
+        t = time.perf_counter()
+        api.refit_nonconverged(ctx, ra["S"], ra["D"], o, ra["beta"], ra["stats"])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t)
+    out = api.evaluate(ctx, cs["grid"], ra["D"], ra["beta"], cs["xq"])
+    l1 = float((cs["w_d"] * (out.double() - cs["ycell"]).abs()).sum().item()) / cs["area"]
+    st = api.stats_to_numpy(ra["stats"])
+    bad = int((st["status"] != 0).sum())
+    return {"refit_subdomains": before, "refit_ms": ms, "field_l1_log10": l1,
+            "fit_status_ok": bad == 0, "subdomains_not_ok": bad, "kkt_max": float(st["kkt"].max())}
+
+
 def facies_section(ctx, api, synth, args, progress, headline=None):
     """The 2-D facies256 workload (8 x 8 subdomains, three rounds, FP32 +
     FP64 pass) with the parts that exist in two dimensions only: the learned
@@ -417,6 +443,8 @@ def facies_section(ctx, api, synth, args, progress, headline=None):
                 variants.insert(0, ("no_learned", dict(hinted=False)))
             for vname, kw in variants:
                 abl[vname] = ablation(cs, cs["step"], kw, rec["value"], "ratio_to_facies256")
+                if vname.startswith("plain_basis_"):
+                    abl[vname]["after_refit"] = plain_refit(ctx, cs, cs["step"], kw["precision"])
                 progress(f"facies256 ablation {vname} done")
             out["ablations"] = abl
     else:
@@ -915,6 +943,8 @@ def main():
             variants += plain_variants(prec)
         for vname, kw in variants:
             abl[vname] = ablation(cs, step, kw, value, "ratio_to_headline")
+            if vname.startswith("plain_basis_"):
+                abl[vname]["after_refit"] = plain_refit(ctx, cs, step, kw["precision"])
             progress(f"ablation {vname} done")
         rec["ablations"] = abl
     if not args.no_comparator:

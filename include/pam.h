@@ -67,8 +67,8 @@ enum {
  * the Shepard basis, but on far worse conditioned active blocks (the
  * unnormalized basis, PAM_BASIS_PLAIN, on refined dictionaries) the FP64
  * refinement can reach its iteration cap first. Such a subdomain reports
- * PAM_ST_NOCONV with the coefficients it reached; fit it again with
- * PAM_PREC_F64. */
+ * PAM_ST_NOCONV with the coefficients it reached; pam_refit_nonconverged fits
+ * exactly those subdomains again with the FP64 Gram. */
 typedef enum {
     PAM_PREC_F64 = 0,   /* FP64 design, FP64 MFMA Gram                         */
     PAM_PREC_F32 = 1,   /* FP32 design, FP32 MFMA Gram, FP64 refinement        */
@@ -257,6 +257,20 @@ typedef struct {
  * stats: [n_sub] or NULL. */
 pam_status pam_fit_subdomains(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,
                               const pam_enet_opts *opts, double *beta, pam_fit_stats *stats);
+
+/* a3-a6 again, with the FP64 Gram (PAM_PREC_F64) and from a cold start, for
+ * exactly the subdomains whose stats entry reads PAM_ST_NOCONV: the recovery
+ * for fits of the FP32/BF16 modes whose FP64 refinement reached its iteration
+ * cap (the same minimizer, Eq. elastic, Sec. 3.3). samples, dict and beta as
+ * in pam_fit_subdomains; stats [n_sub] (device, required) holds the previous
+ * fit's entries on input. The refitted subdomains get new coefficients and
+ * stats entries; every other subdomain's beta and stats stay as they were.
+ * opts gives lambdas, cd_sweeps, max_iter, batched and the team settings; its
+ * precision, warm_start and support_hint are ignored. Stream-ordered after
+ * the fit that wrote stats; no host synchronization. Errors as
+ * pam_fit_subdomains (the FP64 capacity limit applies to m_cap). */
+pam_status pam_refit_nonconverged(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,
+                                  const pam_enet_opts *opts, double *beta, pam_fit_stats *stats);
 
 /* Refinement controls (Alg. 1 inputs K_top, M_max, eps_tol; Sec. 3.4 eta). */
 typedef struct {

@@ -280,6 +280,17 @@ def fit(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts,
     return beta, stats
 
 
+def refit_nonconverged(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, beta: torch.Tensor,
+                       stats: torch.Tensor):
+    """a3-a6 with the FP64 Gram, cold, for the subdomains whose stats read
+    not converged (the previous fit's beta and stats, updated in place)."""
+    ss, ds, os_ = S.struct(), D.struct(), opts.struct(False)
+    ctx.use_current_stream()
+    N.check(N.lib().pam_refit_nonconverged(ctx.h, C.byref(ss), C.byref(ds), C.byref(os_), _p(beta),
+                                           _p(stats)), "pam_refit_nonconverged")
+    return beta, stats
+
+
 def select_lambda(ctx: Context, S: Samples, D: Dictionary, opts: EnetOpts, n_alpha: int = 8,
                   k_folds: int = 5, alpha_min_ratio: float = 1e-3, l1_ratio: float = 0.99):
     """Per-subdomain elastic-net parameters by an alpha path and K-fold

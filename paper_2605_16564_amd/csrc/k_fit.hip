@@ -65,6 +65,21 @@ pam_status launch_check_finite(pam_ctx *ctx, const FitArgs &a, const double *h) 
     return PAM_OK;
 }
 
+// Mask of the subdomains a refit serves: those whose last fit reported
+// PAM_ST_NOCONV (stats of that fit, one entry per subdomain).
+__global__ void __launch_bounds__(256)
+k_noconv_mask(const pam_fit_stats *__restrict__ stats, int n, int32_t *__restrict__ mask) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s < n) mask[s] = stats[s].status == PAM_ST_NOCONV ? 1 : 0;
+}
+
+pam_status launch_noconv_mask(pam_ctx *ctx, const pam_fit_stats *stats, int n, int32_t *mask) {
+    if (n <= 0) return PAM_OK;
+    hipLaunchKernelGGL(k_noconv_mask, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, stats, n, mask);
+    PAM_CHECK_HIP(hipGetLastError());
+    return PAM_OK;
+}
+
 // One Gaussian of the low-precision modes: 2^(-(float)(r2 * sa)) with r2 the
 // squared distance in FP64 and sa = log2(e) / (2 sigma^2). Contraction is off
 // and the operations are written out once here, so that the assembly and the

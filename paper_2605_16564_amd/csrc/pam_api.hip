@@ -92,6 +92,9 @@ KernelTimer::~KernelTimer() {
     ctx_->timing.pending.push_back({kind_, {start_, stop}});
 }
 
+// refit mask (k_fit.hip)
+pam_status launch_noconv_mask(pam_ctx *ctx, const pam_fit_stats *stats, int n, int32_t *mask);
+
 // setup kernels (k_setup.hip)
 pam_status launch_gather(pam_ctx *ctx, const pam_grid *g, const void *tab_dev, int n_sub,
                          int32_t n_max, const double *cell_y, const int64_t *off, double *x,
@@ -716,6 +719,24 @@ pam_status pam_fit_subdomains(pam_ctx *ctx, const pam_samples *samples, const pa
     graph_key_common(k, ctx, plan, opts);
     k.v(opts->warm_start);
     return graph_run(ctx, k.h, [&]() { return fit_enqueue(ctx, plan, nullptr, opts->warm_start, nullptr); });
+}
+
+pam_status pam_refit_nonconverged(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,
+                                  const pam_enet_opts *opts, double *beta, pam_fit_stats *stats) {
+    pam_status st = check_ctx(ctx);
+    if (st != PAM_OK) return st;
+    PAM_REQUIRE(opts, "NULL argument");
+    PAM_REQUIRE(stats, "stats is NULL: the refit reads the statuses of the previous fit");
+    pam_enet_opts o = *opts;
+    o.precision = PAM_PREC_F64;
+    o.warm_start = 0;
+    o.support_hint = nullptr;
+    if ((st = check_fit_args(samples, dict, &o, beta)) != PAM_OK) return st;
+    const int n = samples->n_sub;
+    if ((st = ensure(ctx, BUF_TABLE, (size_t)n * 4)) != PAM_OK) return st;
+    int32_t *mask = wsp<int32_t>(ctx, BUF_TABLE);
+    if ((st = launch_noconv_mask(ctx, stats, n, mask)) != PAM_OK) return st;
+    return run_fit(ctx, samples, dict, &o, beta, stats, mask, 0);
 }
 
 pam_status pam_refine(pam_ctx *ctx, const pam_samples *samples, pam_dict *dict, double *beta,

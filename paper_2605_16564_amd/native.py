@@ -19,7 +19,7 @@ ERR_NONFINITE = -3
 
 EXPORTS = [
     "pam_create", "pam_destroy", "pam_set_stream", "pam_sync", "pam_last_error", "pam_version",
-    "pam_partition_count", "pam_partition_gather", "pam_init_lattice", "pam_fit_subdomains",
+    "pam_partition_count", "pam_partition_gather", "pam_init_lattice", "pam_fit_subdomains", "pam_refit_nonconverged",
     "pam_refine", "pam_eval", "pam_timing_enable", "pam_timing_read",
     "pam_cnn_param_count", "pam_cnn_forward", "pam_cnn_loss_grad", "pam_cnn_adam",
     "pam_grid_patches", "pam_support_hint", "pam_cnn_labels",
@@ -122,6 +122,8 @@ def lib():
         L.pam_init_lattice.argtypes = [P, C.POINTER(PamGrid), P, C.c_double, C.POINTER(PamDict)]
         L.pam_fit_subdomains.argtypes = [P, C.POINTER(PamSamples), C.POINTER(PamDict),
                                          C.POINTER(PamEnetOpts), P, P]
+        L.pam_refit_nonconverged.argtypes = [P, C.POINTER(PamSamples), C.POINTER(PamDict),
+                                             C.POINTER(PamEnetOpts), P, P]
         L.pam_refine.argtypes = [P, C.POINTER(PamSamples), C.POINTER(PamDict), P,
                                  C.POINTER(PamEnetOpts), C.POINTER(PamRefineOpts), P]
         L.pam_eval.argtypes = [P, C.c_int32, C.POINTER(PamField), C.POINTER(PamDict), P, C.c_int32,
