@@ -267,8 +267,9 @@ pam_status pam_fit_subdomains(pam_ctx *ctx, const pam_samples *samples, const pa
  * stats entries; every other subdomain's beta and stats stay as they were.
  * opts gives lambdas, cd_sweeps, max_iter, batched and the team settings; its
  * precision, warm_start and support_hint are ignored. Stream-ordered after
- * the fit that wrote stats; no host synchronization. Errors as
- * pam_fit_subdomains (the FP64 capacity limit applies to m_cap). */
+ * the fit that wrote stats (the mask is read on the device); the host waits
+ * only when the FP64 workspace has to grow. Errors as pam_fit_subdomains
+ * (the FP64 capacity limit applies to m_cap). */
 pam_status pam_refit_nonconverged(pam_ctx *ctx, const pam_samples *samples, const pam_dict *dict,
                                   const pam_enet_opts *opts, double *beta, pam_fit_stats *stats);
 
