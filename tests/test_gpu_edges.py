@@ -1,5 +1,6 @@
 """Edge cases of the fit through the C ABI: more centers than samples (the
-elastic net stays strictly convex through lambda2), subdomains without
+elastic net stays strictly convex through lambda2), duplicated centers (an
+exactly singular Gram; equal coefficients for the copies), subdomains without
 centers, dictionaries beyond what the solve's vectors hold in LDS, subdomains
 beyond what the marking ranks in LDS, the capacity error, non-finite
 input."""
@@ -56,6 +57,45 @@ def test_more_centers_than_samples(ctx, prec):
               for s in range(4))
     print(prec, "M > N coefficient error", err, "support", stn["support"])
     assert err <= (1e-9 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-9), ("f32", 1e-5)])
+def test_duplicated_centers(ctx, prec, tol):
+    """Three centers of a 6x6 lattice appended a second time (same position
+    and width): the Gram is exactly singular and the elastic net is still
+    strictly convex through lambda2, so the minimizer is unique and, by the
+    symmetry of the two identical columns, gives each copy the same
+    coefficient; against the oracle on the same dictionary."""
+    g = synth.facies256(seed=2006, n=64, n_sub=4)
+    S = api.partition(ctx, g)
+    od = O.init_dictionary(g, [6, 6], 40)
+    dup = (0, 7, 20)
+    for s in range(od.n_sub):
+        for i, k in enumerate(dup):
+            j = 36 + i
+            od.c[(s * 40 + j) * 2:(s * 40 + j + 1) * 2] = od.c[(s * 40 + k) * 2:(s * 40 + k + 1) * 2]
+            od.sigma[s * 40 + j] = od.sigma[s * 40 + k]
+            od.level[s * 40 + j] = od.level[s * 40 + k]
+        od.m[s] = 39
+    D = _dict_from(od)
+    print("case duplicated centers, 16 subdomains, M 39 with 3 copies,", prec, flush=True)
+    beta, st = api.fit(ctx, S, D, api.EnetOpts(L1, L2, prec))
+    torch.cuda.synchronize()
+    stn = api.stats_to_numpy(st)
+    assert np.all(stn["status"] == 0) and stn["kkt"].max() < 1e-9, stn["kkt"]
+    bo, sto, _ = O.fit_batch(O.partition(g), od, L1, L2)
+    b = _t(beta)
+    err, asym = 0.0, 0.0
+    for s in range(od.n_sub):
+        ref = bo[s * 40:s * 40 + 39]
+        scale = np.abs(ref).max()
+        err = max(err, np.abs(b[s, :39] - ref).max() / scale)
+        for i, k in enumerate(dup):
+            assert ref[36 + i] == pytest.approx(ref[k], rel=1e-9, abs=1e-12 * scale)
+            asym = max(asym, abs(b[s, 36 + i] - b[s, k]) / scale)
+    print(prec, "duplicated centers: coefficient error", err, "copy asymmetry", asym)
+    assert err <= tol
+    assert asym <= tol
 
 
 def test_subdomains_without_centers(ctx):

@@ -144,3 +144,21 @@ def test_plain_basis_fit_certified(field):
     b, st, _ = O.fit_one(x, y, c, sig, L1, L2, basis="plain")
     assert st == 0
     _certify(W, y, b)
+
+
+def test_duplicated_centers_share_the_coefficient(field):
+    """Two identical columns make the Gram exactly singular; lambda2 > 0
+    keeps the objective strictly convex, so the minimizer is unique and
+    symmetric in the two copies: each gets the same coefficient (the
+    elastic net's grouping of equal columns), and the gap certifies it."""
+    x, y = _patch(field, 32, 64)
+    c, sig = _lattice(32, 64, 8)
+    dup = [0, 9, 30, 63]
+    c2, s2 = np.vstack([c, c[dup]]), np.concatenate([sig, sig[dup]])
+    W = _design(x, c2, s2, plain=False)
+    b, st, _ = O.fit_one(x, y, c2, s2, L1, L2)
+    assert st == 0
+    _certify(W, y, b)
+    scale = np.abs(b).max()
+    for i, k in enumerate(dup):
+        assert abs(b[64 + i] - b[k]) <= 1e-9 * scale, (k, b[64 + i], b[k])
