@@ -265,6 +265,24 @@ def test_c3_layered3d_all_rounds_certified(ctx):
     # by ~1e-8 (lambda1 = 4.6e-4), so the gap is ~1e-8 ||r||^2 at most; a 1e-3
     # change of one coefficient gives gaps of ~1e-2 ||y||^2
     assert worst_gap <= 1e-8
+    # a10 on the same field: the metric points of every cell (2 x 2 x 2 Gauss
+    # points, FP32 queries, one launch as the benchmark runs it), sampled
+    # queries against the oracle's evaluation of the GPU's dictionary and
+    # coefficients
+    pts, _, _ = synth.metric_points(g, 2)
+    xq = torch.as_tensor(pts, dtype=torch.float32, device="cuda")
+    out = _t(api.evaluate(ctx, g, D, beta, xq))
+    torch.cuda.synchronize()
+    od = O.Dictionary(D.n_sub, m_cap, 3)
+    od.m[:] = m
+    od.c[:] = c.ravel()
+    od.sigma[:] = sg.ravel()
+    od.level[:] = _t(D.level).ravel()
+    pick = np.random.default_rng(31).choice(len(pts), 4000, replace=False)
+    ref, nout = O.evaluate(O.grid_axis_coords(g), od, b.ravel(), _t(xq)[pick].astype(np.float64))
+    err = np.abs(out[pick] - ref).max() / max(1.0, np.abs(ref).max())
+    print("C3 evaluation:", len(pts), "queries, sampled", len(pick), "error", err)
+    assert nout == 0 and err <= 2e-4
 
 
 def test_c5_multifield_fit_and_transfer(ctx):
