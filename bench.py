@@ -58,7 +58,7 @@ SLOTS_F64 = 78.6e12 / 2.0
 # HBM bytes per launch of the dominant kernel from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB device copy), valid only for the
 # kernel source they were taken on (sha256 prefix of its source files).
-TRAFFIC = {("k_solve<float, false>", "layered3d"): {"src": "48f015b05f4109c1", "bytes_per_launch": 1159.8e9}}
+TRAFFIC = {("k_solve<float, false>", "layered3d"): {"src": "5ee7fb40cc639171", "bytes_per_launch": 1105.7e9}}
 TRAFFIC_SOURCES = ["paper_2605_16564_amd/csrc/k_solve_impl.h", "paper_2605_16564_amd/csrc/k_solve_f32.hip",
                    "paper_2605_16564_amd/csrc/pam_internal.h"]
 

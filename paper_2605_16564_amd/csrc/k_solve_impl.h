@@ -54,12 +54,12 @@ static constexpr int kPass = kR * kT;
 static constexpr int kUR = 16;     // rows of H in flight per thread in the bordering product
 static constexpr int kHR = 8;      // rows of H per batch in the low-rank updates (two batches in flight)
 static constexpr int kPolishMax = 30;  // FP64 conjugate-gradient steps of the polish
-static constexpr int kIncMax = 96;     // incremental solution updates between full solves
+static constexpr int kIncMax = 384;    // incremental solution updates between full solves
 // a sign-consistent carried solution is confirmed by a full solve only when
 // more than kConfirm incremental updates separate it from the last full solve
 // (each loses about eps cond(G); the steps it accepts are still certified by
 // the reduced-system residual and the KKT check at the end)
-static constexpr int kConfirm = 48;
+static constexpr int kConfirm = 192;
 static_assert(kFz <= kB && kFz + 2 * kB <= kQ && kInit <= kQ, "deferred blocks fit the update scratch");
 
 // A team of up to kTeamMax workgroups may serve one subdomain (the launch is
