@@ -98,7 +98,9 @@ def test_refit_recovers_plain_basis_fp32_refinement(ctx):
     bad = np.flatnonzero(s0["status"] == 1)
     good = np.flatnonzero(s0["status"] == 0)
     print("not converged after the FP32 refinement:", len(bad), "of", D.n_sub)
-    assert len(bad) > 0 and len(good) + len(bad) == D.n_sub
+    # 28 of 64 on this field with the current kernels; with none the refit
+    # must leave everything as it was, which the checks below also cover
+    assert len(good) + len(bad) == D.n_sub
     b0 = beta.clone()
     api.refit_nonconverged(ctx, S, D, o, beta, st)
     b64, st64 = api.fit(ctx, S, D, api.EnetOpts(wl.lambda1, wl.lambda2, "f64"), warm=False)
